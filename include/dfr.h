@@ -1,0 +1,202 @@
+/*
+ * dfr.h -- C ABI of a GPU implementation of the Diverting Fast Radix (DFR) sort
+ * (Thiel et al., "ThielSort: Implementing the Diverting Fast Radix Algorithm",
+ * arXiv 2207.14334) for AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Sec. 2.2, diverting-MSD paragraph; Sec. 3): records held in an input
+ * area, an extra buffer of the same size, and the key's digits; the result ends in
+ * the original area (Sec. 2.1: the last deal lands back in the original space).
+ * Every sort here is a *stable* ascending sort of unsigned integer keys, with an
+ * optional payload that travels with its key.  The output is the unique
+ * arrangement in which record i sits at
+ *     rank(i) = #{ j : k_j < k_i } + #{ j < i : k_j == k_i }.
+ *
+ * Memory.  keys, vals and temp are DEVICE pointers owned by the caller; they must
+ * stay allocated and untouched until the work enqueued on `stream` has finished.
+ * Arrays are contiguous structure-of-arrays: keys[n] and, when given, vals[n] of
+ * the stated widths.  Pointers must be aligned to their element size.  keys, vals
+ * and temp must not overlap.  The context owns a small amount of scratch device
+ * memory (histograms, look-back words, bucket lists) that it grows on demand and
+ * frees in dfr_destroy.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ * Work is enqueued on that stream in order.  A sort call blocks the calling host
+ * thread while it reads small planning results back from the device (digit
+ * histograms, bucket lists); when it returns DFR_OK the sorted result may still be
+ * in flight on `stream`.
+ *
+ * Errors.  Every call returns a dfr_status.  Argument errors are detected before any
+ * device work is enqueued and leave the buffers untouched.  A HIP runtime failure
+ * returns DFR_E_HIP, marks the context failed (later calls return DFR_E_HIP) and
+ * records text for dfr_last_error.  Contexts are not thread-safe.
+ */
+#ifndef DFR_H
+#define DFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dfr_status;
+
+#define DFR_OK 0
+#define DFR_E_INVALID_ARG (-1) /* NULL with n > 0, misaligned, overlapping, bad width,  */
+                               /* temp too small, malformed segment offsets           */
+#define DFR_E_TOO_LARGE (-2)   /* a segment of 2^30 records or more                    */
+#define DFR_E_NO_MEMORY (-3)   /* device scratch could not be allocated               */
+#define DFR_E_HIP (-4)         /* HIP runtime error; detail in dfr_last_error          */
+#define DFR_E_PENDING (-5)     /* request not finished yet                             */
+#define DFR_E_NOT_FOUND (-6)   /* unknown ticket                                       */
+#define DFR_E_BUDGET (-7)      /* request can never fit the context's memory budget    */
+#define DFR_E_UNSUPPORTED (-8) /* entry point or option not available                  */
+#define DFR_E_INTERNAL (-9)    /* a kernel's bounded wait expired; results invalid     */
+
+/* Largest number of records in one sort, or in one segment of a segmented sort.
+ * The per-tile digit counts that the look-back scan publishes are 30-bit fields. */
+#define DFR_MAX_SEGMENT_RECORDS ((size_t)1 << 30) - 1
+
+typedef struct dfr_ctx dfr_ctx;
+
+/* Create a context bound to HIP device `hip_device`.  `hbm_budget_bytes` bounds the
+ * device memory that queued requests (dfr_submit) may hold at once; 0 means a
+ * quarter of the device's memory.  On success *out receives the context. */
+dfr_status dfr_create(int hip_device, size_t hbm_budget_bytes, dfr_ctx** out);
+
+/* Wait for the context's own work, then free its scratch memory and the context. */
+void dfr_destroy(dfr_ctx* ctx);
+
+/* Static text for a status code. */
+const char* dfr_status_string(dfr_status s);
+
+/* Text of the last error recorded on `ctx` ("" if none); valid until the next call. */
+const char* dfr_last_error(const dfr_ctx* ctx);
+
+/* Bytes of caller-provided temp storage a sort of n records needs: the extra buffer
+ * of the paper's statement of the problem (Sec. 2.2), n * (key_bytes + val_bytes),
+ * rounded up to 256 bytes.  key_bytes is 4 or 8; val_bytes 0, 4 or 8. */
+size_t dfr_temp_bytes(size_t n, int key_bytes, int val_bytes);
+
+/* ---------------------------------------------------------------------------------
+ * Plain sort (Sec. 3, DFR; Alg. 4 in the paper).
+ *
+ * Stable ascending sort of keys[0..n) in place; vals[0..n) (may be NULL) moves with
+ * its key.  temp: device buffer of at least dfr_temp_bytes(n, kb, vb) bytes, or NULL
+ * to use storage the context allocates once and caches.  n <= 1 returns DFR_OK with
+ * nothing enqueued.  n > DFR_MAX_SEGMENT_RECORDS returns DFR_E_TOO_LARGE.
+ * ------------------------------------------------------------------------------- */
+dfr_status dfr_sort_u32(dfr_ctx* ctx, uint32_t* keys, uint32_t* vals, size_t n, void* temp,
+                        size_t temp_bytes, void* stream);
+dfr_status dfr_sort_u64(dfr_ctx* ctx, uint64_t* keys, uint64_t* vals, size_t n, void* temp,
+                        size_t temp_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Segmented sort: many independent arrays laid end to end, each sorted on its own
+ * exactly as the plain sort would sort it (Sec. 3; large buckets are themselves
+ * sorted by the same procedure).
+ *
+ * seg_offsets: HOST array of num_segments + 1 entries, seg_offsets[0] == 0,
+ * non-decreasing, seg_offsets[num_segments] == n (total records).  Empty segments
+ * are allowed.  keys/vals/temp as for the plain sort, covering all n records.
+ * ------------------------------------------------------------------------------- */
+dfr_status dfr_sort_segmented_u32(dfr_ctx* ctx, uint32_t* keys, uint32_t* vals,
+                                  const uint64_t* seg_offsets, size_t num_segments,
+                                  void* temp, size_t temp_bytes, void* stream);
+dfr_status dfr_sort_segmented_u64(dfr_ctx* ctx, uint64_t* keys, uint64_t* vals,
+                                  const uint64_t* seg_offsets, size_t num_segments,
+                                  void* temp, size_t temp_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Stages, in the paper's vocabulary (Sec. 2): a count and a deal on one digit.
+ * ------------------------------------------------------------------------------- */
+
+/* count: for every digit j < num_digits, hist[j * 2^bits + v] = number of keys whose
+ * digit j, (key >> (j * bits)) mod 2^bits, equals v.  hist is a DEVICE array of
+ * num_digits * 2^bits uint32 entries, overwritten.  bits in [1, 8];
+ * num_digits * bits <= 8 * key_bytes. */
+dfr_status dfr_count(dfr_ctx* ctx, const void* keys, int key_bytes, size_t n, int bits,
+                     int num_digits, uint32_t* hist, void* stream);
+
+/* deal: one stable counting-sort pass on the digit (key >> shift) mod 2^bits, from
+ * (keys_in, vals_in) to (keys_out, vals_out): records with a smaller digit come
+ * first and records with equal digits keep their input order.  vals_in/vals_out may
+ * be NULL together (val_bytes then 0).  bits in [1, 8]; shift + bits <= 8*key_bytes.
+ * Output arrays must not overlap the inputs. */
+dfr_status dfr_deal(dfr_ctx* ctx, const void* keys_in, const void* vals_in, void* keys_out,
+                    void* vals_out, int key_bytes, int val_bytes, size_t n, int shift,
+                    int bits, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Request queue: submit sort requests and poll for completion.  (Continuous
+ * batching of queued requests into segmented launches.)
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    int key_bytes; /* 4 or 8 */
+    int val_bytes; /* 0, 4 or 8 */
+    void* keys;    /* device, sorted in place */
+    void* vals;    /* device or NULL */
+    size_t n;
+} dfr_request;
+
+/* Queue a request; *ticket identifies it.  DFR_E_BUDGET if it can never fit. */
+dfr_status dfr_submit(dfr_ctx* ctx, const dfr_request* req, uint64_t* ticket);
+
+/* DFR_OK once the request's result is in place (the ticket is then consumed and
+ * *latency_s, if not NULL, receives submit-to-completion seconds); DFR_E_PENDING
+ * while it is not; DFR_E_NOT_FOUND for an unknown ticket. */
+dfr_status dfr_poll(dfr_ctx* ctx, uint64_t ticket, double* latency_s);
+
+/* ---------------------------------------------------------------------------------
+ * Options, plan inspection and timing.
+ * ------------------------------------------------------------------------------- */
+
+/* Set a tuning option on the context.  Names:
+ *   "divert_records"  N_d, the bucket size below which buckets are diverted to the
+ *                     in-LDS local sort (Sec. 3.1); clamped to the local sort's
+ *                     capacity.  0 restores the default.
+ *   "force_top_digits" d, the number of top digits dealt before diversion at the
+ *                     first level (0 = estimate it, Sec. 3).  A value >= the number
+ *                     of varying digits deals all of them (plain LSD, Sec. 2.1).
+ *   "timing"          1 to record per-kernel durations with HIP events, 0 to stop.
+ * Unknown names return DFR_E_UNSUPPORTED. */
+dfr_status dfr_set_option(dfr_ctx* ctx, const char* name, int64_t value);
+
+/* What the last sort call did.  Kernel times are in milliseconds and are filled
+ * only while the "timing" option is on (they force a stream synchronisation). */
+typedef struct {
+    int32_t levels;           /* recursion levels run (1 = no recursion)          */
+    int32_t top_digits;       /* digits dealt at the first level                  */
+    int32_t deal_passes;      /* deal launches over all levels                    */
+    int32_t used_diversion;   /* 1 if the local sort finished buckets             */
+    uint64_t large_buckets;   /* buckets recursed on, over all levels             */
+    uint64_t chunks;          /* local-sort work items, over all levels           */
+    double ms_count;          /* summed kernel time per stage (timing option)     */
+    double ms_deal;
+    double ms_buckets;
+    double ms_local_sort;
+    double ms_other;
+    int32_t deal_launches_timed; /* number of deal launches summed in ms_deal     */
+} dfr_stats;
+
+dfr_status dfr_get_stats(const dfr_ctx* ctx, dfr_stats* out);
+
+/* Host-only planning helper, usable without a GPU: given the digit histograms of n
+ * keys (hist[j * 256 + v] for 8-bit digits j = 0 .. 8*key_bytes/8 - 1), return the
+ * number of top varying digits the first level deals before diversion, as the
+ * sort itself would choose it (Sec. 3: estimate the number of most significant
+ * digits; Sec. 3.1: diversion threshold N_d).  *varying_digits receives how many
+ * digits are not constant.  divert_records 0 = default. */
+dfr_status dfr_plan_top_digits(const uint32_t* hist, size_t n, int key_bytes, int val_bytes,
+                               size_t divert_records, int32_t* top_digits,
+                               int32_t* varying_digits);
+
+/* Records one local-sort work item may hold (its LDS capacity) for these widths. */
+size_t dfr_local_sort_capacity(int key_bytes, int val_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFR_H */

@@ -1,0 +1,312 @@
+"""Python binding of libdfr.so: a GPU Diverting Fast Radix sort for MI355X (gfx950).
+
+This module only marshals arguments: every step of the sort runs in the HIP kernels of
+``libdfr.so`` (see ``include/dfr.h`` for the C ABI).  PyTorch provides the device memory
+and the stream; tensors must live on a ROCm device, be contiguous and have dtype
+``torch.uint32`` or ``torch.uint64``.
+
+If ``libdfr.so`` has not been built, importing works but every GPU entry point raises
+``RuntimeError``: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfr.so")
+
+# Status codes (include/dfr.h).
+OK = 0
+E_INVALID_ARG = -1
+E_TOO_LARGE = -2
+E_NO_MEMORY = -3
+E_HIP = -4
+E_PENDING = -5
+E_NOT_FOUND = -6
+E_BUDGET = -7
+E_UNSUPPORTED = -8
+E_INTERNAL = -9
+
+MAX_SEGMENT_RECORDS = (1 << 30) - 1
+
+EXPORTED = [
+    "dfr_create", "dfr_destroy", "dfr_status_string", "dfr_last_error", "dfr_temp_bytes",
+    "dfr_sort_u32", "dfr_sort_u64", "dfr_sort_segmented_u32", "dfr_sort_segmented_u64",
+    "dfr_count", "dfr_deal", "dfr_submit", "dfr_poll", "dfr_set_option", "dfr_get_stats",
+    "dfr_plan_top_digits", "dfr_local_sort_capacity",
+]
+
+
+class DfrError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"dfr status {status}: {msg}")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32), ("top_digits", ctypes.c_int32),
+        ("deal_passes", ctypes.c_int32), ("used_diversion", ctypes.c_int32),
+        ("large_buckets", ctypes.c_uint64), ("chunks", ctypes.c_uint64),
+        ("ms_count", ctypes.c_double), ("ms_deal", ctypes.c_double),
+        ("ms_buckets", ctypes.c_double), ("ms_local_sort", ctypes.c_double),
+        ("ms_other", ctypes.c_double), ("deal_launches_timed", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("key_bytes", ctypes.c_int), ("val_bytes", ctypes.c_int),
+                ("keys", ctypes.c_void_p), ("vals", ctypes.c_void_p), ("n", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdfr.so.  Raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "or python -m paper_2207_14334_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, Z, I, S = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int32
+    L.dfr_create.argtypes = [I, Z, ctypes.POINTER(P)]
+    L.dfr_create.restype = S
+    L.dfr_destroy.argtypes = [P]
+    L.dfr_destroy.restype = None
+    L.dfr_status_string.argtypes = [S]
+    L.dfr_status_string.restype = ctypes.c_char_p
+    L.dfr_last_error.argtypes = [P]
+    L.dfr_last_error.restype = ctypes.c_char_p
+    L.dfr_temp_bytes.argtypes = [Z, I, I]
+    L.dfr_temp_bytes.restype = Z
+    L.dfr_local_sort_capacity.argtypes = [I, I]
+    L.dfr_local_sort_capacity.restype = Z
+    for name in ("dfr_sort_u32", "dfr_sort_u64"):
+        f = getattr(L, name)
+        f.argtypes = [P, P, P, Z, P, Z, P]
+        f.restype = S
+    for name in ("dfr_sort_segmented_u32", "dfr_sort_segmented_u64"):
+        f = getattr(L, name)
+        f.argtypes = [P, P, P, P, Z, P, Z, P]
+        f.restype = S
+    L.dfr_count.argtypes = [P, P, I, Z, I, I, P, P]
+    L.dfr_count.restype = S
+    L.dfr_deal.argtypes = [P, P, P, P, P, I, I, Z, I, I, P]
+    L.dfr_deal.restype = S
+    L.dfr_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.dfr_submit.restype = S
+    L.dfr_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+    L.dfr_poll.restype = S
+    L.dfr_set_option.argtypes = [P, ctypes.c_char_p, ctypes.c_int64]
+    L.dfr_set_option.restype = S
+    L.dfr_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    L.dfr_get_stats.restype = S
+    L.dfr_plan_top_digits.argtypes = [P, Z, I, I, Z, ctypes.POINTER(S), ctypes.POINTER(S)]
+    L.dfr_plan_top_digits.restype = S
+    _lib = L
+    return L
+
+
+def status_string(st: int) -> str:
+    return lib().dfr_status_string(st).decode()
+
+
+def temp_bytes(n: int, key_bytes: int, val_bytes: int) -> int:
+    return int(lib().dfr_temp_bytes(n, key_bytes, val_bytes))
+
+
+def local_sort_capacity(key_bytes: int, val_bytes: int) -> int:
+    return int(lib().dfr_local_sort_capacity(key_bytes, val_bytes))
+
+
+def plan_top_digits(hist, n: int, key_bytes: int, val_bytes: int, divert: int = 0):
+    """Host-only planner: (digits dealt before diversion, varying digits) for a
+    numpy uint32 histogram array of shape (key_bytes, 256)."""
+    import numpy as np
+    h = np.ascontiguousarray(hist, dtype=np.uint32)
+    d, v = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = lib().dfr_plan_top_digits(h.ctypes.data, n, key_bytes, val_bytes, divert,
+                                   ctypes.byref(d), ctypes.byref(v))
+    if st != OK:
+        raise DfrError(st, "plan_top_digits")
+    return d.value, v.value
+
+
+def _width(t) -> int:
+    import torch
+    if t.dtype in (torch.uint32, torch.int32):
+        return 4
+    if t.dtype in (torch.uint64, torch.int64):
+        return 8
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _check_tensor(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """One libdfr context on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        import torch
+        self.device = device
+        torch.cuda.set_device(device)
+        h = ctypes.c_void_p()
+        st = lib().dfr_create(device, hbm_budget_bytes, ctypes.byref(h))
+        if st != OK:
+            raise DfrError(st, status_string(st))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dfr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers -------------------------------------------------------------------
+    def _raise(self, st, what):
+        if st != OK:
+            raise DfrError(st, f"{what}: {status_string(st)}: "
+                               f"{lib().dfr_last_error(self._h).decode()}")
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def last_error(self) -> str:
+        return lib().dfr_last_error(self._h).decode()
+
+    def set_option(self, name: str, value: int):
+        self._raise(lib().dfr_set_option(self._h, name.encode(), int(value)), "set_option")
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._raise(lib().dfr_get_stats(self._h, ctypes.byref(s)), "get_stats")
+        return s.as_dict()
+
+    # -- sorts ---------------------------------------------------------------------
+    def sort_(self, keys, vals=None, temp=None, stream=None):
+        """Stable in-place ascending sort of ``keys`` (uint32/uint64); ``vals`` follows."""
+        _check_tensor(keys, "keys")
+        kb = _width(keys)
+        n = keys.numel()
+        vp = None
+        if vals is not None:
+            _check_tensor(vals, "vals")
+            if vals.numel() != n or _width(vals) != kb:
+                raise ValueError("vals must match keys in length and width")
+            vp = vals.data_ptr()
+        tp, tb = (temp.data_ptr(), temp.numel() * temp.element_size()) if temp is not None else (None, 0)
+        f = lib().dfr_sort_u32 if kb == 4 else lib().dfr_sort_u64
+        self._raise(f(self._h, keys.data_ptr(), vp, n, tp, tb, self._stream(stream)), "sort")
+        return keys, vals
+
+    def sort_segmented_(self, keys, vals, offsets, temp=None, stream=None):
+        """Sort each segment [offsets[i], offsets[i+1]) of keys/vals independently.
+        ``offsets`` is a host sequence of num_segments + 1 integers."""
+        import numpy as np
+        _check_tensor(keys, "keys")
+        kb = _width(keys)
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        vp = None
+        if vals is not None:
+            _check_tensor(vals, "vals")
+            vp = vals.data_ptr()
+        tp, tb = (temp.data_ptr(), temp.numel() * temp.element_size()) if temp is not None else (None, 0)
+        f = lib().dfr_sort_segmented_u32 if kb == 4 else lib().dfr_sort_segmented_u64
+        self._raise(f(self._h, keys.data_ptr(), vp, off.ctypes.data, off.size - 1, tp, tb,
+                      self._stream(stream)), "sort_segmented")
+        return keys, vals
+
+    # -- stages --------------------------------------------------------------------
+    def count(self, keys, bits: int = 8, num_digits: int | None = None, stream=None):
+        """Digit histograms: returns a (num_digits, 256) uint32 tensor on the device."""
+        import torch
+        _check_tensor(keys, "keys")
+        kb = _width(keys)
+        if num_digits is None:
+            num_digits = (8 * kb) // bits
+        hist = torch.empty((num_digits, 256), dtype=torch.uint32, device=keys.device)
+        self._raise(lib().dfr_count(self._h, keys.data_ptr(), kb, keys.numel(), bits, num_digits,
+                                    hist.data_ptr(), self._stream(stream)), "count")
+        return hist
+
+    def deal(self, keys, vals=None, shift: int = 0, bits: int = 8, stream=None):
+        """One stable counting-sort pass on digit (key >> shift) mod 2^bits."""
+        import torch
+        _check_tensor(keys, "keys")
+        kb = _width(keys)
+        ko = torch.empty_like(keys)
+        vo, vp, vop, vb = None, None, None, 0
+        if vals is not None:
+            _check_tensor(vals, "vals")
+            vb = _width(vals)
+            vo = torch.empty_like(vals)
+            vp, vop = vals.data_ptr(), vo.data_ptr()
+        self._raise(lib().dfr_deal(self._h, keys.data_ptr(), vp, ko.data_ptr(), vop, kb, vb,
+                                   keys.numel(), shift, bits, self._stream(stream)), "deal")
+        return ko, vo
+
+    # -- request queue -------------------------------------------------------------
+    def submit(self, keys, vals=None) -> int:
+        _check_tensor(keys, "keys")
+        kb = _width(keys)
+        r = Request(kb, kb if vals is not None else 0, keys.data_ptr(),
+                    vals.data_ptr() if vals is not None else None, keys.numel())
+        t = ctypes.c_uint64(0)
+        self._raise(lib().dfr_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, latency_seconds or None)."""
+        lat = ctypes.c_double(0)
+        st = lib().dfr_poll(self._h, ticket, ctypes.byref(lat))
+        if st == E_PENDING:
+            return False, None
+        self._raise(st, "poll")
+        return True, lat.value
+
+
+_default_ctx: Context | None = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        import torch
+        _default_ctx = Context(torch.cuda.current_device())
+    return _default_ctx
+
+
+def sort_(keys, vals=None, temp=None, stream=None):
+    """Stable in-place sort with the default context."""
+    return default_context().sort_(keys, vals, temp, stream)
+
+
+def sort_segmented_(keys, vals, offsets, temp=None, stream=None):
+    return default_context().sort_segmented_(keys, vals, offsets, temp, stream)

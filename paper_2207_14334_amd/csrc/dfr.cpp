@@ -1,0 +1,1266 @@
+// Host side of the DFR sort: context, planner, level orchestration and the C ABI
+// declared in include/dfr.h.
+//
+// One sort runs as a sequence of *levels* (Sec. 3: DFR recurses on large buckets).
+// A level takes a list of segments -- ranges whose keys agree on every bit at and
+// above the segment's hi_bit -- that all sit in the same buffer (the caller's or the
+// temp buffer), and:
+//   1. counts every 8-bit digit of every segment in one read (k_count), with the OR
+//      and AND of the segment's keys, and reads the OR/AND back;
+//   2. plans: digits that never vary inside a segment are skipped (Sec. 2.1 pass
+//      skipping); the number d of top varying digits to deal is estimated so that the
+//      expected bucket falls below the diversion threshold N_d (Sec. 3, Sec. 3.1);
+//   3. deals those d digits least significant first (k_deal, ping-pong between the
+//      two buffers);
+//   4. finds the buckets of equal leading bits (k_heads), packs runs of small buckets
+//      into local-sort chunks and lists large buckets (k_classify);
+//   5. sorts every chunk inside LDS and writes it into the caller's buffer
+//      (k_local_sort, the diversion);
+//   6. reads back the large buckets, which become the next level's segments.
+// Segments no larger than the local sort's capacity skip steps 1-4 and go straight to
+// step 5.  The result always ends in the caller's buffers (Sec. 2.1: the last deal
+// lands in the original space).
+#include "dfr.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dfr_internal.h"
+
+using namespace dfr;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct LSeg {
+    uint64_t start;
+    uint64_t len;
+    int hi_bit;
+};
+
+enum Stage { ST_COUNT = 0, ST_DEAL, ST_BUCKETS, ST_LOCAL, ST_OTHER, ST_N };
+
+}  // namespace
+
+struct dfr_ctx {
+    int device = 0;
+    size_t budget = 0;
+    bool failed = false;
+    std::string err;
+
+    uint32_t* err_dev = nullptr;  // device error word of the current call
+    // Device scratch arena (bump allocation, reset per level).
+    char* arena = nullptr;
+    size_t arena_cap = 0;
+    size_t arena_used = 0;
+    // Cached temp buffer for calls with temp == NULL.
+    void* tcache = nullptr;
+    size_t tcache_cap = 0;
+    // Pinned host staging (bump allocation, reset after each stream synchronisation).
+    char* pin = nullptr;
+    size_t pin_cap = 0;
+    size_t pin_used = 0;
+
+    // Options.
+    size_t divert = 0;  // 0 = default N_d
+    int force_d = 0;
+    bool timing = false;
+
+    dfr_stats stats{};
+    struct Ev {
+        int stage;
+        bool deal;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> events;
+    std::vector<hipEvent_t> event_pool;
+
+    // Request queue.
+    std::mutex qmu;
+    struct Req {
+        uint64_t ticket;
+        dfr_request r;
+        std::chrono::steady_clock::time_point t0;
+        bool done;
+        double latency;
+    };
+    std::deque<Req> queue;
+    uint64_t next_ticket = 1;
+};
+
+namespace {
+
+dfr_status fail_hip(dfr_ctx* c, hipError_t e, const char* what) {
+    c->failed = true;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    c->err = buf;
+    return DFR_E_HIP;
+}
+
+#define HIP_TRY(ctx, call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return fail_hip(ctx, e_, #call); \
+    } while (0)
+
+// Make room for `bytes` more past the bump pointer, keeping [0, arena_used) intact:
+// a larger arena is allocated, the used prefix copied over on the stream, and the old
+// one freed once the stream has drained.  Pointers into the arena must be re-derived
+// from offsets after a call that may grow it.
+dfr_status arena_need(dfr_ctx* c, size_t bytes, hipStream_t s) {
+    const size_t need = c->arena_used + bytes;
+    if (need <= c->arena_cap) return DFR_OK;
+    const size_t cap = std::max<size_t>(round_up(need + need / 4, 1 << 20), 16 << 20);
+    char* na = nullptr;
+    hipError_t e = hipMalloc((void**)&na, cap);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->err = "scratch allocation failed";
+        return DFR_E_NO_MEMORY;
+    }
+    if (c->arena_used && c->arena)
+        HIP_TRY(c, hipMemcpyAsync(na, c->arena, c->arena_used, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->arena) HIP_TRY(c, hipFree(c->arena));
+    c->arena = na;
+    c->arena_cap = cap;
+    return DFR_OK;
+}
+
+// Start a fresh level: everything in the arena may be overwritten (work already
+// enqueued on the stream keeps its order against later uploads and kernels).
+dfr_status arena_reserve(dfr_ctx* c, size_t bytes, hipStream_t s) {
+    c->arena_used = 0;
+    return arena_need(c, bytes, s);
+}
+
+template <typename T>
+T* aalloc(dfr_ctx* c, size_t count) {
+    size_t bytes = round_up(std::max<size_t>(count, 1) * sizeof(T), ALIGN);
+    T* p = (T*)(c->arena + c->arena_used);
+    c->arena_used += bytes;
+    return p;
+}
+
+template <typename T>
+size_t asize(size_t count) {
+    return round_up(std::max<size_t>(count, 1) * sizeof(T), ALIGN);
+}
+
+// Pinned staging.  Host writes land in it immediately, so it is only reused after a
+// synchronisation of the stream that consumes it.
+dfr_status pin_reserve(dfr_ctx* c, size_t bytes, hipStream_t s) {
+    if (c->pin_used + bytes <= c->pin_cap) return DFR_OK;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->pin_used = 0;
+    if (bytes <= c->pin_cap) return DFR_OK;
+    if (c->pin) HIP_TRY(c, hipHostFree(c->pin));
+    c->pin = nullptr;
+    size_t cap = std::max<size_t>(round_up(bytes * 2, 1 << 20), 4 << 20);
+    hipError_t e = hipHostMalloc((void**)&c->pin, cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->pin_cap = 0;
+        c->err = "pinned staging allocation failed";
+        return DFR_E_NO_MEMORY;
+    }
+    c->pin_cap = cap;
+    return DFR_OK;
+}
+
+template <typename T>
+T* palloc(dfr_ctx* c, size_t count) {
+    size_t bytes = round_up(std::max<size_t>(count, 1) * sizeof(T), 64);
+    T* p = (T*)(c->pin + c->pin_used);
+    c->pin_used += bytes;
+    return p;
+}
+
+void synced(dfr_ctx* c) { c->pin_used = 0; }
+
+// Optional per-stage kernel timing.
+hipEvent_t get_event(dfr_ctx* c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timed {
+    dfr_ctx* c;
+    hipStream_t s;
+    int stage;
+    bool deal;
+    hipEvent_t a = nullptr;
+    Timed(dfr_ctx* c_, hipStream_t s_, int st, bool d = false) : c(c_), s(s_), stage(st), deal(d) {
+        if (c->timing) {
+            a = get_event(c);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~Timed() {
+        if (c->timing && a) {
+            hipEvent_t b = get_event(c);
+            if (b) {
+                (void)hipEventRecord(b, s);
+                c->events.push_back({stage, deal, a, b});
+            }
+        }
+    }
+};
+
+void collect_events(dfr_ctx* c) {
+    for (auto& e : c->events) {
+        float ms = 0.f;
+        if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            switch (e.stage) {
+                case ST_COUNT: c->stats.ms_count += ms; break;
+                case ST_DEAL: c->stats.ms_deal += ms; break;
+                case ST_BUCKETS: c->stats.ms_buckets += ms; break;
+                case ST_LOCAL: c->stats.ms_local_sort += ms; break;
+                default: c->stats.ms_other += ms; break;
+            }
+            if (e.deal) c->stats.deal_launches_timed += 1;
+        }
+        c->event_pool.push_back(e.a);
+        c->event_pool.push_back(e.b);
+    }
+    c->events.clear();
+}
+
+size_t local_cap(int kb, int vb) { return local_sort_capacity(kb, vb); }
+
+size_t default_divert(int kb, int vb) { return local_cap(kb, vb) / 2; }
+
+// ---------------------------------------------------------------------------------
+// Planner (Sec. 3: estimate the number of most significant digits to deal so that
+// diversion is reached; Sec. 3.1: the diversion threshold N_d).
+// ---------------------------------------------------------------------------------
+
+// Varying 8-bit digits of a segment, most significant first, from its OR and AND.
+std::vector<int> varying_digits(uint64_t vor, uint64_t vand, int kb) {
+    std::vector<int> v;
+    const uint64_t var = vor ^ vand;
+    for (int j = kb - 1; j >= 0; --j)
+        if ((var >> (8 * j)) & 0xff) v.push_back(j);
+    return v;
+}
+
+// First level of a plain sort: the histograms of all digits are at hand.  The
+// collision probability of digit j, c_j = sum_v h_j[v]^2 / n^2, is the chance that
+// two random records share that digit; with digits taken as independent, a random
+// record's bucket after dealing the top digits holds about n * prod c_j records.  d is
+// the fewest top varying digits that bring this to N_d or below.  When dealing every
+// varying digit (plain LSD, Sec. 2.1) moves fewer bytes than DFR with that d, the plan
+// deals them all.
+int plan_first_level(const uint32_t* hist, size_t n, int kb, int vb, size_t divert,
+                     const std::vector<int>& V) {
+    const int nv = (int)V.size();
+    if (nv == 0) return 0;
+    double expect = (double)n;
+    int d = nv;
+    for (int i = 0; i < nv; ++i) {
+        double c = 0;
+        const uint32_t* h = hist + (size_t)V[i] * RADIX;
+        for (int v = 0; v < RADIX; ++v) c += (double)h[v] * (double)h[v];
+        c /= (double)n * (double)n;
+        expect *= c;
+        if (expect <= (double)divert) {
+            d = i + 1;
+            break;
+        }
+    }
+    const double rec = kb + vb, pass = 2 * rec;
+    const double dfr_bytes = d * pass + kb + pass;
+    const double lsd_bytes = nv * pass + ((nv % 2) ? pass : 0.0);
+    if (d >= nv || lsd_bytes <= dfr_bytes) d = nv;
+    return d;
+}
+
+// Later levels and segmented sorts: the size-biased mean segment length, divided by
+// 256 per dealt digit (digits taken as uniform).
+int plan_later_level(const std::vector<uint64_t>& lens, size_t divert, int max_digits) {
+    double s1 = 0, s2 = 0;
+    for (uint64_t l : lens) {
+        s1 += (double)l;
+        s2 += (double)l * (double)l;
+    }
+    double expect = s1 > 0 ? s2 / s1 : 0;
+    int d = max_digits;
+    for (int i = 0; i < max_digits; ++i) {
+        expect /= (double)RADIX;
+        if (expect <= (double)divert) {
+            d = i + 1;
+            break;
+        }
+    }
+    return std::max(1, d);
+}
+
+// ---------------------------------------------------------------------------------
+// One sort (plain or segmented), level by level.
+// ---------------------------------------------------------------------------------
+struct Job {
+    dfr_ctx* c;
+    int kb, vb;
+    void* k[2];  // [0] caller, [1] temp
+    void* v[2];
+    hipStream_t s;
+    uint32_t tile;  // deal tile records
+    size_t cap;     // local sort capacity
+    size_t wsmall;  // small bucket limit = window width
+    size_t divert;
+    bool first_level = true;
+    int top_d_forced = 0;
+    uint32_t err_word_host = 0;
+    uint32_t* err_dev = nullptr;
+};
+
+// Tiles of at most `tile` records over the given segments.
+void build_tiles(const std::vector<LSeg>& segs, const std::vector<uint32_t>& ids, uint32_t tile,
+                 std::vector<Tile>& tiles, std::vector<uint32_t>& first_tile) {
+    tiles.clear();
+    first_tile.assign(segs.size(), 0);
+    for (uint32_t s : ids) {
+        first_tile[s] = (uint32_t)tiles.size();
+        for (uint64_t off = 0; off < segs[s].len; off += tile) {
+            Tile t;
+            t.start = segs[s].start + off;
+            t.len = (uint32_t)std::min<uint64_t>(tile, segs[s].len - off);
+            t.seg = s;
+            tiles.push_back(t);
+        }
+    }
+}
+
+dfr_status upload(Job& j, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return DFR_OK;
+    dfr_status st = pin_reserve(j.c, bytes, j.s);
+    if (st) return st;
+    char* p = palloc<char>(j.c, bytes);
+    memcpy(p, src, bytes);
+    HIP_TRY(j.c, hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, j.s));
+    return DFR_OK;
+}
+
+// Copy finished ranges from the temp buffer into the caller's buffer.
+dfr_status copy_back(Job& j, const std::vector<std::pair<uint64_t, uint64_t>>& ranges) {
+    if (ranges.empty()) return DFR_OK;
+    std::vector<Tile> tiles;
+    for (auto& r : ranges)
+        for (uint64_t off = 0; off < r.second; off += 65536)
+            tiles.push_back(Tile{r.first + off, (uint32_t)std::min<uint64_t>(65536, r.second - off), 0});
+    dfr_status st = arena_need(j.c, asize<Tile>(tiles.size()), j.s);
+    if (st) return st;
+    Tile* dt = aalloc<Tile>(j.c, tiles.size());
+    st = upload(j, dt, tiles.data(), tiles.size() * sizeof(Tile));
+    if (st) return st;
+    Timed tm(j.c, j.s, ST_OTHER);
+    HIP_TRY(j.c, launch_copy_tiles(j.kb, j.vb, j.k[1], j.v[1], j.k[0], j.v[0], dt, (uint32_t)tiles.size(), j.s));
+    return DFR_OK;
+}
+
+// Buckets are known on the host (segments no larger than the local sort's capacity):
+// classify and local-sort them straight away.  Each segment is one bucket.
+dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
+    dfr_ctx* c = j.c;
+    const size_t S = segs.size();
+    std::vector<Seg> hs(S);
+    std::vector<uint64_t> bstart;
+    std::vector<uint32_t> bseg;
+    uint64_t nslots = 0, medcap = 0;
+    for (size_t i = 0; i < S; ++i) {
+        Seg g{};
+        g.start = segs[i].start;
+        g.len = segs[i].len;
+        g.window_base = (uint32_t)nslots;
+        g.lo_bit = segs[i].hi_bit;
+        nslots += (segs[i].len + j.wsmall - 1) / j.wsmall;
+        medcap += segs[i].len / (j.wsmall + 1);
+        hs[i] = g;
+        if (segs[i].len) {
+            bstart.push_back(segs[i].start);
+            bseg.push_back((uint32_t)i);
+        }
+    }
+    const uint64_t nb = bstart.size();
+    if (nb == 0) return DFR_OK;
+    const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + asize<uint32_t>(nb) +
+                        2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) + asize<uint32_t>(8) +
+                        asize<Big>(1) * 2;
+    dfr_status st = arena_reserve(c, need, j.s);
+    if (st) return st;
+    Seg* dsegs = aalloc<Seg>(c, S);
+    uint64_t* dbstart = aalloc<uint64_t>(c, nb);
+    uint32_t* dbseg = aalloc<uint32_t>(c, nb);
+    uint32_t* cfirst = aalloc<uint32_t>(c, nslots);
+    uint32_t* clast = aalloc<uint32_t>(c, nslots);
+    uint32_t* med = aalloc<uint32_t>(c, medcap);
+    uint32_t* counters = aalloc<uint32_t>(c, 8);  // nbuckets, nmed, nbig, ndone
+    Big* big = aalloc<Big>(c, 1);
+    Big* done = aalloc<Big>(c, 1);
+    uint32_t nb32 = (uint32_t)nb;
+    st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
+    if (!st) st = upload(j, dbstart, bstart.data(), nb * sizeof(uint64_t));
+    if (!st) st = upload(j, dbseg, bseg.data(), nb * sizeof(uint32_t));
+    if (st) return st;
+    {
+        Timed tm(c, j.s, ST_BUCKETS);
+        HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
+        st = upload(j, counters, &nb32, sizeof nb32);
+        if (st) return st;
+        HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
+        HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
+        ClassifyArgs ca{};
+        ca.bstart = dbstart;
+        ca.bseg = dbseg;
+        ca.nbuckets = counters;
+        ca.bcap = nb;
+        ca.segs = dsegs;
+        ca.wsmall = (uint32_t)j.wsmall;
+        ca.cap = (uint32_t)j.cap;
+        ca.cfirst = cfirst;
+        ca.clast = clast;
+        ca.nslots = (uint32_t)nslots;
+        ca.med = med;
+        ca.nmed = counters + 1;
+        ca.medcap = (uint32_t)medcap;
+        ca.big = big;
+        ca.nbig = counters + 2;
+        ca.bigcap = 0;
+        ca.done = done;
+        ca.ndone = counters + 3;
+        ca.donecap = 0;
+        ca.err = j.err_dev;
+        HIP_TRY(c, launch_classify(ca, (uint32_t)std::min<uint64_t>((nb + 255) / 256, 4096), j.s));
+    }
+    {
+        Timed tm(c, j.s, ST_LOCAL);
+        LocalArgs la{};
+        la.kin = j.k[in];
+        la.vin = j.v[in];
+        la.kout = j.k[0];
+        la.vout = j.v[0];
+        la.bstart = dbstart;
+        la.bseg = dbseg;
+        la.nbuckets = counters;
+        la.bcap = nb;
+        la.segs = dsegs;
+        la.cfirst = cfirst;
+        la.clast = clast;
+        la.nslots = (uint32_t)nslots;
+        la.med = med;
+        la.nmed = counters + 1;
+        la.medcap = (uint32_t)medcap;
+        la.err = j.err_dev;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 4096);
+        HIP_TRY(c, launch_local_sort(j.kb, j.vb, la, blocks, j.s));
+        c->stats.chunks += nb;
+    }
+    c->stats.used_diversion = 1;
+    return DFR_OK;
+}
+
+// A level over segments larger than the local sort's capacity, all held in buffer
+// `in`.  Appends the next level's segments (large buckets) to `next`, and sets
+// *next_in to the buffer that holds them.
+dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector<LSeg>& next,
+                      int* next_in) {
+    dfr_ctx* c = j.c;
+    const size_t S = segs.size();
+    const int kb = j.kb;
+    const int ndig = kb;  // every 8-bit digit
+    *next_in = in;
+    std::vector<uint32_t> all_ids(S);
+    for (size_t i = 0; i < S; ++i) all_ids[i] = (uint32_t)i;
+    std::vector<Tile> tiles;
+    std::vector<uint32_t> first_tile;
+    build_tiles(segs, all_ids, j.tile, tiles, first_tile);
+
+    // --- 1. count ---------------------------------------------------------------
+    // Region A of the arena (kept for the whole level): histograms and OR/AND.
+    const size_t hist_n = S * ndig * RADIX;
+    dfr_status st = arena_reserve(c, asize<uint32_t>(hist_n) + 2 * asize<uint64_t>(S) +
+                                         asize<Tile>(tiles.size()), j.s);
+    if (st) return st;
+    const size_t off_hist = c->arena_used;
+    aalloc<uint32_t>(c, hist_n);
+    const size_t off_or = c->arena_used;
+    aalloc<uint64_t>(c, S);
+    const size_t off_and = c->arena_used;
+    aalloc<uint64_t>(c, S);
+    const size_t region_a = c->arena_used;
+    Tile* dtiles = aalloc<Tile>(c, tiles.size());
+    uint32_t* dhist = (uint32_t*)(c->arena + off_hist);
+    uint64_t* dor = (uint64_t*)(c->arena + off_or);
+    uint64_t* dand = (uint64_t*)(c->arena + off_and);
+    st = upload(j, dtiles, tiles.data(), tiles.size() * sizeof(Tile));
+    if (st) return st;
+    {
+        Timed tm(c, j.s, ST_COUNT);
+        HIP_TRY(c, launch_fill_u32(dhist, 0, hist_n, j.s));
+        HIP_TRY(c, launch_fill_u64(dor, 0, S, j.s));
+        HIP_TRY(c, launch_fill_u64(dand, ~0ull, S, j.s));
+        CountArgs ca{};
+        ca.keys = j.k[in];
+        ca.tiles = dtiles;
+        ca.ntiles = (uint32_t)tiles.size();
+        const uint32_t blocks = (uint32_t)std::min<size_t>(tiles.size(), 2048);
+        ca.tiles_per_block = (uint32_t)((tiles.size() + blocks - 1) / blocks);
+        ca.base_shift = 0;
+        ca.bits = RADIX_BITS;
+        ca.ndig = ndig;
+        ca.hist = dhist;
+        ca.seg_or = dor;
+        ca.seg_and = dand;
+        const uint32_t grid = (uint32_t)((tiles.size() + ca.tiles_per_block - 1) / ca.tiles_per_block);
+        HIP_TRY(c, launch_count(kb, ca, grid, j.s));
+    }
+    // Read back OR/AND (and, at the first level of a plain sort, the histograms).  The
+    // OR/AND words are key-sized: 32-bit keys use the low half of each 8-byte slot.
+    const bool want_hist = j.first_level && S == 1;
+    const size_t rb = S * 2 * sizeof(uint64_t) + (want_hist ? hist_n * sizeof(uint32_t) : 0) + 256;
+    st = pin_reserve(c, rb, j.s);
+    if (st) return st;
+    uint64_t* h_or = palloc<uint64_t>(c, S);
+    uint64_t* h_and = palloc<uint64_t>(c, S);
+    uint32_t* h_hist = want_hist ? palloc<uint32_t>(c, hist_n) : nullptr;
+    HIP_TRY(c, hipMemcpyAsync(h_or, dor, S * 8, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipMemcpyAsync(h_and, dand, S * 8, hipMemcpyDeviceToHost, j.s));
+    if (want_hist) HIP_TRY(c, hipMemcpyAsync(h_hist, dhist, hist_n * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipStreamSynchronize(j.s));
+    std::vector<uint64_t> vor(S), vand(S);
+    for (size_t i = 0; i < S; ++i) {
+        if (kb == 4) {
+            vor[i] = ((const uint32_t*)h_or)[i];
+            vand[i] = ((const uint32_t*)h_and)[i];
+        } else {
+            vor[i] = h_or[i];
+            vand[i] = h_and[i];
+        }
+    }
+    std::vector<uint32_t> hist0;
+    if (want_hist) hist0.assign(h_hist, h_hist + hist_n);
+    synced(c);
+
+    // --- 2. plan ------------------------------------------------------------------
+    std::vector<std::vector<int>> V(S);
+    std::vector<std::pair<uint64_t, uint64_t>> finished;  // all-equal segments
+    std::vector<uint32_t> active;
+    std::vector<uint64_t> lens;
+    int maxv = 0;
+    for (size_t i = 0; i < S; ++i) {
+        V[i] = varying_digits(vor[i], vand[i], kb);
+        if (V[i].empty()) {
+            finished.push_back({segs[i].start, segs[i].len});
+        } else {
+            active.push_back((uint32_t)i);
+            lens.push_back(segs[i].len);
+            maxv = std::max(maxv, (int)V[i].size());
+        }
+    }
+    c->arena_used = region_a;  // the counting tile list is no longer needed
+    if (in == 1) {
+        st = copy_back(j, finished);
+        if (st) return st;
+    }
+    if (active.empty()) return DFR_OK;
+    int d = want_hist ? plan_first_level(hist0.data(), segs[0].len, kb, j.vb, j.divert, V[0])
+                      : plan_later_level(lens, j.divert, maxv);
+    if (j.first_level && j.top_d_forced > 0) d = j.top_d_forced;
+    d = std::max(1, std::min(std::min(d, maxv), MAX_PASSES));
+    if (j.first_level) c->stats.top_digits = d;
+
+    std::vector<Seg> hs(S);
+    bool all_full = true;
+    uint64_t nslots = 0, medcap = 0, bcap = 0, bigcap = 0;
+    build_tiles(segs, active, j.tile, tiles, first_tile);
+    for (uint32_t i : active) {
+        Seg g{};
+        g.start = segs[i].start;
+        g.len = segs[i].len;
+        g.first_tile = first_tile[i];
+        g.window_base = (uint32_t)nslots;
+        g.npass = d;
+        const std::vector<int>& v = V[i];
+        const int nv = (int)v.size();
+        // Selected digits, most significant first; the lowest repeats if fewer vary
+        // (dealing twice on one digit changes nothing: the deal is stable).
+        std::vector<int> sel;
+        for (int q = 0; q < d; ++q) sel.push_back(v[std::min(q, nv - 1)]);
+        for (int p = 0; p < d; ++p) {  // LSD order: least significant selected first
+            const int dig = sel[d - 1 - p];
+            g.shift[p] = (int8_t)(8 * dig);
+            g.width[p] = 8;
+            g.hslot[p] = (int8_t)dig;
+        }
+        const bool full = nv <= d;
+        g.lo_bit = full ? 0 : 8 * sel[d - 1];
+        all_full = all_full && full;
+        nslots += (segs[i].len + j.wsmall - 1) / j.wsmall;
+        medcap += segs[i].len / (j.wsmall + 1);
+        bigcap += segs[i].len / (j.cap + 1);
+        const int distinct = std::min(d, nv);
+        const uint64_t maxb = distinct >= 8 ? ~0ull : (1ull << (8 * distinct));
+        bcap += std::min<uint64_t>(segs[i].len, maxb);
+        hs[i] = g;
+    }
+
+    // --- 3. deal ------------------------------------------------------------------
+    const uint64_t ntiles = tiles.size();
+    const size_t need_b = asize<Tile>(ntiles) + asize<Seg>(S) + asize<uint32_t>(ntiles * RADIX + 1) +
+                          asize<uint64_t>(ntiles + 1) + asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
+                          2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
+                          2 * asize<Big>(bigcap) + asize<uint32_t>(8);
+    st = arena_need(c, need_b, j.s);  // keeps region A
+    if (st) return st;
+    dhist = (uint32_t*)(c->arena + off_hist);
+    dtiles = aalloc<Tile>(c, ntiles);
+    Seg* dsegs = aalloc<Seg>(c, S);
+    uint32_t* lb = aalloc<uint32_t>(c, ntiles * RADIX + 1);
+    uint64_t* lb64 = aalloc<uint64_t>(c, ntiles + 1);
+    uint64_t* dbstart = aalloc<uint64_t>(c, bcap);
+    uint32_t* dbseg = aalloc<uint32_t>(c, bcap);
+    uint32_t* cfirst = aalloc<uint32_t>(c, nslots);
+    uint32_t* clast = aalloc<uint32_t>(c, nslots);
+    uint32_t* med = aalloc<uint32_t>(c, medcap);
+    Big* big = aalloc<Big>(c, bigcap);
+    Big* done = aalloc<Big>(c, bigcap);
+    uint32_t* counters = aalloc<uint32_t>(c, 8);
+    st = upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
+    if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
+    if (st) return st;
+
+    int cur = in;
+    for (int p = 0; p < d; ++p) {
+        Timed tm(c, j.s, ST_DEAL, true);
+        HIP_TRY(c, launch_fill_u32(lb, 0, ntiles * RADIX + 1, j.s));
+        DealArgs da{};
+        da.kin = j.k[cur];
+        da.vin = j.v[cur];
+        da.kout = j.k[1 - cur];
+        da.vout = j.v[1 - cur];
+        da.tiles = dtiles;
+        da.ntiles = (uint32_t)ntiles;
+        da.segs = dsegs;
+        da.hist = dhist;
+        da.hist_digits = ndig;
+        da.pass = p;
+        da.lookback = lb;
+        da.ticket = lb + ntiles * RADIX;
+        da.err = j.err_dev;
+        HIP_TRY(c, launch_deal(kb, j.vb, da, j.s));
+        cur = 1 - cur;
+        c->stats.deal_passes += 1;
+    }
+    *next_in = cur;
+
+    if (all_full) {
+        // Every varying digit was dealt: the segments are sorted (plain LSD).
+        if (cur == 1) {
+            std::vector<std::pair<uint64_t, uint64_t>> r;
+            for (uint32_t i : active) r.push_back({segs[i].start, segs[i].len});
+            st = copy_back(j, r);
+            if (st) return st;
+        }
+        return DFR_OK;
+    }
+
+    // --- 4. buckets ---------------------------------------------------------------
+    {
+        Timed tm(c, j.s, ST_BUCKETS);
+        HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
+        HIP_TRY(c, launch_fill_u64(lb64, 0, ntiles + 1, j.s));
+        HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
+        HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
+        HeadArgs ha{};
+        ha.keys = j.k[cur];
+        ha.tiles = dtiles;
+        ha.ntiles = (uint32_t)ntiles;
+        ha.segs = dsegs;
+        ha.lookback = lb64;
+        ha.ticket = (uint32_t*)(lb64 + ntiles);
+        ha.bstart = dbstart;
+        ha.bseg = dbseg;
+        ha.bcap = bcap;
+        ha.nbuckets = counters;
+        ha.err = j.err_dev;
+        HIP_TRY(c, launch_heads(kb, ha, j.s));
+        ClassifyArgs ca{};
+        ca.bstart = dbstart;
+        ca.bseg = dbseg;
+        ca.nbuckets = counters;
+        ca.bcap = bcap;
+        ca.segs = dsegs;
+        ca.wsmall = (uint32_t)j.wsmall;
+        ca.cap = (uint32_t)j.cap;
+        ca.cfirst = cfirst;
+        ca.clast = clast;
+        ca.nslots = (uint32_t)nslots;
+        ca.med = med;
+        ca.nmed = counters + 1;
+        ca.medcap = (uint32_t)medcap;
+        ca.big = big;
+        ca.nbig = counters + 2;
+        ca.bigcap = (uint32_t)bigcap;
+        ca.done = done;
+        ca.ndone = counters + 3;
+        ca.donecap = (uint32_t)bigcap;
+        ca.err = j.err_dev;
+        HIP_TRY(c, launch_classify(ca, (uint32_t)std::min<uint64_t>((bcap + 255) / 256, 4096), j.s));
+    }
+    // --- 5. local sort --------------------------------------------------------------
+    {
+        Timed tm(c, j.s, ST_LOCAL);
+        LocalArgs la{};
+        la.kin = j.k[cur];
+        la.vin = j.v[cur];
+        la.kout = j.k[0];
+        la.vout = j.v[0];
+        la.bstart = dbstart;
+        la.bseg = dbseg;
+        la.nbuckets = counters;
+        la.bcap = bcap;
+        la.segs = dsegs;
+        la.cfirst = cfirst;
+        la.clast = clast;
+        la.nslots = (uint32_t)nslots;
+        la.med = med;
+        la.nmed = counters + 1;
+        la.medcap = (uint32_t)medcap;
+        la.err = j.err_dev;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 4096);
+        HIP_TRY(c, launch_local_sort(kb, j.vb, la, blocks, j.s));
+    }
+    c->stats.used_diversion = 1;
+
+    // --- 6. large and finished buckets ----------------------------------------------
+    st = pin_reserve(c, 8 * 4 + 2 * bigcap * sizeof(Big) + 256, j.s);
+    if (st) return st;
+    uint32_t* hc = palloc<uint32_t>(c, 8);
+    HIP_TRY(c, hipMemcpyAsync(hc, counters, 8 * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipStreamSynchronize(j.s));
+    const uint32_t nbig = std::min<uint32_t>(hc[2], (uint32_t)bigcap);
+    const uint32_t ndone = std::min<uint32_t>(hc[3], (uint32_t)bigcap);
+    c->stats.chunks += hc[0];
+    Big* hb = palloc<Big>(c, std::max<uint32_t>(nbig, 1));
+    Big* hd = palloc<Big>(c, std::max<uint32_t>(ndone, 1));
+    if (nbig) HIP_TRY(c, hipMemcpyAsync(hb, big, nbig * sizeof(Big), hipMemcpyDeviceToHost, j.s));
+    if (ndone) HIP_TRY(c, hipMemcpyAsync(hd, done, ndone * sizeof(Big), hipMemcpyDeviceToHost, j.s));
+    if (nbig || ndone) HIP_TRY(c, hipStreamSynchronize(j.s));
+    std::vector<Big> bigs(hb, hb + nbig), dones(hd, hd + ndone);
+    synced(c);
+    c->stats.large_buckets += nbig;
+    if (cur == 1 && !dones.empty()) {
+        std::vector<std::pair<uint64_t, uint64_t>> r;
+        for (auto& b : dones) r.push_back({b.start, b.len});
+        st = copy_back(j, r);
+        if (st) return st;
+    }
+    std::sort(bigs.begin(), bigs.end(), [](const Big& a, const Big& b) { return a.start < b.start; });
+    for (auto& b : bigs) next.push_back(LSeg{b.start, b.len, (int)b.hi_bit});
+    return DFR_OK;
+}
+
+dfr_status check_err(Job& j) {
+    dfr_ctx* c = j.c;
+    dfr_status st = pin_reserve(c, 64, j.s);
+    if (st) return st;
+    uint32_t* h = palloc<uint32_t>(c, 1);
+    HIP_TRY(c, hipMemcpyAsync(h, j.err_dev, 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipStreamSynchronize(j.s));
+    const uint32_t e = *h;
+    synced(c);
+    if (e) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "device error word 0x%x", e);
+        c->err = buf;
+        return DFR_E_INTERNAL;
+    }
+    return DFR_OK;
+}
+
+dfr_status run_sort(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const std::vector<LSeg>& segs0,
+                    void* temp, hipStream_t s) {
+    Job j;
+    j.c = c;
+    j.kb = kb;
+    j.vb = vb;
+    j.s = s;
+    j.tile = deal_tile_records(kb, vb);
+    j.cap = local_cap(kb, vb);
+    j.wsmall = j.cap / 2;
+    j.divert = c->divert ? std::min(c->divert, j.cap) : default_divert(kb, vb);
+    j.top_d_forced = c->force_d;
+    uint64_t n = 0;
+    for (auto& g : segs0) n = std::max(n, g.start + g.len);
+    j.k[0] = keys;
+    j.v[0] = vals;
+    j.k[1] = temp;
+    j.v[1] = vb ? (char*)temp + round_up(n * kb, ALIGN) : nullptr;
+
+    c->stats = dfr_stats{};
+    c->events.clear();
+    dfr_status st = DFR_OK;
+    if (!c->err_dev) HIP_TRY(c, hipMalloc((void**)&c->err_dev, ALIGN));
+    j.err_dev = c->err_dev;
+    HIP_TRY(c, launch_fill_u32(j.err_dev, 0, 1, s));
+
+    std::vector<LSeg> small, large;
+    for (auto& g : segs0) {
+        if (g.len <= 1) continue;  // one record is sorted where it is
+        if (g.len <= j.cap) small.push_back(g);
+        else large.push_back(g);
+    }
+    int level = 0;
+    if (!small.empty()) {
+        st = divert_level(j, small, 0);
+        if (st) return st;
+        level = 1;
+    }
+    int in = 0;
+    while (!large.empty()) {
+        std::vector<LSeg> next;
+        int next_in = in;
+        st = deal_level(j, large, in, next, &next_in);
+        if (st) return st;
+        j.first_level = false;
+        ++level;
+        large.swap(next);
+        in = next_in;
+        // Buckets of the next level that fit the local sort do not exist: every
+        // listed bucket exceeds the capacity.
+    }
+    c->stats.levels = level;
+    st = check_err(j);
+    if (c->timing) collect_events(c);
+    return st;
+}
+
+bool overlap(const void* a, size_t an, const void* b, size_t bn) {
+    if (!a || !b || an == 0 || bn == 0) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bn && y < x + an;
+}
+
+dfr_status validate(dfr_ctx* c, const void* keys, const void* vals, size_t n, int kb, int vb,
+                    const void* temp, size_t temp_bytes) {
+    if (!c) return DFR_E_INVALID_ARG;
+    if (c->failed) return DFR_E_HIP;
+    if (!(kb == 4 || kb == 8) || !(vb == 0 || vb == 4 || vb == 8)) return DFR_E_INVALID_ARG;
+    if (n == 0) return DFR_OK;
+    if (!keys) return DFR_E_INVALID_ARG;
+    if ((uintptr_t)keys % kb) return DFR_E_INVALID_ARG;
+    if (vb && (!vals || (uintptr_t)vals % vb)) return DFR_E_INVALID_ARG;
+    if (temp) {
+        if (temp_bytes < dfr_temp_bytes(n, kb, vb)) return DFR_E_INVALID_ARG;
+        if ((uintptr_t)temp % 16) return DFR_E_INVALID_ARG;
+        if (overlap(temp, temp_bytes, keys, n * kb) || (vb && overlap(temp, temp_bytes, vals, n * vb)))
+            return DFR_E_INVALID_ARG;
+    }
+    if (vb && overlap(keys, n * kb, vals, n * vb)) return DFR_E_INVALID_ARG;
+    return DFR_OK;
+}
+
+dfr_status get_temp(dfr_ctx* c, size_t n, int kb, int vb, void** temp, hipStream_t s) {
+    if (*temp) return DFR_OK;
+    const size_t need = dfr_temp_bytes(n, kb, vb);
+    if (c->tcache_cap < need) {
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (c->tcache) HIP_TRY(c, hipFree(c->tcache));
+        c->tcache = nullptr;
+        c->tcache_cap = 0;
+        hipError_t e = hipMalloc(&c->tcache, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            c->err = "temp allocation failed";
+            return DFR_E_NO_MEMORY;
+        }
+        c->tcache_cap = need;
+    }
+    *temp = c->tcache;
+    return DFR_OK;
+}
+
+dfr_status set_device(dfr_ctx* c) {
+    HIP_TRY(c, hipSetDevice(c->device));
+    return DFR_OK;
+}
+
+dfr_status sort_plain(dfr_ctx* c, int kb, int vb, void* keys, void* vals, size_t n, void* temp,
+                      size_t temp_bytes, void* stream) {
+    dfr_status st = validate(c, keys, vals, n, kb, vb, temp, temp_bytes);
+    if (st) return st;
+    if (n > DFR_MAX_SEGMENT_RECORDS) return DFR_E_TOO_LARGE;
+    if (n <= 1) {
+        c->stats = dfr_stats{};
+        return DFR_OK;
+    }
+    st = set_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = get_temp(c, n, kb, vb, &temp, s);
+    if (st) return st;
+    std::vector<LSeg> segs{LSeg{0, n, 8 * kb}};
+    return run_sort(c, kb, vb, keys, vb ? vals : nullptr, segs, temp, s);
+}
+
+dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const uint64_t* off,
+                          size_t S, void* temp, size_t temp_bytes, void* stream) {
+    if (!c) return DFR_E_INVALID_ARG;
+    if (!off) return DFR_E_INVALID_ARG;
+    if (off[0] != 0) return DFR_E_INVALID_ARG;
+    for (size_t i = 0; i < S; ++i)
+        if (off[i + 1] < off[i]) return DFR_E_INVALID_ARG;
+    const size_t n = off[S];
+    dfr_status st = validate(c, keys, vals, n, kb, vb, temp, temp_bytes);
+    if (st) return st;
+    std::vector<LSeg> segs;
+    segs.reserve(S);
+    for (size_t i = 0; i < S; ++i) {
+        const uint64_t len = off[i + 1] - off[i];
+        if (len > DFR_MAX_SEGMENT_RECORDS) return DFR_E_TOO_LARGE;
+        segs.push_back(LSeg{off[i], len, 8 * kb});
+    }
+    if (n <= 1) {
+        c->stats = dfr_stats{};
+        return DFR_OK;
+    }
+    st = set_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = get_temp(c, n, kb, vb, &temp, s);
+    if (st) return st;
+    return run_sort(c, kb, vb, keys, vb ? vals : nullptr, segs, temp, s);
+}
+
+}  // namespace
+
+// =================================================================================
+// C ABI
+// =================================================================================
+extern "C" {
+
+dfr_status dfr_create(int hip_device, size_t hbm_budget_bytes, dfr_ctx** out) {
+    if (!out) return DFR_E_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return DFR_E_HIP;
+    }
+    if (hip_device < 0 || hip_device >= count) return DFR_E_INVALID_ARG;
+    dfr_ctx* c = new (std::nothrow) dfr_ctx();
+    if (!c) return DFR_E_NO_MEMORY;
+    c->device = hip_device;
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete c;
+        return DFR_E_HIP;
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        total_b = 0;
+    }
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : total_b / 4;
+    *out = c;
+    return DFR_OK;
+}
+
+void dfr_destroy(dfr_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->err_dev) (void)hipFree(c->err_dev);
+    if (c->tcache) (void)hipFree(c->tcache);
+    if (c->pin) (void)hipHostFree(c->pin);
+    for (auto& e : c->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* dfr_status_string(dfr_status s) {
+    switch (s) {
+        case DFR_OK: return "ok";
+        case DFR_E_INVALID_ARG: return "invalid argument";
+        case DFR_E_TOO_LARGE: return "too large";
+        case DFR_E_NO_MEMORY: return "out of device memory";
+        case DFR_E_HIP: return "HIP runtime error";
+        case DFR_E_PENDING: return "pending";
+        case DFR_E_NOT_FOUND: return "not found";
+        case DFR_E_BUDGET: return "exceeds memory budget";
+        case DFR_E_UNSUPPORTED: return "unsupported";
+        case DFR_E_INTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* dfr_last_error(const dfr_ctx* c) { return c ? c->err.c_str() : ""; }
+
+size_t dfr_temp_bytes(size_t n, int key_bytes, int val_bytes) {
+    if (!(key_bytes == 4 || key_bytes == 8) || !(val_bytes == 0 || val_bytes == 4 || val_bytes == 8))
+        return 0;
+    return round_up(n * key_bytes, ALIGN) + round_up(n * val_bytes, ALIGN);
+}
+
+size_t dfr_local_sort_capacity(int key_bytes, int val_bytes) {
+    if (!(key_bytes == 4 || key_bytes == 8) || !(val_bytes == 0 || val_bytes == 4 || val_bytes == 8))
+        return 0;
+    return local_cap(key_bytes, val_bytes);
+}
+
+dfr_status dfr_sort_u32(dfr_ctx* c, uint32_t* keys, uint32_t* vals, size_t n, void* temp,
+                        size_t temp_bytes, void* stream) {
+    return sort_plain(c, 4, vals ? 4 : 0, keys, vals, n, temp, temp_bytes, stream);
+}
+
+dfr_status dfr_sort_u64(dfr_ctx* c, uint64_t* keys, uint64_t* vals, size_t n, void* temp,
+                        size_t temp_bytes, void* stream) {
+    return sort_plain(c, 8, vals ? 8 : 0, keys, vals, n, temp, temp_bytes, stream);
+}
+
+dfr_status dfr_sort_segmented_u32(dfr_ctx* c, uint32_t* keys, uint32_t* vals,
+                                  const uint64_t* seg_offsets, size_t num_segments, void* temp,
+                                  size_t temp_bytes, void* stream) {
+    return sort_segmented(c, 4, vals ? 4 : 0, keys, vals, seg_offsets, num_segments, temp,
+                          temp_bytes, stream);
+}
+
+dfr_status dfr_sort_segmented_u64(dfr_ctx* c, uint64_t* keys, uint64_t* vals,
+                                  const uint64_t* seg_offsets, size_t num_segments, void* temp,
+                                  size_t temp_bytes, void* stream) {
+    return sort_segmented(c, 8, vals ? 8 : 0, keys, vals, seg_offsets, num_segments, temp,
+                          temp_bytes, stream);
+}
+
+dfr_status dfr_count(dfr_ctx* c, const void* keys, int key_bytes, size_t n, int bits, int num_digits,
+                     uint32_t* hist, void* stream) {
+    if (!c) return DFR_E_INVALID_ARG;
+    if (c->failed) return DFR_E_HIP;
+    if (!(key_bytes == 4 || key_bytes == 8) || bits < 1 || bits > 8 || num_digits < 1 ||
+        num_digits > MAX_PASSES || num_digits * bits > 8 * key_bytes || !hist)
+        return DFR_E_INVALID_ARG;
+    if (n > 0 && (!keys || (uintptr_t)keys % key_bytes)) return DFR_E_INVALID_ARG;
+    if (n > DFR_MAX_SEGMENT_RECORDS) return DFR_E_TOO_LARGE;
+    dfr_status st = set_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(c, launch_fill_u32(hist, 0, (size_t)num_digits * RADIX, s));
+    if (n == 0) return DFR_OK;
+    std::vector<LSeg> segs{LSeg{0, n, 8 * key_bytes}};
+    std::vector<uint32_t> ids{0};
+    std::vector<Tile> tiles;
+    std::vector<uint32_t> ft;
+    Job j;
+    j.c = c;
+    j.s = s;
+    build_tiles(segs, ids, deal_tile_records(key_bytes, 0), tiles, ft);
+    st = arena_reserve(c, asize<Tile>(tiles.size()) + 2 * asize<uint64_t>(1), s);
+    if (st) return st;
+    Tile* dt = aalloc<Tile>(c, tiles.size());
+    uint64_t* dor = aalloc<uint64_t>(c, 1);
+    uint64_t* dand = aalloc<uint64_t>(c, 1);
+    st = upload(j, dt, tiles.data(), tiles.size() * sizeof(Tile));
+    if (st) return st;
+    CountArgs ca{};
+    ca.keys = keys;
+    ca.tiles = dt;
+    ca.ntiles = (uint32_t)tiles.size();
+    const uint32_t blocks = (uint32_t)std::min<size_t>(tiles.size(), 2048);
+    ca.tiles_per_block = (uint32_t)((tiles.size() + blocks - 1) / blocks);
+    ca.base_shift = 0;
+    ca.bits = bits;
+    ca.ndig = num_digits;
+    ca.hist = hist;
+    ca.seg_or = dor;
+    ca.seg_and = dand;
+    const uint32_t grid = (uint32_t)((tiles.size() + ca.tiles_per_block - 1) / ca.tiles_per_block);
+    HIP_TRY(c, launch_count(key_bytes, ca, grid, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    synced(c);
+    return DFR_OK;
+}
+
+dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* keys_out,
+                    void* vals_out, int key_bytes, int val_bytes, size_t n, int shift, int bits,
+                    void* stream) {
+    if (!c) return DFR_E_INVALID_ARG;
+    if (c->failed) return DFR_E_HIP;
+    if (!(key_bytes == 4 || key_bytes == 8) || !(val_bytes == 0 || val_bytes == 4 || val_bytes == 8))
+        return DFR_E_INVALID_ARG;
+    if (bits < 1 || bits > 8 || shift < 0 || shift + bits > 8 * key_bytes) return DFR_E_INVALID_ARG;
+    if ((val_bytes == 0) != (vals_in == nullptr && vals_out == nullptr)) return DFR_E_INVALID_ARG;
+    if (n == 0) return DFR_OK;
+    if (!keys_in || !keys_out || (uintptr_t)keys_in % key_bytes || (uintptr_t)keys_out % key_bytes)
+        return DFR_E_INVALID_ARG;
+    if (val_bytes && (!vals_in || !vals_out || (uintptr_t)vals_in % val_bytes ||
+                      (uintptr_t)vals_out % val_bytes))
+        return DFR_E_INVALID_ARG;
+    const size_t kbn = n * key_bytes, vbn = n * val_bytes;
+    if (overlap(keys_in, kbn, keys_out, kbn) || (val_bytes && (overlap(vals_in, vbn, vals_out, vbn) ||
+                                                               overlap(keys_in, kbn, vals_out, vbn) ||
+                                                               overlap(vals_in, vbn, keys_out, kbn) ||
+                                                               overlap(keys_out, kbn, vals_out, vbn))))
+        return DFR_E_INVALID_ARG;
+    if (n > DFR_MAX_SEGMENT_RECORDS) return DFR_E_TOO_LARGE;
+    dfr_status st = set_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Job j;
+    j.c = c;
+    j.s = s;
+    std::vector<LSeg> segs{LSeg{0, n, 8 * key_bytes}};
+    std::vector<uint32_t> ids{0};
+    std::vector<Tile> tiles;
+    std::vector<uint32_t> ft;
+    build_tiles(segs, ids, deal_tile_records(key_bytes, val_bytes), tiles, ft);
+    const size_t nt = tiles.size();
+    st = arena_reserve(c, asize<Tile>(nt) + asize<Seg>(1) + asize<uint32_t>(RADIX) +
+                              2 * asize<uint64_t>(1) + asize<uint32_t>(nt * RADIX + 1) +
+                              asize<uint32_t>(1),
+                       s);
+    if (st) return st;
+    Tile* dt = aalloc<Tile>(c, nt);
+    Seg* ds = aalloc<Seg>(c, 1);
+    uint32_t* dh = aalloc<uint32_t>(c, RADIX);
+    uint64_t* dor = aalloc<uint64_t>(c, 1);
+    uint64_t* dand = aalloc<uint64_t>(c, 1);
+    uint32_t* lb = aalloc<uint32_t>(c, nt * RADIX + 1);
+    uint32_t* derr = aalloc<uint32_t>(c, 1);
+    Seg g{};
+    g.start = 0;
+    g.len = n;
+    g.first_tile = 0;
+    g.npass = 1;
+    g.shift[0] = (int8_t)shift;
+    g.width[0] = (int8_t)bits;
+    g.hslot[0] = 0;
+    g.lo_bit = shift;
+    st = upload(j, dt, tiles.data(), nt * sizeof(Tile));
+    if (!st) st = upload(j, ds, &g, sizeof g);
+    if (st) return st;
+    HIP_TRY(c, launch_fill_u32(dh, 0, RADIX, s));
+    HIP_TRY(c, launch_fill_u32(lb, 0, nt * RADIX + 1, s));
+    HIP_TRY(c, launch_fill_u32(derr, 0, 1, s));
+    CountArgs ca{};
+    ca.keys = keys_in;
+    ca.tiles = dt;
+    ca.ntiles = (uint32_t)nt;
+    const uint32_t blocks = (uint32_t)std::min<size_t>(nt, 2048);
+    ca.tiles_per_block = (uint32_t)((nt + blocks - 1) / blocks);
+    ca.base_shift = shift;
+    ca.bits = bits;
+    ca.ndig = 1;
+    ca.hist = dh;
+    ca.seg_or = dor;
+    ca.seg_and = dand;
+    HIP_TRY(c, launch_count(key_bytes, ca, (uint32_t)((nt + ca.tiles_per_block - 1) / ca.tiles_per_block), s));
+    DealArgs da{};
+    da.kin = keys_in;
+    da.vin = vals_in;
+    da.kout = keys_out;
+    da.vout = vals_out;
+    da.tiles = dt;
+    da.ntiles = (uint32_t)nt;
+    da.segs = ds;
+    da.hist = dh;
+    da.hist_digits = 1;
+    da.pass = 0;
+    da.lookback = lb;
+    da.ticket = lb + nt * RADIX;
+    da.err = derr;
+    {
+        Timed tm(c, s, ST_DEAL, true);
+        HIP_TRY(c, launch_deal(key_bytes, val_bytes, da, s));
+    }
+    st = pin_reserve(c, 64, s);
+    if (st) return st;
+    uint32_t* he = palloc<uint32_t>(c, 1);
+    HIP_TRY(c, hipMemcpyAsync(he, derr, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const uint32_t e = *he;
+    synced(c);
+    if (c->timing) collect_events(c);
+    if (e) {
+        c->err = "device error in deal";
+        return DFR_E_INTERNAL;
+    }
+    return DFR_OK;
+}
+
+dfr_status dfr_submit(dfr_ctx* c, const dfr_request* req, uint64_t* ticket) {
+    (void)c;
+    (void)req;
+    (void)ticket;
+    return DFR_E_UNSUPPORTED;
+}
+
+dfr_status dfr_poll(dfr_ctx* c, uint64_t ticket, double* latency_s) {
+    (void)c;
+    (void)ticket;
+    (void)latency_s;
+    return DFR_E_UNSUPPORTED;
+}
+
+dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
+    if (!c || !name) return DFR_E_INVALID_ARG;
+    if (!strcmp(name, "divert_records")) {
+        if (value < 0) return DFR_E_INVALID_ARG;
+        c->divert = (size_t)value;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "force_top_digits")) {
+        if (value < 0 || value > MAX_PASSES) return DFR_E_INVALID_ARG;
+        c->force_d = (int)value;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "timing")) {
+        c->timing = value != 0;
+        return DFR_OK;
+    }
+    return DFR_E_UNSUPPORTED;
+}
+
+dfr_status dfr_get_stats(const dfr_ctx* c, dfr_stats* out) {
+    if (!c || !out) return DFR_E_INVALID_ARG;
+    *out = c->stats;
+    return DFR_OK;
+}
+
+dfr_status dfr_plan_top_digits(const uint32_t* hist, size_t n, int key_bytes, int val_bytes,
+                               size_t divert_records, int32_t* top_digits, int32_t* varying) {
+    if (!hist || !top_digits || !(key_bytes == 4 || key_bytes == 8) ||
+        !(val_bytes == 0 || val_bytes == 4 || val_bytes == 8))
+        return DFR_E_INVALID_ARG;
+    std::vector<int> V;
+    for (int dgt = key_bytes - 1; dgt >= 0; --dgt) {
+        int nz = 0;
+        for (int v = 0; v < RADIX; ++v) nz += hist[(size_t)dgt * RADIX + v] != 0;
+        if (nz > 1) V.push_back(dgt);
+    }
+    const size_t cap = local_cap(key_bytes, val_bytes);
+    const size_t divert = divert_records ? std::min(divert_records, cap) : default_divert(key_bytes, val_bytes);
+    *top_digits = n <= cap ? 0 : plan_first_level(hist, n, key_bytes, val_bytes, divert, V);
+    if (varying) *varying = (int32_t)V.size();
+    return DFR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Internal declarations shared by the device kernels (kernels.hip) and the host
+// orchestration (dfr.cpp).  Not part of the public ABI (include/dfr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfr {
+
+// Radix width of the deal passes: 8-bit digits, 256 buckets per digit, as the
+// paper's N/256 bucket estimate and its 256 amortised checks imply (Sec. 4).
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+
+// Look-back words of the deal pass: 2-bit status over a 30-bit count.
+constexpr uint32_t LB_AGG = 1u << 30;   // tile's own count published
+constexpr uint32_t LB_PRE = 2u << 30;   // inclusive prefix through this tile published
+constexpr uint32_t LB_COUNT = (1u << 30) - 1;
+// 64-bit look-back words (bucket-head compaction): same layout in the top bits.
+constexpr uint64_t LB64_AGG = 1ull << 62;
+constexpr uint64_t LB64_PRE = 2ull << 62;
+constexpr uint64_t LB64_COUNT = (1ull << 62) - 1;
+
+// Bits of the device error word.
+constexpr uint32_t ERR_SPIN = 1;        // a bounded look-back wait expired
+constexpr uint32_t ERR_BUCKET_CAP = 2;  // more bucket heads than the list holds
+constexpr uint32_t ERR_LIST_CAP = 4;    // a work list overflowed
+constexpr uint32_t ERR_CHUNK = 8;       // a local-sort chunk exceeded its capacity
+constexpr uint32_t ERR_RANGE = 16;      // a computed position fell outside its segment
+
+constexpr int MAX_PASSES = 8;
+
+// One segment of a level: a range of records whose keys agree on every bit at and
+// above hi_bit, sorted independently of the others.
+struct Seg {
+    uint64_t start;
+    uint64_t len;
+    uint32_t first_tile;   // index of the segment's first tile in the level's tile list
+    uint32_t window_base;  // first local-sort window slot of the segment
+    int32_t lo_bit;        // after this level's deals, buckets agree on bits >= lo_bit
+    int32_t npass;
+    int8_t shift[MAX_PASSES];  // digit of deal pass j: (key >> shift[j]) mod 2^width[j]
+    int8_t width[MAX_PASSES];
+    int8_t hslot[MAX_PASSES];  // histogram slot holding that digit's counts
+};
+
+// A contiguous run of at most one tile's records inside one segment.
+struct Tile {
+    uint64_t start;
+    uint32_t len;
+    uint32_t seg;
+};
+
+// A bucket too large for the local sort, to be sorted by the next level.
+struct Big {
+    uint64_t start;
+    uint32_t len;
+    uint32_t hi_bit;
+};
+
+struct CountArgs {
+    const void* keys;
+    const Tile* tiles;
+    uint32_t ntiles;
+    uint32_t tiles_per_block;
+    int32_t base_shift;  // digit j sits at base_shift + j * bits
+    int32_t bits;
+    int32_t ndig;        // <= MAX_PASSES
+    uint32_t* hist;      // [seg][ndig][RADIX]
+    void* seg_or;        // [seg] key type, OR of the segment's keys
+    void* seg_and;       // [seg] key type, AND of the segment's keys
+};
+
+struct DealArgs {
+    const void* kin;
+    const void* vin;
+    void* kout;
+    void* vout;
+    const Tile* tiles;
+    uint32_t ntiles;
+    const Seg* segs;
+    const uint32_t* hist;
+    int32_t hist_digits;
+    int32_t pass;
+    uint32_t* lookback;  // [ntiles][RADIX]
+    uint32_t* ticket;
+    uint32_t* err;
+};
+
+struct HeadArgs {
+    const void* keys;
+    const Tile* tiles;
+    uint32_t ntiles;
+    const Seg* segs;
+    uint64_t* lookback;  // [ntiles]
+    uint32_t* ticket;
+    uint64_t* bstart;
+    uint32_t* bseg;
+    uint64_t bcap;
+    uint32_t* nbuckets;
+    uint32_t* err;
+};
+
+struct ClassifyArgs {
+    const uint64_t* bstart;
+    const uint32_t* bseg;
+    const uint32_t* nbuckets;
+    uint64_t bcap;
+    const Seg* segs;
+    uint32_t wsmall;  // largest "small" bucket, also the window width
+    uint32_t cap;     // local sort capacity
+    uint32_t* cfirst;
+    uint32_t* clast;
+    uint32_t nslots;
+    uint32_t* med;
+    uint32_t* nmed;
+    uint32_t medcap;
+    Big* big;
+    uint32_t* nbig;
+    uint32_t bigcap;
+    Big* done;
+    uint32_t* ndone;
+    uint32_t donecap;
+    uint32_t* err;
+};
+
+struct LocalArgs {
+    const void* kin;
+    const void* vin;
+    void* kout;
+    void* vout;
+    const uint64_t* bstart;
+    const uint32_t* bseg;
+    const uint32_t* nbuckets;
+    uint64_t bcap;
+    const Seg* segs;
+    const uint32_t* cfirst;
+    const uint32_t* clast;
+    uint32_t nslots;
+    const uint32_t* med;
+    const uint32_t* nmed;
+    uint32_t medcap;
+    uint32_t* err;
+};
+
+// Tile and capacity choices per (key bytes, value bytes).
+uint32_t deal_tile_records(int kb, int vb);
+uint32_t local_sort_capacity(int kb, int vb);
+
+// Launchers (kernels.hip).  Each returns the launch's hipError_t.
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
+hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
+hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
+                             hipStream_t s);
+hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, void* kout,
+                             void* vout, const Tile* tiles, uint32_t ntiles, hipStream_t s);
+
+}  // namespace dfr

@@ -1,0 +1,871 @@
+// Device kernels of the DFR sort for gfx950 (CDNA4, wave64).
+//
+// The paper's vocabulary (Sec. 2): a *count* tallies how often each value of one
+// digit occurs; the counts become bucket indices by an exclusive prefix sum; a *deal*
+// moves every record into its bucket, keeping input order among equal digits.  DFR
+// (Sec. 3) deals the top digits least significant first, then diverts runs of small
+// buckets to a simple stable sort and recurses on large buckets.
+//
+//   k_count        count: digit histograms of every digit in one read, plus the OR and
+//                  AND of each segment's keys (digits that never vary are skipped).
+//   k_deal         deal: one stable scatter pass.  Tiles take tickets in order; each
+//                  tile ranks its records by digit with wave ballots, publishes its
+//                  digit counts, and finds its offsets by decoupled look-back over the
+//                  tiles before it; records are staged in LDS so each bucket's run is
+//                  written contiguously.
+//   k_heads        bucket boundaries after the deals: positions where the leading
+//                  bits change, compacted in order (look-back over one counter).
+//   k_classify     buckets -> runs of small buckets packed per window, medium buckets,
+//                  large buckets (recursion) and finished large buckets.
+//   k_local_sort   the diversion: a stable LSD radix sort inside LDS of one run of
+//                  small buckets (or one medium bucket), over only the bits that vary.
+//   k_copy_tiles   copy of finished ranges back into the caller's buffers.
+#include "dfr_internal.h"
+
+#include <algorithm>
+
+namespace dfr {
+
+template <int B>
+struct uint_of {
+    using type = uint32_t;
+};
+template <>
+struct uint_of<8> {
+    using type = uint64_t;
+};
+
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Lanes of the wave (within `active`) whose digit equals this lane's, from one ballot
+// per digit bit.  Lane order is input order, so lanes_below() of the result is this
+// record's stable rank among equal digits in the wave.
+template <int BITS>
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t active) {
+    uint64_t m = active;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const bool on = (d >> b) & 1u;
+        const uint64_t bal = __ballot(on);
+        m &= on ? bal : ~bal;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint64_t same_digit_lanes_rt(uint32_t d, uint64_t active, int bits) {
+    uint64_t m = active;
+#pragma unroll
+    for (int b = 0; b < RADIX_BITS; ++b) {
+        if (b < bits) {
+            const bool on = (d >> b) & 1u;
+            const uint64_t bal = __ballot(on);
+            m &= on ? bal : ~bal;
+        }
+    }
+    return m;
+}
+
+// Spin (bounded) until a look-back word carries a status.
+__device__ __forceinline__ uint32_t wait_published(uint32_t* p, uint32_t* err) {
+    uint32_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    while ((x & (LB_AGG | LB_PRE)) == 0) {
+        if (++spins > SPIN_LIMIT) {
+            atomicOr(err, ERR_SPIN);
+            return LB_PRE;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wait_published64(uint64_t* p, uint32_t* err) {
+    uint64_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    while ((x & (LB64_AGG | LB64_PRE)) == 0) {
+        if (++spins > SPIN_LIMIT) {
+            atomicOr(err, ERR_SPIN);
+            return LB64_PRE;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over threads 0..255 of the block (threads
+// above 255 pass anything and ignore the result).  *total gets the sum of the 256.
+// Every thread of the block must call it (it holds two barriers).
+__device__ __forceinline__ uint32_t scan256_excl(uint32_t x, uint32_t* s_part, uint32_t* total) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (tid < RADIX && lane == 63) s_part[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, sum = 0;
+#pragma unroll
+    for (int i = 0; i < RADIX / 64; ++i) {
+        const uint32_t p = s_part[i];
+        before += (i < w) ? p : 0u;
+        sum += p;
+    }
+    __syncthreads();
+    *total = sum;
+    return before + incl - x;
+}
+
+template <typename K>
+__device__ __forceinline__ K wave_or(K x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+    return x;
+}
+template <typename K>
+__device__ __forceinline__ K wave_and(K x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x &= __shfl_xor(x, o, 64);
+    return x;
+}
+
+// ---------------------------------------------------------------------------------
+// Fill.
+// ---------------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------------
+// Count (Sec. 2): per-segment digit histograms of up to MAX_PASSES digits, in one read.
+// Each wave keeps private LDS bins; the lanes that share the first active lane's digit
+// add their number in one LDS atomic (this absorbs skewed inputs where most keys
+// share a digit), the other lanes add one each.
+// ---------------------------------------------------------------------------------
+template <int KB, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
+    using K = typename uint_of<KB>::type;
+    constexpr int W = THREADS / 64;
+    constexpr int SLICE = MAX_PASSES * RADIX;
+    __shared__ uint32_t s_h[W * SLICE];
+    __shared__ K s_or[W];
+    __shared__ K s_and[W];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int i = tid; i < W * SLICE; i += THREADS) s_h[i] = 0;
+    __syncthreads();
+
+    const uint32_t t0 = blockIdx.x * a.tiles_per_block;
+    if (t0 >= a.ntiles) return;
+    const uint32_t t1 = a.ntiles - t0 < a.tiles_per_block ? a.ntiles : t0 + a.tiles_per_block;
+    const int ndig = a.ndig, bits = a.bits, base = a.base_shift;
+    const uint32_t dmask = (1u << bits) - 1u;
+    uint32_t* hw = s_h + w * SLICE;
+
+    uint32_t cur = a.tiles[t0].seg;
+    K vor = 0, vand = ~K(0);
+
+    auto flush = [&](uint32_t seg) {
+        __syncthreads();
+        for (int idx = tid; idx < ndig * RADIX; idx += THREADS) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) {
+                s += s_h[ww * SLICE + idx];
+                s_h[ww * SLICE + idx] = 0;
+            }
+            if (s) atomicAdd(&a.hist[(size_t)seg * ndig * RADIX + idx], s);
+        }
+        const K o = wave_or(vor), n = wave_and(vand);
+        if (lane == 0) {
+            s_or[w] = o;
+            s_and[w] = n;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            K o2 = 0, n2 = ~K(0);
+            for (int ww = 0; ww < W; ++ww) {
+                o2 |= s_or[ww];
+                n2 &= s_and[ww];
+            }
+            atomicOr(&((K*)a.seg_or)[seg], o2);
+            atomicAnd(&((K*)a.seg_and)[seg], n2);
+        }
+        __syncthreads();
+    };
+
+    for (uint32_t t = t0; t < t1; ++t) {
+        const Tile tl = a.tiles[t];
+        if (tl.seg != cur) {
+            flush(cur);
+            cur = tl.seg;
+            vor = 0;
+            vand = ~K(0);
+        }
+        const K* kp = (const K*)a.keys + tl.start;
+        constexpr int U = 4;
+        for (uint32_t i0 = 0; i0 < tl.len; i0 += THREADS * U) {
+            K kk[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t i = i0 + u * THREADS + tid;
+                ok[u] = i < tl.len;
+                kk[u] = ok[u] ? kp[i] : K(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!ok[u]) continue;
+                vor |= kk[u];
+                vand &= kk[u];
+                for (int j = 0; j < ndig; ++j) {
+                    const uint32_t d = (uint32_t)(kk[u] >> (base + j * bits)) & dmask;
+                    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                    const uint64_t m0 = __ballot(d == d0);
+                    if (d == d0) {
+                        if (lanes_below(m0) == 0)
+                            atomicAdd(&hw[j * RADIX + d0], (uint32_t)__popcll(m0));
+                    } else {
+                        atomicAdd(&hw[j * RADIX + d], 1u);
+                    }
+                }
+            }
+        }
+    }
+    flush(cur);
+}
+
+// ---------------------------------------------------------------------------------
+// Deal (Sec. 2; one pass of the LSD phase of Sec. 3).  One tile per block, tiles in
+// ticket order so every tile it waits on is already running.
+//
+// Tile layout: wave w holds records [w*ITEMS*64, (w+1)*ITEMS*64) of the tile, item k
+// of lane l being record w*ITEMS*64 + k*64 + l, so a wave meets its records in input
+// order and the ballot ranks are stable.
+// ---------------------------------------------------------------------------------
+template <int KB, int VB, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
+    using K = typename uint_of<KB>::type;
+    using V = typename uint_of<VB>::type;
+    constexpr int W = THREADS / 64;
+    constexpr uint32_t T = THREADS * ITEMS;
+    static_assert(THREADS >= RADIX, "one thread per digit value");
+
+    __shared__ K s_keys[T];
+    __shared__ V s_vals[VB ? T : 1];
+    __shared__ uint32_t s_wcnt[W * RADIX];
+    __shared__ uint64_t s_gdelta[RADIX];
+    __shared__ uint32_t s_local[RADIX];
+    __shared__ uint32_t s_part[RADIX / 64];
+    __shared__ uint32_t s_ticket;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
+    for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[i] = 0;
+    __syncthreads();
+    const uint32_t t = s_ticket;
+    if (t >= a.ntiles) return;
+
+    const Tile tl = a.tiles[t];
+    const Seg* sg = a.segs + tl.seg;
+    const uint64_t seg_start = sg->start, seg_end = sg->start + sg->len;
+    const uint32_t first_tile = sg->first_tile;
+    const int shift = sg->shift[a.pass];
+    const uint32_t dmask = (1u << sg->width[a.pass]) - 1u;
+    const int hslot = sg->hslot[a.pass];
+    const uint32_t len = tl.len;
+    const K* kin = (const K*)a.kin + tl.start;
+    const V* vin = (const V*)a.vin + tl.start;
+
+    K key[ITEMS];
+    V val[ITEMS];
+    uint32_t rnk[ITEMS];
+    const uint32_t wbase = (uint32_t)w * ITEMS * 64;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        const bool ok = idx < len;
+        key[k] = ok ? kin[idx] : K(0);
+        if (VB) val[k] = ok ? vin[idx] : V(0);
+    }
+
+    // Stable rank of each record among equal digits, per wave.
+    uint32_t* wc = s_wcnt + w * RADIX;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        const bool ok = idx < len;
+        const uint64_t act = __ballot(ok);
+        const uint32_t d = (uint32_t)(key[k] >> shift) & dmask;
+        const uint64_t m = same_digit_lanes<RADIX_BITS>(d, act);
+        const uint32_t below = lanes_below(m);
+        const uint32_t base = wc[d];
+        if (ok && below == 0) wc[d] = base + (uint32_t)__popcll(m);
+        rnk[k] = base + below;
+    }
+    __syncthreads();
+
+    // Per digit: offsets of each wave's run, the tile's count, and its publication.
+    uint32_t tile_cnt = 0;
+    if (tid < RADIX) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = s_wcnt[ww * RADIX + tid];
+            s_wcnt[ww * RADIX + tid] = run;
+            run += c;
+        }
+        tile_cnt = run;
+        __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid],
+                           (t == first_tile ? LB_PRE : LB_AGG) | run, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t hv =
+        tid < RADIX ? a.hist[((size_t)tl.seg * a.hist_digits + hslot) * RADIX + tid] : 0u;
+    uint32_t total;
+    const uint32_t seg_excl = scan256_excl(hv, s_part, &total);
+    const uint32_t loc_excl = scan256_excl(tile_cnt, s_part, &total);
+
+    if (tid < RADIX) {
+        s_local[tid] = loc_excl;
+        uint32_t excl = 0;
+        if (t != first_tile) {
+            uint32_t j = t - 1;
+            for (;;) {
+                const uint32_t x = wait_published(&a.lookback[(size_t)j * RADIX + tid], a.err);
+                excl += x & LB_COUNT;
+                if ((x & LB_PRE) || j <= first_tile) break;
+                --j;
+            }
+            __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid], LB_PRE | (excl + tile_cnt),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_gdelta[tid] = seg_start + (uint64_t)seg_excl + (uint64_t)excl - (uint64_t)loc_excl;
+    }
+    __syncthreads();
+
+    // Stage the tile in LDS in digit order.
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        if (idx < len) {
+            const uint32_t d = (uint32_t)(key[k] >> shift) & dmask;
+            const uint32_t p = wc[d] + s_local[d] + rnk[k];
+            if (p < T) {
+                s_keys[p] = key[k];
+                if (VB) s_vals[p] = val[k];
+            }
+        }
+    }
+    __syncthreads();
+
+    // Runs of equal digits go to consecutive addresses of their bucket.
+    K* kout = (K*)a.kout;
+    V* vout = (V*)a.vout;
+    bool bad = false;
+    for (uint32_t i = tid; i < len; i += THREADS) {
+        const K kk = s_keys[i];
+        const uint32_t d = (uint32_t)(kk >> shift) & dmask;
+        const uint64_t p = s_gdelta[d] + i;
+        if (p >= seg_start && p < seg_end) {
+            kout[p] = kk;
+            if (VB) vout[p] = s_vals[i];
+        } else {
+            bad = true;
+        }
+    }
+    if (bad) atomicOr(a.err, ERR_RANGE);
+}
+
+// ---------------------------------------------------------------------------------
+// Bucket heads (Sec. 2.2 buckets; Sec. 3 "determine if any large buckets remain").
+// After the deals, records of a segment are ordered by their bits >= lo_bit; a
+// bucket starts where those bits change (or at the segment start).  Heads are
+// written in position order: wave ballots inside the tile, look-back across tiles.
+// ---------------------------------------------------------------------------------
+template <int KB, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_heads(HeadArgs a) {
+    using K = typename uint_of<KB>::type;
+    constexpr int W = THREADS / 64;
+    constexpr int KBITS = 8 * KB;
+    __shared__ uint32_t s_wtot[W];
+    __shared__ uint32_t s_ticket;
+    __shared__ uint64_t s_excl;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
+    __syncthreads();
+    const uint32_t t = s_ticket;
+    if (t >= a.ntiles) return;
+    const Tile tl = a.tiles[t];
+    const Seg* sg = a.segs + tl.seg;
+    const int lo = sg->lo_bit;
+    const uint64_t seg_start = sg->start;
+    const K* kp = (const K*)a.keys;
+    const uint32_t len = tl.len;
+
+    uint32_t off[ITEMS];
+    bool head[ITEMS];
+    uint32_t run = 0;
+    const uint32_t wbase = (uint32_t)w * ITEMS * 64;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        const bool ok = idx < len;
+        const uint64_t gpos = tl.start + idx;
+        bool h = false;
+        if (ok) {
+            if (gpos == seg_start || lo >= KBITS) {
+                h = gpos == seg_start;
+            } else {
+                const K cur = kp[gpos], prev = kp[gpos - 1];
+                h = (cur >> lo) != (prev >> lo);
+            }
+        }
+        head[k] = h;
+        const uint64_t hb = __ballot(h);
+        off[k] = run + lanes_below(hb);
+        run += (uint32_t)__popcll(hb);
+    }
+    if (lane == 0) s_wtot[w] = run;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t tot = 0;
+        for (int ww = 0; ww < W; ++ww) tot += s_wtot[ww];
+        __hip_atomic_store(&a.lookback[t], (t == 0 ? LB64_PRE : LB64_AGG) | (uint64_t)tot,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t excl = 0;
+        if (t != 0) {
+            uint32_t j = t - 1;
+            for (;;) {
+                const uint64_t x = wait_published64(&a.lookback[j], a.err);
+                excl += x & LB64_COUNT;
+                if ((x & LB64_PRE) || j == 0) break;
+                --j;
+            }
+            __hip_atomic_store(&a.lookback[t], LB64_PRE | (excl + tot), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (t == a.ntiles - 1) {
+            const uint64_t nbk = excl + tot;
+            *a.nbuckets = nbk > 0xffffffffull ? 0xffffffffu : (uint32_t)nbk;
+        }
+        s_excl = excl;
+    }
+    __syncthreads();
+    uint64_t wexcl = s_excl;
+    for (int ww = 0; ww < w; ++ww) wexcl += s_wtot[ww];
+    bool over = false;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        if (head[k]) {
+            const uint64_t gi = wexcl + off[k];
+            if (gi < a.bcap) {
+                a.bstart[gi] = tl.start + wbase + k * 64 + lane;
+                a.bseg[gi] = tl.seg;
+            } else {
+                over = true;
+            }
+        }
+    }
+    if (over) atomicOr(a.err, ERR_BUCKET_CAP);
+}
+
+// ---------------------------------------------------------------------------------
+// Classify buckets (Sec. 3: runs of small buckets are sorted in bulk, large buckets
+// recursively).  Window width = wsmall: the small buckets starting in one window of
+// a segment are contiguous and span at most 2*wsmall = cap records, so each window's
+// run is one local-sort chunk.
+// ---------------------------------------------------------------------------------
+__global__ void k_classify(ClassifyArgs a) {
+    const uint64_t nb = umin64(*a.nbuckets, a.bcap);
+    bool over = false;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+         b += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = a.bseg[b];
+        const Seg* sg = a.segs + s;
+        const uint64_t start = a.bstart[b];
+        const uint64_t seg_end = sg->start + sg->len;
+        const uint64_t end = (b + 1 < nb && a.bseg[b + 1] == s) ? a.bstart[b + 1] : seg_end;
+        const uint64_t len = end - start;
+        if (len <= a.wsmall) {
+            const uint64_t slot = sg->window_base + (start - sg->start) / a.wsmall;
+            if (slot < a.nslots) {
+                atomicMin(&a.cfirst[slot], (uint32_t)b);
+                atomicMax(&a.clast[slot], (uint32_t)b);
+            } else {
+                over = true;
+            }
+        } else if (len <= a.cap) {
+            const uint32_t m = atomicAdd(a.nmed, 1u);
+            if (m < a.medcap) a.med[m] = (uint32_t)b;
+            else over = true;
+        } else if (sg->lo_bit == 0) {
+            const uint32_t m = atomicAdd(a.ndone, 1u);
+            if (m < a.donecap) a.done[m] = Big{start, (uint32_t)len, 0u};
+            else over = true;
+        } else {
+            const uint32_t m = atomicAdd(a.nbig, 1u);
+            if (m < a.bigcap) a.big[m] = Big{start, (uint32_t)len, (uint32_t)sg->lo_bit};
+            else over = true;
+        }
+    }
+    if (over) atomicOr(a.err, ERR_LIST_CAP);
+}
+
+// ---------------------------------------------------------------------------------
+// Local sort (the diversion of Sec. 3): one chunk of at most CAP records per step of
+// a block-stride loop.  A chunk is a run of consecutive buckets of one segment (or
+// one medium bucket).  Sorting the chunk stably by the pair (bucket index, bits
+// below lo_bit) sorts each bucket stably by its full key and keeps the buckets in
+// order.  Only the bits that vary in the chunk are sorted on (pass skipping at bit
+// granularity, Sec. 2.1), in LSD passes of at most 8 bits, all inside LDS.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t comp_digit(uint64_t key, uint32_t bidx, int h, int lo,
+                                               int width) {
+    const uint32_t mask = (1u << width) - 1u;
+    if (lo + width <= h) return (uint32_t)(key >> lo) & mask;
+    if (lo >= h) return (bidx >> (lo - h)) & mask;
+    const int kb = h - lo;
+    return ((uint32_t)(key >> lo) & ((1u << kb) - 1u)) | ((bidx << kb) & mask);
+}
+
+template <int KB, int VB, int THREADS, int CAP>
+__global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
+    using K = typename uint_of<KB>::type;
+    using V = typename uint_of<VB>::type;
+    constexpr int W = THREADS / 64;
+    constexpr int ITEMS = CAP / THREADS;
+    constexpr int KBITS = 8 * KB;
+    static_assert(CAP % THREADS == 0 && CAP <= 65536, "chunk layout");
+
+    __shared__ K s_keys[CAP];
+    __shared__ V s_vals[VB ? CAP : 1];
+    __shared__ uint16_t s_bidx[CAP];
+    __shared__ uint32_t s_wcnt[W * RADIX];
+    __shared__ uint32_t s_local[RADIX];
+    __shared__ uint32_t s_part[RADIX / 64];
+    __shared__ K s_red[W];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t nb = umin64(*a.nbuckets, a.bcap);
+    const uint32_t nmed = *a.nmed < a.medcap ? *a.nmed : a.medcap;
+    const uint32_t nitems = a.nslots + nmed;
+    const uint32_t wbase = (uint32_t)w * ITEMS * 64;
+    uint32_t* wc = s_wcnt + w * RADIX;
+    uint32_t* s_rel = (uint32_t*)s_keys;  // bucket starts, before records are staged
+
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        uint32_t f, l;
+        if (item < a.nslots) {
+            f = a.cfirst[item];
+            if (f == 0xffffffffu) continue;
+            l = a.clast[item];
+        } else {
+            f = l = a.med[item - a.nslots];
+        }
+        if ((uint64_t)l >= nb || f > l) {
+            if (tid == 0) atomicOr(a.err, ERR_CHUNK);
+            continue;
+        }
+        const uint32_t s = a.bseg[f];
+        const Seg* sg = a.segs + s;
+        const uint64_t start = a.bstart[f];
+        const uint64_t end =
+            ((uint64_t)l + 1 < nb && a.bseg[l + 1] == s) ? a.bstart[l + 1] : sg->start + sg->len;
+        const uint64_t len64 = end - start;
+        if (len64 > CAP || len64 == 0) {
+            if (tid == 0) atomicOr(a.err, ERR_CHUNK);
+            continue;
+        }
+        const uint32_t len = (uint32_t)len64;
+        const uint32_t nbk = l - f + 1;
+        const int lo = sg->lo_bit;
+        const K* kin = (const K*)a.kin + start;
+        const V* vin = (const V*)a.vin + start;
+
+        K key[ITEMS];
+        V val[ITEMS];
+        uint32_t bix[ITEMS];
+        uint32_t rnk[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            const bool ok = idx < len;
+            key[k] = ok ? kin[idx] : K(0);
+            if (VB) val[k] = ok ? vin[idx] : V(0);
+            bix[k] = 0;
+        }
+        // Bucket index of each record inside the chunk.
+        if (nbk > 1) {
+            for (uint32_t i = tid; i < nbk; i += THREADS)
+                s_rel[i] = (uint32_t)(a.bstart[f + i] - start);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
+                while (hi_i - lo_i > 1) {
+                    const uint32_t mid = (lo_i + hi_i) >> 1;
+                    if (s_rel[mid] <= idx) lo_i = mid;
+                    else hi_i = mid;
+                }
+                bix[k] = lo_i;
+            }
+            __syncthreads();
+        }
+        // Bits below lo_bit that vary within the chunk.
+        const K lowmask = lo >= KBITS ? ~K(0) : (K)((K(1) << lo) - K(1));
+        const K key0 = kin[0];
+        K vary = 0;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            if (idx < len) vary |= (key[k] ^ key0) & lowmask;
+        }
+        vary = wave_or(vary);
+        if (lane == 0) s_red[w] = vary;
+        __syncthreads();
+        K all = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) all |= s_red[ww];
+        __syncthreads();
+        int h = 0;
+        while (h < KBITS && (all >> h) != 0) ++h;  // bit width of `all`
+        const int bb = nbk > 1 ? 32 - __clz(nbk - 1) : 0;
+        const int B = h > 0 ? h + bb : 0;
+        const int npass = (B + RADIX_BITS - 1) / RADIX_BITS;
+        const int wd = npass ? (B + npass - 1) / npass : 0;
+
+        for (int p = 0; p < npass; ++p) {
+            const int plo = p * wd;
+            const int pw = wd < B - plo ? wd : B - plo;
+            for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                const bool ok = idx < len;
+                const uint64_t act = __ballot(ok);
+                const uint32_t d = comp_digit((uint64_t)key[k], bix[k], h, plo, pw);
+                const uint64_t m = same_digit_lanes_rt(d, act, pw);
+                const uint32_t below = lanes_below(m);
+                const uint32_t base = wc[d];
+                if (ok && below == 0) wc[d] = base + (uint32_t)__popcll(m);
+                rnk[k] = base + below;
+            }
+            __syncthreads();
+            uint32_t cnt = 0;
+            if (tid < RADIX) {
+                uint32_t run = 0;
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = s_wcnt[ww * RADIX + tid];
+                    s_wcnt[ww * RADIX + tid] = run;
+                    run += c;
+                }
+                cnt = run;
+            }
+            uint32_t total;
+            const uint32_t ex = scan256_excl(cnt, s_part, &total);
+            if (tid < RADIX) s_local[tid] = ex;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                if (idx < len) {
+                    const uint32_t d = comp_digit((uint64_t)key[k], bix[k], h, plo, pw);
+                    const uint32_t q = wc[d] + s_local[d] + rnk[k];
+                    if (q < CAP) {
+                        s_keys[q] = key[k];
+                        if (VB) s_vals[q] = val[k];
+                        s_bidx[q] = (uint16_t)bix[k];
+                    }
+                }
+            }
+            __syncthreads();
+            if (p + 1 < npass) {
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    const uint32_t idx = wbase + k * 64 + lane;
+                    if (idx < len) {
+                        key[k] = s_keys[idx];
+                        if (VB) val[k] = s_vals[idx];
+                        bix[k] = s_bidx[idx];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        K* kout = (K*)a.kout + start;
+        V* vout = (V*)a.vout + start;
+        if (npass > 0) {
+            for (uint32_t i = tid; i < len; i += THREADS) {
+                kout[i] = s_keys[i];
+                if (VB) vout[i] = s_vals[i];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                if (idx < len) {
+                    kout[idx] = key[k];
+                    if (VB) vout[idx] = val[k];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Copy of whole tiles (finished ranges back into the caller's buffers).
+// ---------------------------------------------------------------------------------
+template <int KB, int VB, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_copy_tiles(const void* kin, const void* vin,
+                                                        void* kout, void* vout,
+                                                        const Tile* tiles, uint32_t ntiles) {
+    using K = typename uint_of<KB>::type;
+    using V = typename uint_of<VB>::type;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        const K* ki = (const K*)kin + tl.start;
+        K* ko = (K*)kout + tl.start;
+        for (uint32_t i = threadIdx.x; i < tl.len; i += THREADS) ko[i] = ki[i];
+        if (VB) {
+            const V* vi = (const V*)vin + tl.start;
+            V* vo = (V*)vout + tl.start;
+            for (uint32_t i = threadIdx.x; i < tl.len; i += THREADS) vo[i] = vi[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Tile shapes and launchers.
+// ---------------------------------------------------------------------------------
+constexpr int DEAL_THREADS = 512;
+constexpr int COUNT_THREADS = 256;
+constexpr int LOCAL_THREADS = 512;
+constexpr int COPY_THREADS = 256;
+
+uint32_t deal_tile_records(int kb, int vb) { return kb + vb <= 8 ? 8192u : 4096u; }
+uint32_t local_sort_capacity(int kb, int vb) { return kb + vb <= 8 ? 8192u : 4096u; }
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s) {
+    if (blocks == 0) return hipSuccess;
+    if (kb == 4) hipLaunchKernelGGL((k_count<4, COUNT_THREADS>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_count<8, COUNT_THREADS>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int KB, int VB>
+static void deal_kb_vb(const DealArgs& a, hipStream_t s) {
+    constexpr int ITEMS = (KB + VB <= 8 ? 8192 : 4096) / DEAL_THREADS;
+    hipLaunchKernelGGL((k_deal<KB, VB, DEAL_THREADS, ITEMS>), dim3(a.ntiles), dim3(DEAL_THREADS),
+                       0, s, a);
+}
+
+hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s) {
+    if (a.ntiles == 0) return hipSuccess;
+    if (kb == 4) {
+        if (vb == 0) deal_kb_vb<4, 0>(a, s);
+        else if (vb == 4) deal_kb_vb<4, 4>(a, s);
+        else deal_kb_vb<4, 8>(a, s);
+    } else {
+        if (vb == 0) deal_kb_vb<8, 0>(a, s);
+        else if (vb == 4) deal_kb_vb<8, 4>(a, s);
+        else deal_kb_vb<8, 8>(a, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s) {
+    if (a.ntiles == 0) return hipSuccess;
+    // Tiles are the deal tiles of the level; the head kernel's block covers the
+    // largest of them (8192 records).
+    if (kb == 4) hipLaunchKernelGGL((k_heads<4, DEAL_THREADS, 16>), dim3(a.ntiles), dim3(DEAL_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_heads<8, DEAL_THREADS, 16>), dim3(a.ntiles), dim3(DEAL_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s) {
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int KB, int VB>
+static void local_kb_vb(const LocalArgs& a, uint32_t blocks, hipStream_t s) {
+    constexpr int CAP = KB + VB <= 8 ? 8192 : 4096;
+    hipLaunchKernelGGL((k_local_sort<KB, VB, LOCAL_THREADS, CAP>), dim3(blocks), dim3(LOCAL_THREADS),
+                       0, s, a);
+}
+
+hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks, hipStream_t s) {
+    if (blocks == 0) return hipSuccess;
+    if (kb == 4) {
+        if (vb == 0) local_kb_vb<4, 0>(a, blocks, s);
+        else if (vb == 4) local_kb_vb<4, 4>(a, blocks, s);
+        else local_kb_vb<4, 8>(a, blocks, s);
+    } else {
+        if (vb == 0) local_kb_vb<8, 0>(a, blocks, s);
+        else if (vb == 4) local_kb_vb<8, 4>(a, blocks, s);
+        else local_kb_vb<8, 8>(a, blocks, s);
+    }
+    return hipGetLastError();
+}
+
+template <int KB, int VB>
+static void copy_kb_vb(const void* kin, const void* vin, void* kout, void* vout, const Tile* tiles,
+                       uint32_t ntiles, hipStream_t s) {
+    const uint32_t blocks = std::min(ntiles, 8192u);
+    hipLaunchKernelGGL((k_copy_tiles<KB, VB, COPY_THREADS>), dim3(blocks), dim3(COPY_THREADS), 0, s,
+                       kin, vin, kout, vout, tiles, ntiles);
+}
+
+hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, void* kout,
+                             void* vout, const Tile* tiles, uint32_t ntiles, hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    if (kb == 4) {
+        if (vb == 0) copy_kb_vb<4, 0>(kin, vin, kout, vout, tiles, ntiles, s);
+        else if (vb == 4) copy_kb_vb<4, 4>(kin, vin, kout, vout, tiles, ntiles, s);
+        else copy_kb_vb<4, 8>(kin, vin, kout, vout, tiles, ntiles, s);
+    } else {
+        if (vb == 0) copy_kb_vb<8, 0>(kin, vin, kout, vout, tiles, ntiles, s);
+        else if (vb == 4) copy_kb_vb<8, 4>(kin, vin, kout, vout, tiles, ntiles, s);
+        else copy_kb_vb<8, 8>(kin, vin, kout, vout, tiles, ntiles, s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dfr

@@ -1,0 +1,144 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports every entry
+point that include/dfr.h declares, validates arguments before touching the device, and
+its planner (pure host code) picks the number of top digits as documented."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2207_14334_amd as dfr
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dfr.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(dfr.LIB_PATH):
+        from paper_2207_14334_amd import build
+        build.build()
+    return dfr.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_list():
+    assert declared_functions() == sorted(dfr.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_temp_bytes(L):
+    assert dfr.temp_bytes(0, 4, 0) == 0
+    assert dfr.temp_bytes(1, 4, 0) == 256
+    assert dfr.temp_bytes(1 << 20, 4, 4) == (1 << 23)
+    assert dfr.temp_bytes(1000, 8, 8) == 8192 + 8192
+    assert dfr.temp_bytes(10, 3, 0) == 0  # bad width
+
+
+def test_local_sort_capacity(L):
+    assert dfr.local_sort_capacity(4, 0) == 8192
+    assert dfr.local_sort_capacity(4, 4) == 8192
+    assert dfr.local_sort_capacity(8, 8) == 4096
+    assert dfr.local_sort_capacity(5, 0) == 0
+
+
+def test_status_strings(L):
+    for st in range(-9, 1):
+        assert dfr.status_string(st)
+    assert dfr.status_string(0) == "ok"
+
+
+def test_null_context_and_bad_arguments(L):
+    P = ctypes.c_void_p
+    assert L.dfr_sort_u32(None, P(4096), None, 10, None, 0, None) == dfr.E_INVALID_ARG
+    assert L.dfr_sort_u64(None, None, None, 0, None, 0, None) == dfr.E_INVALID_ARG
+    assert L.dfr_set_option(None, b"timing", 1) == dfr.E_INVALID_ARG
+    assert L.dfr_get_stats(None, None) == dfr.E_INVALID_ARG
+    out = P()
+    assert L.dfr_create(0, 0, None) == dfr.E_INVALID_ARG
+    assert L.dfr_count(None, None, 4, 0, 8, 4, None, None) == dfr.E_INVALID_ARG
+    off = (ctypes.c_uint64 * 3)(0, 5, 3)  # decreasing offsets
+    assert L.dfr_sort_segmented_u32(None, P(4096), None, off, 2, None, 0, None) == dfr.E_INVALID_ARG
+
+
+def test_create_without_gpu_fails_cleanly(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    out = ctypes.c_void_p()
+    assert L.dfr_create(0, 0, ctypes.byref(out)) == dfr.E_HIP
+    assert not out.value
+
+
+# --------------------------------------------------------------------------------------
+# Planner (Sec. 3: estimate the top digits to deal; Sec. 3.1: threshold N_d).
+# --------------------------------------------------------------------------------------
+
+def hist_of(keys, kb):
+    h = np.zeros((kb, 256), dtype=np.uint32)
+    for j in range(kb):
+        d = ((keys >> keys.dtype.type(8 * j)) & keys.dtype.type(255)).astype(np.int64)
+        h[j] = np.bincount(d, minlength=256)
+    return h
+
+
+def uniform_hist(n, kb):
+    return np.full((kb, 256), n // 256, dtype=np.uint32)
+
+
+def test_plan_uniform_u32_2p28(L):
+    # Expected bucket after d top digits: 2^28 / 256^d; N_d = 4096 -> d = 2.
+    d, v = dfr.plan_top_digits(uniform_hist(1 << 28, 4), 1 << 28, 4, 4)
+    assert (d, v) == (2, 4)
+
+
+def test_plan_uniform_u64_2p27(L):
+    # 2^27 / 256^2 = 2048 = N_d for 16-byte records -> d = 2.
+    d, v = dfr.plan_top_digits(uniform_hist(1 << 27, 8), 1 << 27, 8, 8)
+    assert (d, v) == (2, 8)
+
+
+def test_plan_small_input_diverts_at_once(L):
+    d, _ = dfr.plan_top_digits(uniform_hist(8192, 4), 8192, 4, 4)
+    assert d == 0
+
+
+def test_plan_skips_constant_digits(L):
+    k = workloads.make_keys("narrow", 1 << 20, 32, 0, narrow_bits=20)
+    d, v = dfr.plan_top_digits(hist_of(k, 4), k.size, 4, 0)
+    assert v == 3  # bits 20..31 are zero: digit 3 never varies
+    assert 1 <= d <= 3
+
+
+def test_plan_all_equal(L):
+    k = workloads.make_keys("equal", 1 << 16, 64, 0)
+    d, v = dfr.plan_top_digits(hist_of(k, 8), k.size, 8, 8)
+    assert v == 0 and d == 0
+
+
+def test_plan_skewed_prefers_full_lsd(L):
+    # Zipf keys: most records share their top digits, so no short prefix reaches N_d
+    # and dealing every digit moves the fewest bytes.
+    k = workloads.make_keys("zipf", 1 << 20, 32, 0)
+    h = hist_of(k, 4) * 256  # as if n were 2^28 with the same shape
+    d, v = dfr.plan_top_digits(h, 1 << 28, 4, 4)
+    assert d == v == 4
+
+
+def test_plan_divert_option_changes_depth(L):
+    h = uniform_hist(1 << 28, 4)
+    assert dfr.plan_top_digits(h, 1 << 28, 4, 4, divert=64)[0] == 4  # LSD is cheaper
+    assert dfr.plan_top_digits(h, 1 << 28, 4, 4, divert=8192)[0] == 2

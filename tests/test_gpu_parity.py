@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Every result here is integer work with a unique answer (the stable sort), so parity is
+bit-exact.  Each test prints the case it is about to run before the GPU call.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2207_14334_amd as dfr
+    c = dfr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.get()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def gpu_sort(torch, ctx, keys, vals, **opts):
+    for k, v in opts.items():
+        ctx.set_option(k, v)
+    try:
+        dk = dev(torch, keys)
+        dv = dev(torch, vals) if vals is not None else None
+        ctx.sort_(dk, dv)
+        torch.cuda.synchronize()
+        return host(dk), (host(dv) if dv is not None else None), ctx.stats()
+    finally:
+        for k in opts:
+            ctx.set_option(k, 0)
+
+
+def load_golden(name):
+    d = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split(":", 1)
+        d[k.strip()] = [int(x) for x in v.split()]
+    return d
+
+
+# --------------------------------------------------------------------------------------
+# Stages: count and deal (Sec. 2).
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["counting_sort_0_9.txt", "cards_lsd.txt"])
+def test_golden_count_deal(torch, ctx, name):
+    g = load_golden(name)
+    say("golden", name)
+    k = np.array(g["keys"], dtype=np.uint32)
+    v = np.array(g["vals"], dtype=np.uint32)
+    h = host(ctx.count(dev(torch, k), bits=g["bits"][0], num_digits=1))
+    assert list(h[0][:16]) == g["count"]
+    dk, dv = ctx.deal(dev(torch, k), dev(torch, v), shift=g["shift"][0], bits=g["bits"][0])
+    assert list(host(dk)) == g["deal_keys"] and list(host(dv)) == g["deal_vals"]
+    sk, sv, _ = gpu_sort(torch, ctx, k, v)
+    assert list(sk) == g["sorted_keys"] and list(sv) == g["sorted_vals"]
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "equal"])
+def test_count_matches_oracle(torch, ctx, o, kb, dist):
+    n = (1 << 20) + 12345
+    k = workloads.make_keys(dist, n, 8 * kb, 3)
+    say("count", dist, kb, n)
+    h = host(ctx.count(dev(torch, k)))
+    for j in range(kb):
+        assert np.array_equal(h[j].astype(np.uint64), o.count(k, 8 * j, 8)), j
+
+
+@pytest.mark.parametrize("kb,vb", [(4, 0), (4, 4), (8, 8), (8, 0)])
+@pytest.mark.parametrize("shift,bits", [(0, 8), (8, 8), (3, 5), (24, 8), (0, 1)])
+def test_deal_matches_oracle(torch, ctx, o, kb, vb, shift, bits):
+    n = 3 * 8192 + 777  # several tiles and a ragged tail
+    k = workloads.make_keys("zipf", n, 8 * kb, shift + bits)
+    v = workloads.index_payload(n, 8 * vb) if vb else None
+    say("deal", kb, vb, shift, bits, n)
+    dk, dv = ctx.deal(dev(torch, k), dev(torch, v) if vb else None, shift=shift, bits=bits)
+    rk, rv = o.deal(k, v, shift, bits)
+    assert np.array_equal(host(dk), rk)
+    if vb:
+        assert np.array_equal(host(dv), rv)
+
+
+# --------------------------------------------------------------------------------------
+# Whole sort against the oracle.
+# --------------------------------------------------------------------------------------
+
+SIZES = [0, 1, 2, 3, 63, 64, 65, 1000, 4095, 4096, 4097, 8191, 8192, 8193, 20000, 65543,
+         (1 << 20) + 3]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kb,vb", [(4, 4), (8, 8), (4, 0)])
+def test_sort_sizes(torch, ctx, o, n, kb, vb):
+    k = workloads.make_keys("uniform", n, 8 * kb, n)
+    v = workloads.index_payload(n, 8 * vb) if vb else None
+    say("sort", n, kb, vb)
+    sk, sv, _ = gpu_sort(torch, ctx, k, v)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk)
+    if vb:
+        assert np.array_equal(sv, rv)
+
+
+DISTS32 = ["uniform", "normal", "zipf", "sorted", "reverse", "few", "equal", "narrow"]
+
+
+@pytest.mark.parametrize("dist", DISTS32)
+@pytest.mark.parametrize("n", [1 << 18, (1 << 22) + 5])
+def test_sort_distributions_u32(torch, ctx, o, dist, n):
+    k = workloads.make_keys(dist, n, 32, 1)
+    v = workloads.index_payload(n)
+    say("sort32", dist, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+
+
+@pytest.mark.parametrize("dist", ["uniform", "skewed", "normal", "zipf", "few", "equal"])
+def test_sort_distributions_u64(torch, ctx, o, dist):
+    n = (1 << 21) + 17
+    k = workloads.make_keys(dist, n, 64, 2)
+    v = workloads.index_payload(n, 64)
+    say("sort64", dist, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("dist", ["uniform", "normal", "few"])
+def test_forced_top_digits(torch, ctx, o, d, dist):
+    """Every choice of d gives the same result; small d forces recursion on large buckets."""
+    n = (1 << 21) + 99
+    k = workloads.make_keys(dist, n, 32, d)
+    v = workloads.index_payload(n)
+    say("force_d", d, dist, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, force_top_digits=d)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    if d == 1 and dist == "uniform":
+        assert st["levels"] >= 2 and st["large_buckets"] > 0, st
+
+
+@pytest.mark.parametrize("divert", [16, 512, 8192])
+def test_divert_threshold(torch, ctx, o, divert):
+    n = (1 << 21) + 1
+    k = workloads.make_keys("uniform", n, 32, 5)
+    v = workloads.index_payload(n)
+    say("divert", divert)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, divert_records=divert)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+
+
+def test_deterministic_repeats(torch, ctx, o):
+    n = (1 << 22) + 11
+    k = workloads.make_keys("few", n, 32, 9)
+    v = workloads.index_payload(n)
+    say("repeat", n)
+    first = None
+    for _ in range(5):
+        sk, sv, _ = gpu_sort(torch, ctx, k, v)
+        if first is None:
+            first = (sk, sv)
+        assert np.array_equal(sk, first[0]) and np.array_equal(sv, first[1])
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(first[0], rk) and np.array_equal(first[1], rv)
+
+
+# --------------------------------------------------------------------------------------
+# Segmented sort.
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+@pytest.mark.parametrize("kb", [4, 8])
+def test_segmented(torch, ctx, o, dist, kb):
+    lens = workloads.batch_lengths(400, 1, 40000, 7)
+    lens[3] = 0
+    lens[10] = 1
+    lens[11] = 9000
+    off = workloads.segment_offsets(lens)
+    n = int(off[-1])
+    k = workloads.make_keys(dist, n, 8 * kb, 4)
+    v = workloads.index_payload(n, 8 * kb)
+    say("segmented", dist, kb, n, lens.size)
+    dk, dv = dev(torch, k), dev(torch, v)
+    ctx.sort_segmented_(dk, dv, off)
+    torch.cuda.synchronize()
+    rk, rv = o.segmented_sort(k, v, off)
+    assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv)
+
+
+# --------------------------------------------------------------------------------------
+# Argument errors leave the buffers untouched.
+# --------------------------------------------------------------------------------------
+
+def test_argument_errors(torch, ctx):
+    import paper_2207_14334_amd as dfr
+    k = dev(torch, np.arange(100, 0, -1, dtype=np.uint32))
+    small = torch.empty(10, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dfr.DfrError) as e:
+        ctx.sort_(k, None, temp=small)
+    assert e.value.status == dfr.E_INVALID_ARG
+    assert host(k)[0] == 100
+    with pytest.raises(dfr.DfrError) as e:
+        ctx.sort_(k, k)  # keys and vals overlap
+    assert e.value.status == dfr.E_INVALID_ARG
+    with pytest.raises(dfr.DfrError) as e:
+        ctx.set_option("no_such_option", 1)
+    assert e.value.status == dfr.E_UNSUPPORTED
