@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the DFR sort hot path on one MI355X.
+
+One step = one plain DFR sort (count, deals of the top digits, bucket finding, local
+sort of runs of small buckets, recursion if any) of 2^28 uint32 keys drawn i.i.d.
+uniform over [0, 2^32) with a uint32 index payload, seed 0.  Every step sorts its own
+copy of that input, made resident in HBM before the timed region starts, so the timed
+region holds nothing but the sorts.
+
+Printed: ONE JSON line with the throughput (Gkeys/s), the roofline of the dominant
+kernel (the deal pass) from HIP events recorded around its launches during the timed
+region, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gkeys/s at 2^28 u32 & % HBM peak; batched/serving p99 vs plain calls"
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "deal_u32x32_2p28_uniform_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2207_14334_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def counter_traffic():
+    """Per-launch HBM bytes of the deal kernel from the committed rocprofv3 counter
+    summary, or None if that summary is missing or was taken on other kernel source."""
+    try:
+        text = open(PROFILE_COUNTERS).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernels\.hip sha256:\s*([0-9a-f]{64})", text)
+    m_bytes = re.search(r"traffic bytes per launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def check_result(keys_in, keys_out, vals_out):
+    """Stable-sort properties under the index payload (numpy, no oracle)."""
+    import numpy as np
+    n = keys_in.size
+    if not (keys_out[1:] >= keys_out[:-1]).all():
+        return "keys not sorted"
+    if np.bincount(vals_out.astype(np.int64), minlength=n).max() != 1:
+        return "payload is not a permutation"
+    if not np.array_equal(keys_in[vals_out], keys_out):
+        return "key/payload mismatch"
+    eq = keys_out[1:] == keys_out[:-1]
+    if not (vals_out[1:][eq] > vals_out[:-1][eq]).all():
+        return "equal keys out of input order"
+    return "pass"
+
+
+def cpu_baseline(dist, log2n_sample=24, seeds=(0, 1, 2)):
+    """The CPU oracle (single-threaded C stable sort) on a bounded sample."""
+    import oracle
+    import workloads
+    o = oracle.get()
+    total_keys, total_s = 0, 0.0
+    for seed in seeds:
+        k = workloads.make_keys(dist, 1 << log2n_sample, 32, seed)
+        v = workloads.index_payload(k.size)
+        t0 = time.perf_counter()
+        o.stable_sort(k, v)
+        total_s += time.perf_counter() - t0
+        total_keys += k.size
+    return {
+        "value": round(total_keys / total_s / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+        "kind": "oracle",
+        "sample": f"{len(seeds)} x 2^{log2n_sample} {dist} uint32 keys with uint32 index "
+                  f"payload (seeds {list(seeds)}), single-threaded, {total_s:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--dist", default="uniform")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the sort's "
+                                   "multi-GPU path is not built (see DESIGN.md)"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2207_14334_amd as dfr
+    import workloads
+
+    torch.cuda.set_device(0)
+    n = 1 << args.log2n
+    log(f"generating {n} {args.dist} keys")
+    keys_h = workloads.make_keys(args.dist, n, 32, 0)
+    vals_h = workloads.index_payload(n)
+    base_k = torch.from_numpy(keys_h).cuda()
+    base_v = torch.from_numpy(vals_h).cuda()
+    copies = args.warmup + args.steps
+    ks = [torch.empty_like(base_k) for _ in range(copies)]
+    vs = [torch.empty_like(base_v) for _ in range(copies)]
+    for i in range(copies):
+        ks[i].copy_(base_k)
+        vs[i].copy_(base_v)
+    temp = torch.empty(dfr.temp_bytes(n, 4, 4), dtype=torch.uint8, device="cuda")
+    ctx = dfr.Context(0)
+    torch.cuda.synchronize()
+    log(f"{copies} resident copies ready")
+
+    for i in range(args.warmup):
+        ctx.sort_(ks[i], vs[i], temp)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    ctx.set_option("timing", 1)
+    agg = {"ms_deal": 0.0, "deal_launches_timed": 0, "ms_count": 0.0, "ms_buckets": 0.0,
+           "ms_local_sort": 0.0, "ms_other": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = None
+    for i in range(args.warmup, copies):
+        ctx.sort_(ks[i], vs[i], temp)
+        st = ctx.stats()
+        for k in agg:
+            agg[k] += st[k]
+        plan = st
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_option("timing", 0)
+    elapsed = t1 - t0
+    ms_step = elapsed / args.steps * 1e3
+    gkeys = n * args.steps / elapsed / 1e9
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {gkeys:.2f} Gkeys/s")
+
+    parity = check_result(keys_h, ks[-1].cpu().numpy(), vs[-1].cpu().numpy())
+    log(f"result check: {parity}")
+
+    rec_bytes = 4 + 4
+    deal_bytes = 2 * rec_bytes * n  # read + write of key and payload, one pass
+    deal_ms = agg["ms_deal"] / max(agg["deal_launches_timed"], 1)
+    deal_gbs = deal_bytes / (deal_ms * 1e-3) / 1e9
+    traffic = counter_traffic()
+    # Algorithmic bytes of the whole sort: count (kb/key), d deals (2(kb+vb)/key),
+    # bucket heads (kb/key), local sort (2(kb+vb)/key).
+    d = plan["top_digits"] if plan else 0
+    sort_bytes = n * (4 + d * 2 * rec_bytes + (4 + 2 * rec_bytes if plan and plan["used_diversion"] else 0))
+    hbm_frac_sort = sort_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.dist)
+
+    out = {
+        "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"plain DFR sort of 2^{args.log2n} uint32 keys, i.i.d. "
+                               f"{args.dist}, uint32 index payload, seed 0",
+                   "n": n, "key_bits": 32, "payload_bits": 32, "distribution": args.dist,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_deal<4,4,512,16>",
+                     "achieved": round(deal_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(deal_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": deal_bytes,
+                     "avg_launch_ms": round(deal_ms, 4),
+                     "launches": agg["deal_launches_timed"]},
+        "cpu_baseline": cpu,
+        "hbm_frac_sort": round(hbm_frac_sort, 4),
+        "plan": {"top_digits": d, "levels": plan["levels"] if plan else 0,
+                 "deal_passes": plan["deal_passes"] if plan else 0,
+                 "large_buckets": plan["large_buckets"] if plan else 0},
+        "stage_ms_per_step": {k: round(v / args.steps, 4) for k, v in agg.items()
+                              if k.startswith("ms_")},
+        "result_check": parity,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    if parity != "pass":
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -244,7 +244,10 @@ void collect_events(dfr_ctx* c) {
 
 size_t local_cap(int kb, int vb) { return local_sort_capacity(kb, vb); }
 
-size_t default_divert(int kb, int vb) { return local_cap(kb, vb) / 2; }
+// Default N_d: three quarters of the local sort's capacity.  A bucket whose expected
+// size is N_d has a standard deviation near sqrt(N_d), so its largest siblings stay
+// well inside the capacity and few buckets recurse.
+size_t default_divert(int kb, int vb) { return local_cap(kb, vb) * 3 / 4; }
 
 // ---------------------------------------------------------------------------------
 // Planner (Sec. 3: estimate the number of most significant digits to deal so that
@@ -375,22 +378,18 @@ dfr_status copy_back(Job& j, const std::vector<std::pair<uint64_t, uint64_t>>& r
 }
 
 // Buckets are known on the host (segments no larger than the local sort's capacity):
-// classify and local-sort them straight away.  Each segment is one bucket.
+// each segment is one bucket and one local-sort chunk of its own.
 dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     dfr_ctx* c = j.c;
     const size_t S = segs.size();
     std::vector<Seg> hs(S);
     std::vector<uint64_t> bstart;
     std::vector<uint32_t> bseg;
-    uint64_t nslots = 0, medcap = 0;
     for (size_t i = 0; i < S; ++i) {
         Seg g{};
         g.start = segs[i].start;
         g.len = segs[i].len;
-        g.window_base = (uint32_t)nslots;
         g.lo_bit = segs[i].hi_bit;
-        nslots += (segs[i].len + j.wsmall - 1) / j.wsmall;
-        medcap += segs[i].len / (j.wsmall + 1);
         hs[i] = g;
         if (segs[i].len) {
             bstart.push_back(segs[i].start);
@@ -399,55 +398,26 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     }
     const uint64_t nb = bstart.size();
     if (nb == 0) return DFR_OK;
-    const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + asize<uint32_t>(nb) +
-                        2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) + asize<uint32_t>(8) +
-                        asize<Big>(1) * 2;
+    std::vector<uint32_t> med(nb);
+    for (uint64_t i = 0; i < nb; ++i) med[i] = (uint32_t)i;
+    uint32_t counts3[3] = {(uint32_t)nb, (uint32_t)nb, 0};  // buckets, medium chunks, spills
+    const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + 3 * asize<uint32_t>(nb) +
+                        asize<uint32_t>(3) + asize<uint32_t>(1);
     dfr_status st = arena_reserve(c, need, j.s);
     if (st) return st;
     Seg* dsegs = aalloc<Seg>(c, S);
     uint64_t* dbstart = aalloc<uint64_t>(c, nb);
     uint32_t* dbseg = aalloc<uint32_t>(c, nb);
-    uint32_t* cfirst = aalloc<uint32_t>(c, nslots);
-    uint32_t* clast = aalloc<uint32_t>(c, nslots);
-    uint32_t* med = aalloc<uint32_t>(c, medcap);
-    uint32_t* counters = aalloc<uint32_t>(c, 8);  // nbuckets, nmed, nbig, ndone
-    Big* big = aalloc<Big>(c, 1);
-    Big* done = aalloc<Big>(c, 1);
-    uint32_t nb32 = (uint32_t)nb;
+    uint32_t* dmed = aalloc<uint32_t>(c, nb);
+    uint32_t* dspill = aalloc<uint32_t>(c, nb);
+    uint32_t* dcounts = aalloc<uint32_t>(c, 3);
+    uint32_t* dnone = aalloc<uint32_t>(c, 1);
     st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
     if (!st) st = upload(j, dbstart, bstart.data(), nb * sizeof(uint64_t));
     if (!st) st = upload(j, dbseg, bseg.data(), nb * sizeof(uint32_t));
+    if (!st) st = upload(j, dmed, med.data(), nb * sizeof(uint32_t));
+    if (!st) st = upload(j, dcounts, counts3, sizeof counts3);
     if (st) return st;
-    {
-        Timed tm(c, j.s, ST_BUCKETS);
-        HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
-        st = upload(j, counters, &nb32, sizeof nb32);
-        if (st) return st;
-        HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
-        HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
-        ClassifyArgs ca{};
-        ca.bstart = dbstart;
-        ca.bseg = dbseg;
-        ca.nbuckets = counters;
-        ca.bcap = nb;
-        ca.segs = dsegs;
-        ca.wsmall = (uint32_t)j.wsmall;
-        ca.cap = (uint32_t)j.cap;
-        ca.cfirst = cfirst;
-        ca.clast = clast;
-        ca.nslots = (uint32_t)nslots;
-        ca.med = med;
-        ca.nmed = counters + 1;
-        ca.medcap = (uint32_t)medcap;
-        ca.big = big;
-        ca.nbig = counters + 2;
-        ca.bigcap = 0;
-        ca.done = done;
-        ca.ndone = counters + 3;
-        ca.donecap = 0;
-        ca.err = j.err_dev;
-        HIP_TRY(c, launch_classify(ca, (uint32_t)std::min<uint64_t>((nb + 255) / 256, 4096), j.s));
-    }
     {
         Timed tm(c, j.s, ST_LOCAL);
         LocalArgs la{};
@@ -457,17 +427,20 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         la.vout = j.v[0];
         la.bstart = dbstart;
         la.bseg = dbseg;
-        la.nbuckets = counters;
+        la.nbuckets = dcounts;
         la.bcap = nb;
         la.segs = dsegs;
-        la.cfirst = cfirst;
-        la.clast = clast;
-        la.nslots = (uint32_t)nslots;
-        la.med = med;
-        la.nmed = counters + 1;
-        la.medcap = (uint32_t)medcap;
+        la.cfirst = dnone;
+        la.clast = dnone;
+        la.nslots = 0;
+        la.med = dmed;
+        la.nmed = dcounts + 1;
+        la.medcap = (uint32_t)nb;
+        la.spill = dspill;
+        la.nspill = dcounts + 2;
+        la.spillcap = (uint32_t)nb;
         la.err = j.err_dev;
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 4096);
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nb, 8192);
         HIP_TRY(c, launch_local_sort(j.kb, j.vb, la, blocks, j.s));
         c->stats.chunks += nb;
     }
@@ -625,7 +598,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const size_t need_b = asize<Tile>(ntiles) + asize<Seg>(S) + asize<uint32_t>(ntiles * RADIX + 1) +
                           asize<uint64_t>(ntiles + 1) + asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
-                          2 * asize<Big>(bigcap) + asize<uint32_t>(8);
+                          2 * asize<Big>(bigcap) + asize<uint32_t>(nslots + medcap) +
+                          asize<uint32_t>(8);
     st = arena_need(c, need_b, j.s);  // keeps region A
     if (st) return st;
     dhist = (uint32_t*)(c->arena + off_hist);
@@ -640,15 +614,16 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* med = aalloc<uint32_t>(c, medcap);
     Big* big = aalloc<Big>(c, bigcap);
     Big* done = aalloc<Big>(c, bigcap);
-    uint32_t* counters = aalloc<uint32_t>(c, 8);
+    uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
+    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill
     st = upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
     if (st) return st;
 
     int cur = in;
     for (int p = 0; p < d; ++p) {
-        Timed tm(c, j.s, ST_DEAL, true);
         HIP_TRY(c, launch_fill_u32(lb, 0, ntiles * RADIX + 1, j.s));
+        Timed tm(c, j.s, ST_DEAL, true);
         DealArgs da{};
         da.kin = j.k[cur];
         da.vin = j.v[cur];
@@ -708,6 +683,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ca.segs = dsegs;
         ca.wsmall = (uint32_t)j.wsmall;
         ca.cap = (uint32_t)j.cap;
+        ca.kbits = 8 * kb;
         ca.cfirst = cfirst;
         ca.clast = clast;
         ca.nslots = (uint32_t)nslots;
@@ -742,8 +718,11 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         la.med = med;
         la.nmed = counters + 1;
         la.medcap = (uint32_t)medcap;
+        la.spill = spill;
+        la.nspill = counters + 4;
+        la.spillcap = (uint32_t)(nslots + medcap);
         la.err = j.err_dev;
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 4096);
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 8192);
         HIP_TRY(c, launch_local_sort(kb, j.vb, la, blocks, j.s));
     }
     c->stats.used_diversion = 1;
@@ -803,7 +782,7 @@ dfr_status run_sort(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const st
     j.s = s;
     j.tile = deal_tile_records(kb, vb);
     j.cap = local_cap(kb, vb);
-    j.wsmall = j.cap / 2;
+    j.wsmall = j.cap / 4;
     j.divert = c->divert ? std::min(c->divert, j.cap) : default_divert(kb, vb);
     j.top_d_forced = c->force_d;
     uint64_t n = 0;

@@ -109,6 +109,7 @@ struct ClassifyArgs {
     const Seg* segs;
     uint32_t wsmall;  // largest "small" bucket, also the window width
     uint32_t cap;     // local sort capacity
+    int32_t kbits;    // key bits
     uint32_t* cfirst;
     uint32_t* clast;
     uint32_t nslots;
@@ -140,6 +141,10 @@ struct LocalArgs {
     const uint32_t* med;
     const uint32_t* nmed;
     uint32_t medcap;
+    uint32_t* spill;    // chunks the packed local sort hands to the general one
+    uint32_t* nspill;   // zero before the launch
+    uint32_t spillcap;
+    int32_t spill_only; // set by the launcher
     uint32_t* err;
 };
 

@@ -45,30 +45,34 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 
 // Lanes of the wave (within `active`) whose digit equals this lane's, from one ballot
 // per digit bit.  Lane order is input order, so lanes_below() of the result is this
-// record's stable rank among equal digits in the wave.
+// record's stable rank among equal digits in the wave.  Per bit: the bit as 0 / ~0,
+// its ballot, and the lanes whose bit differs (ballot XOR own bit) folded into a
+// mismatch mask.
 template <int BITS>
 __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t active) {
-    uint64_t m = active;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-        const bool on = (d >> b) & 1u;
-        const uint64_t bal = __ballot(on);
-        m &= on ? bal : ~bal;
+        const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+        const uint64_t bal = __ballot(m != 0);
+        lo |= (uint32_t)bal ^ m;
+        hi |= (uint32_t)(bal >> 32) ^ m;
     }
-    return m;
+    return active & ~(((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ uint64_t same_digit_lanes_rt(uint32_t d, uint64_t active, int bits) {
-    uint64_t m = active;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int b = 0; b < RADIX_BITS; ++b) {
         if (b < bits) {
-            const bool on = (d >> b) & 1u;
-            const uint64_t bal = __ballot(on);
-            m &= on ? bal : ~bal;
+            const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+            const uint64_t bal = __ballot(m != 0);
+            lo |= (uint32_t)bal ^ m;
+            hi |= (uint32_t)(bal >> 32) ^ m;
         }
     }
-    return m;
+    return active & ~(((uint64_t)hi << 32) | lo);
 }
 
 // Spin (bounded) until a look-back word carries a status.
@@ -154,15 +158,19 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
 
 // ---------------------------------------------------------------------------------
 // Count (Sec. 2): per-segment digit histograms of up to MAX_PASSES digits, in one read.
-// Each wave keeps private LDS bins; the lanes that share the first active lane's digit
-// add their number in one LDS atomic (this absorbs skewed inputs where most keys
-// share a digit), the other lanes add one each.
+// Keys arrive in 16-byte vector loads, all of a thread's share of a tile in flight at
+// once.  Each wave keeps private LDS bins.  A digit on which a wave's first keys mostly
+// agree (a skewed input) is added per group of equal lanes -- the lanes that share the
+// first active lane's digit add their number in one LDS atomic -- and otherwise one
+// atomic per key.
 // ---------------------------------------------------------------------------------
 template <int KB, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     using K = typename uint_of<KB>::type;
     constexpr int W = THREADS / 64;
     constexpr int SLICE = MAX_PASSES * RADIX;
+    constexpr int PER_VEC = 16 / KB;  // keys per 16-byte load
+    constexpr int VECS = 8;           // 16-byte loads in flight per thread
     __shared__ uint32_t s_h[W * SLICE];
     __shared__ K s_or[W];
     __shared__ K s_and[W];
@@ -184,13 +192,13 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     auto flush = [&](uint32_t seg) {
         __syncthreads();
         for (int idx = tid; idx < ndig * RADIX; idx += THREADS) {
-            uint32_t s = 0;
+            uint32_t sum = 0;
 #pragma unroll
             for (int ww = 0; ww < W; ++ww) {
-                s += s_h[ww * SLICE + idx];
+                sum += s_h[ww * SLICE + idx];
                 s_h[ww * SLICE + idx] = 0;
             }
-            if (s) atomicAdd(&a.hist[(size_t)seg * ndig * RADIX + idx], s);
+            if (sum) atomicAdd(&a.hist[(size_t)seg * ndig * RADIX + idx], sum);
         }
         const K o = wave_or(vor), n = wave_and(vand);
         if (lane == 0) {
@@ -210,6 +218,26 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
         __syncthreads();
     };
 
+    // One key into the wave's bins; `skew` marks digits added per group of lanes.
+    auto add_key = [&](K key, uint32_t skew) {
+        vor |= key;
+        vand &= key;
+        for (int j = 0; j < ndig; ++j) {
+            const uint32_t d = (uint32_t)(key >> (base + j * bits)) & dmask;
+            if ((skew >> j) & 1u) {
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                const uint64_t m0 = __ballot(d == d0);
+                if (d == d0) {
+                    if (lanes_below(m0) == 0) atomicAdd(&hw[j * RADIX + d0], (uint32_t)__popcll(m0));
+                } else {
+                    atomicAdd(&hw[j * RADIX + d], 1u);
+                }
+            } else {
+                atomicAdd(&hw[j * RADIX + d], 1u);
+            }
+        }
+    };
+
     for (uint32_t t = t0; t < t1; ++t) {
         const Tile tl = a.tiles[t];
         if (tl.seg != cur) {
@@ -219,30 +247,45 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
             vand = ~K(0);
         }
         const K* kp = (const K*)a.keys + tl.start;
-        constexpr int U = 4;
-        for (uint32_t i0 = 0; i0 < tl.len; i0 += THREADS * U) {
-            K kk[U];
-            bool ok[U];
+        // Unaligned head, 16-byte aligned body, tail.
+        uint32_t head = (uint32_t)(((16u - ((uintptr_t)kp & 15u)) & 15u) / KB);
+        if (head > tl.len) head = tl.len;
+        const uint32_t nvec = (tl.len - head) / PER_VEC;
+        const uint32_t tail = head + nvec * PER_VEC;
+        for (uint32_t i = tid; i < head; i += THREADS) add_key(kp[i], 0u);
+        for (uint32_t i = tail + tid; i < tl.len; i += THREADS) add_key(kp[i], 0u);
+        const uint4* vp = (const uint4*)(kp + head);
+        for (uint32_t v0 = 0; v0 < nvec; v0 += THREADS * VECS) {
+            uint4 buf[VECS];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t i = i0 + u * THREADS + tid;
-                ok[u] = i < tl.len;
-                kk[u] = ok[u] ? kp[i] : K(0);
+            for (int r = 0; r < VECS; ++r) {
+                const uint32_t v = v0 + r * THREADS + tid;
+                buf[r] = v < nvec ? vp[v] : make_uint4(0, 0, 0, 0);
+            }
+            // Skew test on each wave's first vector: digits on which more than a quarter
+            // of the lanes share the first lane's value.
+            uint32_t skew = 0;
+            {
+                const K k0 = (K)buf[0].x | (KB == 8 ? ((K)buf[0].y << (8 * KB / 2)) : K(0));
+                const bool ok0 = v0 + tid < nvec;
+                for (int j = 0; j < ndig; ++j) {
+                    const uint32_t d = (uint32_t)(k0 >> (base + j * bits)) & dmask;
+                    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                    if (__popcll(__ballot(ok0 && d == d0)) > 16) skew |= 1u << j;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (!ok[u]) continue;
-                vor |= kk[u];
-                vand &= kk[u];
-                for (int j = 0; j < ndig; ++j) {
-                    const uint32_t d = (uint32_t)(kk[u] >> (base + j * bits)) & dmask;
-                    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                    const uint64_t m0 = __ballot(d == d0);
-                    if (d == d0) {
-                        if (lanes_below(m0) == 0)
-                            atomicAdd(&hw[j * RADIX + d0], (uint32_t)__popcll(m0));
+            for (int r = 0; r < VECS; ++r) {
+                const uint32_t v = v0 + r * THREADS + tid;
+                if (v < nvec) {
+                    if (KB == 4) {
+                        add_key((K)buf[r].x, skew);
+                        add_key((K)buf[r].y, skew);
+                        add_key((K)buf[r].z, skew);
+                        add_key((K)buf[r].w, skew);
                     } else {
-                        atomicAdd(&hw[j * RADIX + d], 1u);
+                        add_key((K)buf[r].x | ((K)buf[r].y << 32), skew);
+                        add_key((K)buf[r].z | ((K)buf[r].w << 32), skew);
                     }
                 }
             }
@@ -417,26 +460,36 @@ __global__ __launch_bounds__(THREADS) void k_heads(HeadArgs a) {
     const Seg* sg = a.segs + tl.seg;
     const int lo = sg->lo_bit;
     const uint64_t seg_start = sg->start;
-    const K* kp = (const K*)a.keys;
+    const K* kp = (const K*)a.keys + tl.start;
     const uint32_t len = tl.len;
+    const uint32_t wbase = (uint32_t)w * ITEMS * 64;
+
+    // All loads first; a record's predecessor comes from the lane (or item) before.
+    K key[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        key[k] = idx < len ? kp[idx] : K(0);
+    }
+    const uint64_t gpos0 = tl.start + wbase;  // position of the wave's first record
+    K before = 0;
+    if (lane == 0 && wbase < len && gpos0 > seg_start) before = kp[(int64_t)wbase - 1];
 
     uint32_t off[ITEMS];
     bool head[ITEMS];
     uint32_t run = 0;
-    const uint32_t wbase = (uint32_t)w * ITEMS * 64;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t idx = wbase + k * 64 + lane;
         const bool ok = idx < len;
+        const K up = __shfl_up(key[k], 1, 64);
+        const K last = k > 0 ? __shfl(key[k > 0 ? k - 1 : 0], 63, 64) : before;
+        const K prev = lane == 0 ? last : up;
         const uint64_t gpos = tl.start + idx;
         bool h = false;
         if (ok) {
-            if (gpos == seg_start || lo >= KBITS) {
-                h = gpos == seg_start;
-            } else {
-                const K cur = kp[gpos], prev = kp[gpos - 1];
-                h = (cur >> lo) != (prev >> lo);
-            }
+            if (gpos == seg_start) h = true;
+            else if (lo < KBITS) h = (key[k] >> lo) != (prev >> lo);
         }
         head[k] = h;
         const uint64_t hb = __ballot(h);
@@ -445,28 +498,52 @@ __global__ __launch_bounds__(THREADS) void k_heads(HeadArgs a) {
     }
     if (lane == 0) s_wtot[w] = run;
     __syncthreads();
-    if (tid == 0) {
+    if (w == 0) {
+        // Wave 0 publishes the tile's count, then looks back 64 tiles per step: lane i
+        // reads tile j - i; the walk ends at the newest inclusive prefix once every
+        // word up to it is published.
         uint32_t tot = 0;
         for (int ww = 0; ww < W; ++ww) tot += s_wtot[ww];
-        __hip_atomic_store(&a.lookback[t], (t == 0 ? LB64_PRE : LB64_AGG) | (uint64_t)tot,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0)
+            __hip_atomic_store(&a.lookback[t], (t == 0 ? LB64_PRE : LB64_AGG) | (uint64_t)tot,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t excl = 0;
-        if (t != 0) {
-            uint32_t j = t - 1;
-            for (;;) {
-                const uint64_t x = wait_published64(&a.lookback[j], a.err);
-                excl += x & LB64_COUNT;
-                if ((x & LB64_PRE) || j == 0) break;
-                --j;
+        int64_t j = (int64_t)t - 1;
+        uint32_t spins = 0;
+        while (j >= 0) {
+            const int64_t jj = j - lane;
+            const uint64_t x = jj >= 0 ? __hip_atomic_load(&a.lookback[jj], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : LB64_PRE;
+            const uint64_t pre = __ballot((x & LB64_PRE) != 0);
+            const int stop = pre ? (int)__builtin_ctzll(pre) : 63;  // last lane to take
+            const uint64_t upto = stop == 63 ? ~0ull : ((2ull << stop) - 1);
+            const uint64_t unready = __ballot((x & (LB64_AGG | LB64_PRE)) == 0) & upto;
+            if (unready) {
+                if (++spins > SPIN_LIMIT) {
+                    if (lane == 0) atomicOr(a.err, ERR_SPIN);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                continue;
             }
-            __hip_atomic_store(&a.lookback[t], LB64_PRE | (excl + tot), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t c = ((uint64_t)lane <= (uint64_t)stop) ? (x & LB64_COUNT) : 0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+            excl += c;
+            if (pre) break;
+            j -= 64;
         }
-        if (t == a.ntiles - 1) {
-            const uint64_t nbk = excl + tot;
-            *a.nbuckets = nbk > 0xffffffffull ? 0xffffffffu : (uint32_t)nbk;
+        if (lane == 0) {
+            if (t != 0)
+                __hip_atomic_store(&a.lookback[t], LB64_PRE | (excl + tot), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (t == a.ntiles - 1) {
+                const uint64_t nbk = excl + tot;
+                *a.nbuckets = nbk > 0xffffffffull ? 0xffffffffu : (uint32_t)nbk;
+            }
+            s_excl = excl;
         }
-        s_excl = excl;
     }
     __syncthreads();
     uint64_t wexcl = s_excl;
@@ -489,9 +566,10 @@ __global__ __launch_bounds__(THREADS) void k_heads(HeadArgs a) {
 
 // ---------------------------------------------------------------------------------
 // Classify buckets (Sec. 3: runs of small buckets are sorted in bulk, large buckets
-// recursively).  Window width = wsmall: the small buckets starting in one window of
-// a segment are contiguous and span at most 2*wsmall = cap records, so each window's
-// run is one local-sort chunk.
+// recursively).  Window width = wsmall <= cap/2: the small buckets starting in one
+// window of a segment are contiguous (a bucket longer than wsmall is the last to start
+// in its window) and span at most 2*wsmall records, so each window's run is one
+// local-sort chunk.
 // ---------------------------------------------------------------------------------
 __global__ void k_classify(ClassifyArgs a) {
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
@@ -504,7 +582,13 @@ __global__ void k_classify(ClassifyArgs a) {
         const uint64_t seg_end = sg->start + sg->len;
         const uint64_t end = (b + 1 < nb && a.bseg[b + 1] == s) ? a.bstart[b + 1] : seg_end;
         const uint64_t len = end - start;
-        if (len <= a.wsmall) {
+        if (len <= a.cap && (len > a.wsmall || sg->lo_bit >= a.kbits)) {
+            // Medium bucket, or a bucket with no prefix bits to tell it from its
+            // neighbours (a whole caller segment): a chunk of its own.
+            const uint32_t m = atomicAdd(a.nmed, 1u);
+            if (m < a.medcap) a.med[m] = (uint32_t)b;
+            else over = true;
+        } else if (len <= a.wsmall) {
             const uint64_t slot = sg->window_base + (start - sg->start) / a.wsmall;
             if (slot < a.nslots) {
                 atomicMin(&a.cfirst[slot], (uint32_t)b);
@@ -512,10 +596,6 @@ __global__ void k_classify(ClassifyArgs a) {
             } else {
                 over = true;
             }
-        } else if (len <= a.cap) {
-            const uint32_t m = atomicAdd(a.nmed, 1u);
-            if (m < a.medcap) a.med[m] = (uint32_t)b;
-            else over = true;
         } else if (sg->lo_bit == 0) {
             const uint32_t m = atomicAdd(a.ndone, 1u);
             if (m < a.donecap) a.done[m] = Big{start, (uint32_t)len, 0u};
@@ -529,115 +609,132 @@ __global__ void k_classify(ClassifyArgs a) {
     if (over) atomicOr(a.err, ERR_LIST_CAP);
 }
 
-// ---------------------------------------------------------------------------------
-// Local sort (the diversion of Sec. 3): one chunk of at most CAP records per step of
-// a block-stride loop.  A chunk is a run of consecutive buckets of one segment (or
-// one medium bucket).  Sorting the chunk stably by the pair (bucket index, bits
-// below lo_bit) sorts each bucket stably by its full key and keeps the buckets in
-// order.  Only the bits that vary in the chunk are sorted on (pass skipping at bit
-// granularity, Sec. 2.1), in LSD passes of at most 8 bits, all inside LDS.
-// ---------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t comp_digit(uint64_t key, uint32_t bidx, int h, int lo,
-                                               int width) {
-    const uint32_t mask = (1u << width) - 1u;
-    if (lo + width <= h) return (uint32_t)(key >> lo) & mask;
-    if (lo >= h) return (bidx >> (lo - h)) & mask;
-    const int kb = h - lo;
-    return ((uint32_t)(key >> lo) & ((1u << kb) - 1u)) | ((bidx << kb) & mask);
+// A local-sort work item: either a window slot (a run of small buckets) or a medium
+// bucket.  Returns false (uniformly across the block) for an empty slot or a bad one.
+struct Chunk {
+    uint64_t start;
+    uint32_t len;
+    uint32_t nbk;  // buckets in the chunk
+    uint32_t f;    // first bucket
+    int lo;        // buckets agree on bits >= lo
+};
+
+__device__ __forceinline__ bool decode_chunk(const LocalArgs& a, uint32_t item, uint64_t nb,
+                                             uint32_t cap, Chunk& ch) {
+    uint32_t f, l;
+    if (item < a.nslots) {
+        f = a.cfirst[item];
+        if (f == 0xffffffffu) return false;
+        l = a.clast[item];
+    } else {
+        f = l = a.med[item - a.nslots];
+    }
+    if ((uint64_t)l >= nb || f > l) {
+        if (threadIdx.x == 0) atomicOr(a.err, ERR_CHUNK);
+        return false;
+    }
+    const uint32_t s = a.bseg[f];
+    const Seg* sg = a.segs + s;
+    const uint64_t start = a.bstart[f];
+    const uint64_t end =
+        ((uint64_t)l + 1 < nb && a.bseg[l + 1] == s) ? a.bstart[l + 1] : sg->start + sg->len;
+    const uint64_t len = end - start;
+    if (len > cap || len == 0) {
+        if (threadIdx.x == 0) atomicOr(a.err, ERR_CHUNK);
+        return false;
+    }
+    ch.start = start;
+    ch.len = (uint32_t)len;
+    ch.nbk = l - f + 1;
+    ch.f = f;
+    ch.lo = sg->lo_bit;
+    return true;
 }
 
+// Offsets from per-wave digit counts (digit-major, then wave order), computed by wave 0
+// alone; every thread calls it, only wave 0 works.
+template <int W>
+__device__ __forceinline__ void wave0_offsets(uint32_t* cnt, int w, int lane) {
+    if (w != 0) return;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < RADIX / 64; ++q) {
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) sum += cnt[ww * RADIX + lane * (RADIX / 64) + q];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int q = 0; q < RADIX / 64; ++q) {
+        const int v = lane * (RADIX / 64) + q;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = cnt[ww * RADIX + v];
+            cnt[ww * RADIX + v] = run;
+            run += c;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Local sort, packed form (the common case).  When the sort bits B of a chunk leave
+// room for the record's position in the chunk (B + log2(CAP) <= key bits), each
+// record travels through the LDS passes as ONE key-sized word: sort bits below, its
+// position above.  Values stay in memory and are gathered by that position at the
+// end (the chunk's value lines are read from HBM once either way).  Chunks that do
+// not fit go to a spill list that the general kernel below sorts.
+// ---------------------------------------------------------------------------------
 template <int KB, int VB, int THREADS, int CAP>
-__global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
+__global__ __launch_bounds__(THREADS, 4) void k_local_sort_packed(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
-    constexpr int ITEMS = CAP / THREADS;
+    constexpr int MAXI = CAP / THREADS;
     constexpr int KBITS = 8 * KB;
-    static_assert(CAP % THREADS == 0 && CAP <= 65536, "chunk layout");
+    constexpr int IB = CAP <= 4096 ? 12 : CAP <= 8192 ? 13 : 16;  // bits of a position
+    static_assert(CAP % THREADS == 0 && CAP <= (1 << IB), "chunk layout");
 
-    __shared__ K s_keys[CAP];
-    __shared__ V s_vals[VB ? CAP : 1];
-    __shared__ uint16_t s_bidx[CAP];
-    __shared__ uint32_t s_wcnt[W * RADIX];
-    __shared__ uint32_t s_local[RADIX];
-    __shared__ uint32_t s_part[RADIX / 64];
+    __shared__ K s_c[CAP];
+    __shared__ uint32_t s_wcnt[2][W * RADIX];
     __shared__ K s_red[W];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
     const uint32_t nmed = *a.nmed < a.medcap ? *a.nmed : a.medcap;
     const uint32_t nitems = a.nslots + nmed;
-    const uint32_t wbase = (uint32_t)w * ITEMS * 64;
-    uint32_t* wc = s_wcnt + w * RADIX;
-    uint32_t* s_rel = (uint32_t*)s_keys;  // bucket starts, before records are staged
+    uint32_t* s_rel = (uint32_t*)s_c;
 
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-        uint32_t f, l;
-        if (item < a.nslots) {
-            f = a.cfirst[item];
-            if (f == 0xffffffffu) continue;
-            l = a.clast[item];
-        } else {
-            f = l = a.med[item - a.nslots];
-        }
-        if ((uint64_t)l >= nb || f > l) {
-            if (tid == 0) atomicOr(a.err, ERR_CHUNK);
-            continue;
-        }
-        const uint32_t s = a.bseg[f];
-        const Seg* sg = a.segs + s;
-        const uint64_t start = a.bstart[f];
-        const uint64_t end =
-            ((uint64_t)l + 1 < nb && a.bseg[l + 1] == s) ? a.bstart[l + 1] : sg->start + sg->len;
-        const uint64_t len64 = end - start;
-        if (len64 > CAP || len64 == 0) {
-            if (tid == 0) atomicOr(a.err, ERR_CHUNK);
-            continue;
-        }
-        const uint32_t len = (uint32_t)len64;
-        const uint32_t nbk = l - f + 1;
-        const int lo = sg->lo_bit;
+        Chunk ch;
+        if (!decode_chunk(a, item, nb, CAP, ch)) continue;
+        const uint64_t start = ch.start;
+        const uint32_t len = ch.len, nbk = ch.nbk;
+        const int lo = ch.lo;
         const K* kin = (const K*)a.kin + start;
         const V* vin = (const V*)a.vin + start;
+        const uint32_t iu = (len + THREADS - 1) / THREADS;
+        const uint32_t wbase = (uint32_t)w * iu * 64;
 
-        K key[ITEMS];
-        V val[ITEMS];
-        uint32_t bix[ITEMS];
-        uint32_t rnk[ITEMS];
+        K c[MAXI];
+        uint32_t rnk[MAXI];
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
+        for (int k = 0; k < MAXI; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
-            const bool ok = idx < len;
-            key[k] = ok ? kin[idx] : K(0);
-            if (VB) val[k] = ok ? vin[idx] : V(0);
-            bix[k] = 0;
+            c[k] = ((uint32_t)k < iu && idx < len) ? kin[idx] : K(0);
         }
-        // Bucket index of each record inside the chunk.
-        if (nbk > 1) {
-            for (uint32_t i = tid; i < nbk; i += THREADS)
-                s_rel[i] = (uint32_t)(a.bstart[f + i] - start);
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
-                const uint32_t idx = wbase + k * 64 + lane;
-                uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
-                while (hi_i - lo_i > 1) {
-                    const uint32_t mid = (lo_i + hi_i) >> 1;
-                    if (s_rel[mid] <= idx) lo_i = mid;
-                    else hi_i = mid;
-                }
-                bix[k] = lo_i;
-            }
-            __syncthreads();
-        }
-        // Bits below lo_bit that vary within the chunk.
+        for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[0][i] = 0;
         const K lowmask = lo >= KBITS ? ~K(0) : (K)((K(1) << lo) - K(1));
         const K key0 = kin[0];
         K vary = 0;
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
+        for (int k = 0; k < MAXI; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
-            if (idx < len) vary |= (key[k] ^ key0) & lowmask;
+            if ((uint32_t)k < iu && idx < len) vary |= (c[k] ^ key0) & lowmask;
         }
         vary = wave_or(vary);
         if (lane == 0) s_red[w] = vary;
@@ -645,87 +742,338 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
         K all = 0;
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) all |= s_red[ww];
+        int h = 0;
+        while (h < KBITS && (all >> h) != 0) ++h;
+        const int bb = nbk > 1 ? 32 - __clz(nbk - 1) : 0;
+        const int B = h > 0 ? h + bb : 0;
+        if (B + IB > KBITS) {  // no room for the position: the general kernel takes it
+            if (tid == 0) {
+                const uint32_t m = atomicAdd(a.nspill, 1u);
+                if (m < a.spillcap) a.spill[m] = item;
+                else atomicOr(a.err, ERR_LIST_CAP);
+            }
+            __syncthreads();
+            continue;
+        }
+        K* kout = (K*)a.kout + start;
+        V* vout = (V*)a.vout + start;
+        if (B == 0) {  // nothing varies: the chunk is in order already
+#pragma unroll
+            for (int k = 0; k < MAXI; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                if ((uint32_t)k < iu && idx < len) {
+                    kout[idx] = c[k];
+                    if (VB) vout[idx] = vin[idx];
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        const K mask_h = (K)((K(1) << h) - K(1));  // h < KBITS here
+        if (nbk > 1) {
+            for (uint32_t i = tid; i < nbk; i += THREADS) s_rel[i] = (uint32_t)(a.bstart[ch.f + i] - start);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            uint32_t bi = 0;
+            if (nbk > 1) {
+                uint32_t lo_i = 0, hi_i = nbk;
+                while (hi_i - lo_i > 1) {
+                    const uint32_t mid = (lo_i + hi_i) >> 1;
+                    if (s_rel[mid] <= idx) lo_i = mid;
+                    else hi_i = mid;
+                }
+                bi = lo_i;
+            }
+            c[k] = (c[k] & mask_h) | ((K)bi << h) | ((K)idx << B);
+        }
+        if (nbk > 1) __syncthreads();
+        const int npass = (B + RADIX_BITS - 1) / RADIX_BITS;
+        const int wd = (B + npass - 1) / npass;
+
+        for (int p = 0; p < npass; ++p) {
+            const int plo = p * wd;
+            const int pw = wd < B - plo ? wd : B - plo;
+            const uint32_t pmask = (1u << pw) - 1u;
+            uint32_t* cnt = s_wcnt[p & 1];
+            uint32_t* wc = cnt + w * RADIX;
+#pragma unroll
+            for (int k = 0; k < MAXI; ++k) {
+                if ((uint32_t)k < iu) {
+                    const uint32_t idx = wbase + k * 64 + lane;
+                    const bool ok = idx < len;
+                    const uint64_t act = __ballot(ok);
+                    const uint32_t d = (uint32_t)(c[k] >> plo) & pmask;
+                    const uint64_t m = same_digit_lanes_rt(d, act, pw);
+                    const uint32_t below = lanes_below(m);
+                    const uint32_t base = wc[d];
+                    if (ok && below == 0) wc[d] = base + (uint32_t)__popcll(m);
+                    rnk[k] = base + below;
+                }
+                __builtin_amdgcn_sched_barrier(0);  // one item at a time: bounded registers
+            }
+            __syncthreads();
+            wave0_offsets<W>(cnt, w, lane);
+            if (w != 0 && p + 1 < npass) {
+                uint32_t* nxt = s_wcnt[(p + 1) & 1];
+                for (int i = tid - 64; i < W * RADIX; i += THREADS - 64) nxt[i] = 0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < MAXI; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                if ((uint32_t)k < iu && idx < len) {
+                    const uint32_t d = (uint32_t)(c[k] >> plo) & pmask;
+                    const uint32_t q = wc[d] + rnk[k];
+                    if (q < CAP) s_c[q] = c[k];
+                }
+            }
+            __syncthreads();
+            if (p + 1 < npass) {
+#pragma unroll
+                for (int k = 0; k < MAXI; ++k) {
+                    const uint32_t idx = wbase + k * 64 + lane;
+                    if ((uint32_t)k < iu && idx < len) c[k] = s_c[idx];
+                }
+            }
+        }
+        // Gather every value (and, for several buckets, the high key bits) before any
+        // write: the output may be the input buffer itself.
+        const K hi0 = key0 & ~mask_h;
+        V g[MAXI];
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            if ((uint32_t)k < iu && idx < len) {
+                const K C = s_c[idx];
+                const uint32_t src = (uint32_t)(C >> B) & ((1u << IB) - 1u);
+                const K hi = nbk > 1 ? (kin[idx] & ~mask_h) : hi0;
+                c[k] = (C & mask_h) | hi;
+                if (VB) g[k] = vin[src < len ? src : 0];
+            }
+        }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            if ((uint32_t)k < iu && idx < len) {
+                kout[idx] = c[k];
+                if (VB) vout[idx] = g[k];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Local sort (the diversion of Sec. 3): one chunk of at most CAP records per step of
+// a block-stride loop.  A chunk is a run of consecutive buckets of one segment (or one
+// medium bucket).  Sorting the chunk stably by the pair (bucket index, bits below
+// lo_bit) sorts each bucket stably by its full key and keeps the buckets in order.
+// Only the bits that vary in the chunk are sorted on (pass skipping at bit
+// granularity, Sec. 2.1), in LSD passes of at most 8 bits inside LDS.
+//
+// The pair is packed into the key word itself: the h varying low bits stay, and the
+// bucket index goes right above them.  It fits, because distinct buckets differ in
+// their bits >= lo_bit, so there are at most 2^(KBITS - lo_bit) of them and h <= lo_bit.
+// On the way out the bits >= h are restored from the input record at the same
+// position: it belongs to the same bucket (buckets keep their ranges), and bits in
+// [h, lo_bit) do not vary in the chunk.
+// ---------------------------------------------------------------------------------
+template <int KB, int VB, int THREADS, int CAP>
+__global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
+    using K = typename uint_of<KB>::type;
+    using V = typename uint_of<VB>::type;
+    constexpr int W = THREADS / 64;
+    constexpr int MAXI = CAP / THREADS;
+    constexpr int KBITS = 8 * KB;
+    static_assert(CAP % THREADS == 0, "chunk layout");
+
+    __shared__ K s_c[CAP];
+    __shared__ V s_v[VB ? CAP : 1];
+    __shared__ uint32_t s_wcnt[2][W * RADIX];  // per-wave digit counters, double-buffered
+    __shared__ K s_red[W];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t nb = umin64(*a.nbuckets, a.bcap);
+    const uint32_t nmed = *a.nmed < a.medcap ? *a.nmed : a.medcap;
+    const uint32_t nspill = *a.nspill < a.spillcap ? *a.nspill : a.spillcap;
+    const uint32_t nitems = a.spill_only ? nspill : a.nslots + nmed;
+    uint32_t* s_rel = (uint32_t*)s_c;  // bucket starts, before records are staged
+
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t item = a.spill_only ? a.spill[it] : it;
+        Chunk ch;
+        if (!decode_chunk(a, item, nb, CAP, ch)) continue;
+        const uint64_t start = ch.start;
+        const uint32_t len = ch.len;
+        const uint32_t nbk = ch.nbk;
+        const uint32_t f = ch.f;
+        const int lo = ch.lo;
+        const K* kin = (const K*)a.kin + start;
+        const V* vin = (const V*)a.vin + start;
+        const uint32_t iu = (len + THREADS - 1) / THREADS;  // items per thread in use
+        const uint32_t wbase = (uint32_t)w * iu * 64;
+
+        K key[MAXI];
+        V val[MAXI];
+        uint32_t rnk[MAXI];
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            const bool ok = (uint32_t)k < iu && idx < len;
+            key[k] = ok ? kin[idx] : K(0);
+            if (VB) val[k] = ok ? vin[idx] : V(0);
+        }
+        for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[0][i] = 0;
+        // Bits below lo_bit that vary within the chunk.
+        const K lowmask = lo >= KBITS ? ~K(0) : (K)((K(1) << lo) - K(1));
+        const K key0 = kin[0];
+        K vary = 0;
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            if ((uint32_t)k < iu && idx < len) vary |= (key[k] ^ key0) & lowmask;
+        }
+        vary = wave_or(vary);
+        if (lane == 0) s_red[w] = vary;
+        __syncthreads();
+        K all = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) all |= s_red[ww];
         int h = 0;
         while (h < KBITS && (all >> h) != 0) ++h;  // bit width of `all`
         const int bb = nbk > 1 ? 32 - __clz(nbk - 1) : 0;
         const int B = h > 0 ? h + bb : 0;
+        if (B > KBITS) {  // cannot happen for buckets told apart by their prefixes
+            if (tid == 0) atomicOr(a.err, ERR_CHUNK);
+            __syncthreads();
+            continue;
+        }
+        const K mask_h = h >= KBITS ? ~K(0) : (K)((K(1) << h) - K(1));
+        if (B > 0) {
+            if (nbk > 1) {
+                for (uint32_t i = tid; i < nbk; i += THREADS)
+                    s_rel[i] = (uint32_t)(a.bstart[f + i] - start);
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < MAXI; ++k) {
+                    const uint32_t idx = wbase + k * 64 + lane;
+                    uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
+                    while (hi_i - lo_i > 1) {
+                        const uint32_t mid = (lo_i + hi_i) >> 1;
+                        if (s_rel[mid] <= idx) lo_i = mid;
+                        else hi_i = mid;
+                    }
+                    key[k] = (key[k] & mask_h) | ((K)lo_i << h);
+                }
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int k = 0; k < MAXI; ++k) key[k] &= mask_h;
+            }
+        }
         const int npass = (B + RADIX_BITS - 1) / RADIX_BITS;
         const int wd = npass ? (B + npass - 1) / npass : 0;
 
         for (int p = 0; p < npass; ++p) {
             const int plo = p * wd;
             const int pw = wd < B - plo ? wd : B - plo;
-            for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[i] = 0;
-            __syncthreads();
+            const uint32_t pmask = (1u << pw) - 1u;
+            uint32_t* cnt = s_wcnt[p & 1];
+            uint32_t* wc = cnt + w * RADIX;
+            // Rank: stable position of each record among equal digits in its wave.
 #pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
-                const uint32_t idx = wbase + k * 64 + lane;
-                const bool ok = idx < len;
-                const uint64_t act = __ballot(ok);
-                const uint32_t d = comp_digit((uint64_t)key[k], bix[k], h, plo, pw);
-                const uint64_t m = same_digit_lanes_rt(d, act, pw);
-                const uint32_t below = lanes_below(m);
-                const uint32_t base = wc[d];
-                if (ok && below == 0) wc[d] = base + (uint32_t)__popcll(m);
-                rnk[k] = base + below;
-            }
-            __syncthreads();
-            uint32_t cnt = 0;
-            if (tid < RADIX) {
-                uint32_t run = 0;
-#pragma unroll
-                for (int ww = 0; ww < W; ++ww) {
-                    const uint32_t c = s_wcnt[ww * RADIX + tid];
-                    s_wcnt[ww * RADIX + tid] = run;
-                    run += c;
+            for (int k = 0; k < MAXI; ++k) {
+                if ((uint32_t)k < iu) {
+                    const uint32_t idx = wbase + k * 64 + lane;
+                    const bool ok = idx < len;
+                    const uint64_t act = __ballot(ok);
+                    const uint32_t d = (uint32_t)(key[k] >> plo) & pmask;
+                    const uint64_t m = same_digit_lanes_rt(d, act, pw);
+                    const uint32_t below = lanes_below(m);
+                    const uint32_t base = wc[d];
+                    if (ok && below == 0) wc[d] = base + (uint32_t)__popcll(m);
+                    rnk[k] = base + below;
                 }
-                cnt = run;
+                __builtin_amdgcn_sched_barrier(0);  // one item at a time: bounded registers
             }
-            uint32_t total;
-            const uint32_t ex = scan256_excl(cnt, s_part, &total);
-            if (tid < RADIX) s_local[tid] = ex;
             __syncthreads();
+            // Wave 0 turns the per-wave counts into block offsets, digit-major then wave
+            // order; the other waves clear the counters of the next pass meanwhile.
+            if (w == 0) {
+                uint32_t tot[RADIX / 64];
+                uint32_t sum = 0;
 #pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
+                for (int q = 0; q < RADIX / 64; ++q) {
+                    uint32_t t = 0;
+#pragma unroll
+                    for (int ww = 0; ww < W; ++ww) t += cnt[ww * RADIX + lane * (RADIX / 64) + q];
+                    tot[q] = t;
+                    sum += t;
+                }
+                uint32_t incl = sum;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += y;
+                }
+                uint32_t run = incl - sum;
+#pragma unroll
+                for (int q = 0; q < RADIX / 64; ++q) {
+                    const int v = lane * (RADIX / 64) + q;
+#pragma unroll
+                    for (int ww = 0; ww < W; ++ww) {
+                        const uint32_t c = cnt[ww * RADIX + v];
+                        cnt[ww * RADIX + v] = run;
+                        run += c;
+                    }
+                }
+            } else if (p + 1 < npass) {
+                uint32_t* nxt = s_wcnt[(p + 1) & 1];
+                for (int i = tid - 64; i < W * RADIX; i += THREADS - 64) nxt[i] = 0;
+            }
+            __syncthreads();
+            // Stage in LDS in digit order.
+#pragma unroll
+            for (int k = 0; k < MAXI; ++k) {
                 const uint32_t idx = wbase + k * 64 + lane;
-                if (idx < len) {
-                    const uint32_t d = comp_digit((uint64_t)key[k], bix[k], h, plo, pw);
-                    const uint32_t q = wc[d] + s_local[d] + rnk[k];
+                if ((uint32_t)k < iu && idx < len) {
+                    const uint32_t d = (uint32_t)(key[k] >> plo) & pmask;
+                    const uint32_t q = wc[d] + rnk[k];
                     if (q < CAP) {
-                        s_keys[q] = key[k];
-                        if (VB) s_vals[q] = val[k];
-                        s_bidx[q] = (uint16_t)bix[k];
+                        s_c[q] = key[k];
+                        if (VB) s_v[q] = val[k];
                     }
                 }
             }
             __syncthreads();
             if (p + 1 < npass) {
 #pragma unroll
-                for (int k = 0; k < ITEMS; ++k) {
+                for (int k = 0; k < MAXI; ++k) {
                     const uint32_t idx = wbase + k * 64 + lane;
-                    if (idx < len) {
-                        key[k] = s_keys[idx];
-                        if (VB) val[k] = s_vals[idx];
-                        bix[k] = s_bidx[idx];
+                    if ((uint32_t)k < iu && idx < len) {
+                        key[k] = s_c[idx];
+                        if (VB) val[k] = s_v[idx];
                     }
                 }
-                __syncthreads();
             }
         }
 
         K* kout = (K*)a.kout + start;
         V* vout = (V*)a.vout + start;
-        if (npass > 0) {
-            for (uint32_t i = tid; i < len; i += THREADS) {
-                kout[i] = s_keys[i];
-                if (VB) vout[i] = s_vals[i];
-            }
-        } else {
+        const K hi0 = key0 & ~mask_h;
 #pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
-                const uint32_t idx = wbase + k * 64 + lane;
-                if (idx < len) {
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            if ((uint32_t)k < iu && idx < len) {
+                if (npass > 0) {
+                    const K hi = nbk > 1 ? (kin[idx] & ~mask_h) : hi0;
+                    kout[idx] = (s_c[idx] & mask_h) | hi;
+                    if (VB) vout[idx] = s_v[idx];
+                } else {
                     kout[idx] = key[k];
                     if (VB) vout[idx] = val[k];
                 }
@@ -760,13 +1108,44 @@ __global__ __launch_bounds__(THREADS) void k_copy_tiles(const void* kin, const v
 // ---------------------------------------------------------------------------------
 // Tile shapes and launchers.
 // ---------------------------------------------------------------------------------
-constexpr int DEAL_THREADS = 512;
+// Shapes (overridable at build time for tuning sweeps).
+#ifndef DFR_DEAL_THREADS
+#define DFR_DEAL_THREADS 512
+#endif
+#ifndef DFR_DEAL_TILE_SMALL  // records per deal tile when key + value <= 8 bytes
+#define DFR_DEAL_TILE_SMALL 8192
+#endif
+#ifndef DFR_DEAL_TILE_LARGE  // records per deal tile for 12- and 16-byte records
+#define DFR_DEAL_TILE_LARGE 4096
+#endif
+#ifndef DFR_LOCAL_THREADS
+#define DFR_LOCAL_THREADS 512
+#endif
+#ifndef DFR_LOCAL_CAP_SMALL
+#define DFR_LOCAL_CAP_SMALL 8192
+#endif
+#ifndef DFR_LOCAL_CAP_LARGE
+#define DFR_LOCAL_CAP_LARGE 4096
+#endif
+constexpr int DEAL_THREADS = DFR_DEAL_THREADS;
+constexpr int DEAL_TILE_SMALL = DFR_DEAL_TILE_SMALL;
+constexpr int DEAL_TILE_LARGE = DFR_DEAL_TILE_LARGE;
 constexpr int COUNT_THREADS = 256;
-constexpr int LOCAL_THREADS = 512;
+constexpr int LOCAL_THREADS = DFR_LOCAL_THREADS;
+constexpr int LOCAL_CAP_SMALL = DFR_LOCAL_CAP_SMALL;
+constexpr int LOCAL_CAP_LARGE = DFR_LOCAL_CAP_LARGE;
 constexpr int COPY_THREADS = 256;
+constexpr int HEAD_THREADS = 512;
+constexpr int GENERAL_THREADS = 256;
+static_assert(DEAL_TILE_SMALL % DEAL_THREADS == 0 && DEAL_TILE_LARGE % DEAL_THREADS == 0, "tile");
+static_assert(DEAL_TILE_SMALL >= DEAL_TILE_LARGE, "head kernel covers the larger tile");
 
-uint32_t deal_tile_records(int kb, int vb) { return kb + vb <= 8 ? 8192u : 4096u; }
-uint32_t local_sort_capacity(int kb, int vb) { return kb + vb <= 8 ? 8192u : 4096u; }
+uint32_t deal_tile_records(int kb, int vb) {
+    return kb + vb <= 8 ? (uint32_t)DEAL_TILE_SMALL : (uint32_t)DEAL_TILE_LARGE;
+}
+uint32_t local_sort_capacity(int kb, int vb) {
+    return kb + vb <= 8 ? (uint32_t)LOCAL_CAP_SMALL : (uint32_t)LOCAL_CAP_LARGE;
+}
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
@@ -790,7 +1169,7 @@ hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t
 
 template <int KB, int VB>
 static void deal_kb_vb(const DealArgs& a, hipStream_t s) {
-    constexpr int ITEMS = (KB + VB <= 8 ? 8192 : 4096) / DEAL_THREADS;
+    constexpr int ITEMS = (KB + VB <= 8 ? DEAL_TILE_SMALL : DEAL_TILE_LARGE) / DEAL_THREADS;
     hipLaunchKernelGGL((k_deal<KB, VB, DEAL_THREADS, ITEMS>), dim3(a.ntiles), dim3(DEAL_THREADS),
                        0, s, a);
 }
@@ -813,8 +1192,9 @@ hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s) {
     if (a.ntiles == 0) return hipSuccess;
     // Tiles are the deal tiles of the level; the head kernel's block covers the
     // largest of them (8192 records).
-    if (kb == 4) hipLaunchKernelGGL((k_heads<4, DEAL_THREADS, 16>), dim3(a.ntiles), dim3(DEAL_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_heads<8, DEAL_THREADS, 16>), dim3(a.ntiles), dim3(DEAL_THREADS), 0, s, a);
+    constexpr int ITEMS = DEAL_TILE_SMALL / HEAD_THREADS;
+    if (kb == 4) hipLaunchKernelGGL((k_heads<4, HEAD_THREADS, ITEMS>), dim3(a.ntiles), dim3(HEAD_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_heads<8, HEAD_THREADS, ITEMS>), dim3(a.ntiles), dim3(HEAD_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -826,9 +1206,16 @@ hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s
 
 template <int KB, int VB>
 static void local_kb_vb(const LocalArgs& a, uint32_t blocks, hipStream_t s) {
-    constexpr int CAP = KB + VB <= 8 ? 8192 : 4096;
-    hipLaunchKernelGGL((k_local_sort<KB, VB, LOCAL_THREADS, CAP>), dim3(blocks), dim3(LOCAL_THREADS),
-                       0, s, a);
+    constexpr int CAP = KB + VB <= 8 ? LOCAL_CAP_SMALL : LOCAL_CAP_LARGE;
+    LocalArgs pa = a;
+    pa.spill_only = 0;
+    hipLaunchKernelGGL((k_local_sort_packed<KB, VB, LOCAL_THREADS, CAP>), dim3(blocks),
+                       dim3(LOCAL_THREADS), 0, s, pa);
+    LocalArgs ga = a;
+    ga.spill_only = 1;
+    const uint32_t gblocks = blocks < 2048 ? blocks : 2048;
+    hipLaunchKernelGGL((k_local_sort<KB, VB, GENERAL_THREADS, CAP>), dim3(gblocks),
+                       dim3(GENERAL_THREADS), 0, s, ga);
 }
 
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks, hipStream_t s) {

@@ -100,13 +100,13 @@ def uniform_hist(n, kb):
 
 
 def test_plan_uniform_u32_2p28(L):
-    # Expected bucket after d top digits: 2^28 / 256^d; N_d = 4096 -> d = 2.
+    # Expected bucket after d top digits: 2^28 / 256^d; N_d = 6144 -> d = 2.
     d, v = dfr.plan_top_digits(uniform_hist(1 << 28, 4), 1 << 28, 4, 4)
     assert (d, v) == (2, 4)
 
 
 def test_plan_uniform_u64_2p27(L):
-    # 2^27 / 256^2 = 2048 = N_d for 16-byte records -> d = 2.
+    # 2^27 / 256^2 = 2048 <= N_d = 3072 for 16-byte records -> d = 2.
     d, v = dfr.plan_top_digits(uniform_hist(1 << 27, 8), 1 << 27, 8, 8)
     assert (d, v) == (2, 8)
 
@@ -141,4 +141,5 @@ def test_plan_skewed_prefers_full_lsd(L):
 def test_plan_divert_option_changes_depth(L):
     h = uniform_hist(1 << 28, 4)
     assert dfr.plan_top_digits(h, 1 << 28, 4, 4, divert=64)[0] == 4  # LSD is cheaper
+    assert dfr.plan_top_digits(h + np.uint32(3) * (np.arange(256) % 2).astype(np.uint32), 1 << 28, 4, 4)[0] == 2
     assert dfr.plan_top_digits(h, 1 << 28, 4, 4, divert=8192)[0] == 2
