@@ -400,9 +400,9 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     if (nb == 0) return DFR_OK;
     std::vector<uint32_t> med(nb);
     for (uint64_t i = 0; i < nb; ++i) med[i] = (uint32_t)i;
-    uint32_t counts3[3] = {(uint32_t)nb, (uint32_t)nb, 0};  // buckets, medium chunks, spills
+    uint32_t counts3[4] = {(uint32_t)nb, (uint32_t)nb, 0, (uint32_t)nb};  // buckets, medium, spills, work
     const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + 3 * asize<uint32_t>(nb) +
-                        asize<uint32_t>(3) + asize<uint32_t>(1);
+                        asize<uint32_t>(4) + asize<uint32_t>(1);
     dfr_status st = arena_reserve(c, need, j.s);
     if (st) return st;
     Seg* dsegs = aalloc<Seg>(c, S);
@@ -410,7 +410,7 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     uint32_t* dbseg = aalloc<uint32_t>(c, nb);
     uint32_t* dmed = aalloc<uint32_t>(c, nb);
     uint32_t* dspill = aalloc<uint32_t>(c, nb);
-    uint32_t* dcounts = aalloc<uint32_t>(c, 3);
+    uint32_t* dcounts = aalloc<uint32_t>(c, 4);
     uint32_t* dnone = aalloc<uint32_t>(c, 1);
     st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
     if (!st) st = upload(j, dbstart, bstart.data(), nb * sizeof(uint64_t));
@@ -436,6 +436,9 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         la.med = dmed;
         la.nmed = dcounts + 1;
         la.medcap = (uint32_t)nb;
+        la.work = dmed;  // medium index i is work item i (no window slots)
+        la.nwork = dcounts + 3;
+        la.workcap = (uint32_t)nb;
         la.spill = dspill;
         la.nspill = dcounts + 2;
         la.spillcap = (uint32_t)nb;
@@ -598,7 +601,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const size_t need_b = asize<Tile>(ntiles) + asize<Seg>(S) + asize<uint32_t>(ntiles * RADIX + 1) +
                           asize<uint64_t>(ntiles + 1) + asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
-                          2 * asize<Big>(bigcap) + asize<uint32_t>(nslots + medcap) +
+                          2 * asize<Big>(bigcap) + 2 * asize<uint32_t>(nslots + medcap) +
                           asize<uint32_t>(8);
     st = arena_need(c, need_b, j.s);  // keeps region A
     if (st) return st;
@@ -615,7 +618,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     Big* big = aalloc<Big>(c, bigcap);
     Big* done = aalloc<Big>(c, bigcap);
     uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
-    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill
+    uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
+    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work
     st = upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
     if (st) return st;
@@ -696,6 +700,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ca.done = done;
         ca.ndone = counters + 3;
         ca.donecap = (uint32_t)bigcap;
+        ca.work = work;
+        ca.nwork = counters + 5;
+        ca.workcap = (uint32_t)(nslots + medcap);
         ca.err = j.err_dev;
         HIP_TRY(c, launch_classify(ca, (uint32_t)std::min<uint64_t>((bcap + 255) / 256, 4096), j.s));
     }
@@ -718,6 +725,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         la.med = med;
         la.nmed = counters + 1;
         la.medcap = (uint32_t)medcap;
+        la.work = work;
+        la.nwork = counters + 5;
+        la.workcap = (uint32_t)(nslots + medcap);
         la.spill = spill;
         la.nspill = counters + 4;
         la.spillcap = (uint32_t)(nslots + medcap);

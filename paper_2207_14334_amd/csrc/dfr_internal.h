@@ -116,6 +116,9 @@ struct ClassifyArgs {
     uint32_t* med;
     uint32_t* nmed;
     uint32_t medcap;
+    uint32_t* work;    // non-empty local-sort work items, appended as found
+    uint32_t* nwork;
+    uint32_t workcap;
     Big* big;
     uint32_t* nbig;
     uint32_t bigcap;
@@ -141,6 +144,9 @@ struct LocalArgs {
     const uint32_t* med;
     const uint32_t* nmed;
     uint32_t medcap;
+    const uint32_t* work;   // non-empty work items (window slots, then nslots + medium index)
+    const uint32_t* nwork;
+    uint32_t workcap;
     uint32_t* spill;    // chunks the packed local sort hands to the general one
     uint32_t* nspill;   // zero before the launch
     uint32_t spillcap;

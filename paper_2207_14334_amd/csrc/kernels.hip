@@ -586,12 +586,23 @@ __global__ void k_classify(ClassifyArgs a) {
             // Medium bucket, or a bucket with no prefix bits to tell it from its
             // neighbours (a whole caller segment): a chunk of its own.
             const uint32_t m = atomicAdd(a.nmed, 1u);
-            if (m < a.medcap) a.med[m] = (uint32_t)b;
-            else over = true;
+            if (m < a.medcap) {
+                a.med[m] = (uint32_t)b;
+                const uint32_t wk = atomicAdd(a.nwork, 1u);
+                if (wk < a.workcap) a.work[wk] = a.nslots + m;
+                else over = true;
+            } else {
+                over = true;
+            }
         } else if (len <= a.wsmall) {
             const uint64_t slot = sg->window_base + (start - sg->start) / a.wsmall;
             if (slot < a.nslots) {
-                atomicMin(&a.cfirst[slot], (uint32_t)b);
+                // The first bucket to reach a window lists it as a work item.
+                if (atomicMin(&a.cfirst[slot], (uint32_t)b) == 0xffffffffu) {
+                    const uint32_t wk = atomicAdd(a.nwork, 1u);
+                    if (wk < a.workcap) a.work[wk] = (uint32_t)slot;
+                    else over = true;
+                }
                 atomicMax(&a.clast[slot], (uint32_t)b);
             } else {
                 over = true;
@@ -609,8 +620,14 @@ __global__ void k_classify(ClassifyArgs a) {
     if (over) atomicOr(a.err, ERR_LIST_CAP);
 }
 
+// Largest chunk any local-sort kernel accepts (the general kernel's capacity).
+#ifndef DFR_LOCAL_CAP_SMALL
+#define DFR_LOCAL_CAP_SMALL 8192
+#endif
+constexpr uint32_t LOCAL_CAP_ANY = DFR_LOCAL_CAP_SMALL;
+
 // A local-sort work item: either a window slot (a run of small buckets) or a medium
-// bucket.  Returns false (uniformly across the block) for an empty slot or a bad one.
+// bucket (item >= nslots).  Returns false (uniformly across the block) for an empty slot or a bad one.
 struct Chunk {
     uint64_t start;
     uint32_t len;
@@ -682,59 +699,85 @@ __device__ __forceinline__ void wave0_offsets(uint32_t* cnt, int w, int lane) {
 }
 
 // ---------------------------------------------------------------------------------
-// Local sort, packed form (the common case).  When the sort bits B of a chunk leave
-// room for the record's position in the chunk (B + log2(CAP) <= key bits), each
-// record travels through the LDS passes as ONE key-sized word: sort bits below, its
-// position above.  Values stay in memory and are gathered by that position at the
-// end (the chunk's value lines are read from HBM once either way).  Chunks that do
-// not fit go to a spill list that the general kernel below sorts.
+// Local sort, bucketed form (the common case).
+//
+// Each record becomes one 64-bit word: its sort bits (the h bits that vary below
+// lo_bit, with the bucket index above them) in the high part and its position in the
+// chunk in the low IB bits.  Words are then distinct, and ordering them orders the
+// records by (sort bits, input position) -- the stable order -- so no step needs to
+// be stable.  The words are bucket-sorted in LDS by their top bits (LDS atomics hand
+// out slots; ~one word per bin on average), and each word's final place is its bin's
+// start plus the number of smaller words in its bin: the rank formula applied inside
+// the bin, the small-group comparison sort of the diversion (Sec. 3; insertion sort
+// in the paper).  Values are gathered by the carried position.  A chunk whose sort
+// bits do not fit next to the position, or whose largest bin exceeds GMAX records,
+// goes to the spill list for the stable radix kernel below.
 // ---------------------------------------------------------------------------------
 template <int KB, int VB, int THREADS, int CAP>
-__global__ __launch_bounds__(THREADS, 4) void k_local_sort_packed(LocalArgs a) {
+__global__ __launch_bounds__(THREADS, 3 * THREADS / 256) void k_local_sort_bucket(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
     constexpr int MAXI = CAP / THREADS;
     constexpr int KBITS = 8 * KB;
     constexpr int IB = CAP <= 4096 ? 12 : CAP <= 8192 ? 13 : 16;  // bits of a position
+    constexpr int DB = IB - 1;                                     // most bin bits
+    constexpr int NWORDS = (1 << DB) / 2;  // two 16-bit bin counters per LDS word
+    constexpr uint32_t GMAX = 64;
     static_assert(CAP % THREADS == 0 && CAP <= (1 << IB), "chunk layout");
 
-    __shared__ K s_c[CAP];
-    __shared__ uint32_t s_wcnt[2][W * RADIX];
+    __shared__ uint64_t s_w[CAP];
+    __shared__ uint32_t s_bin[NWORDS];
+    __shared__ uint32_t s_part[W];
+    __shared__ uint32_t s_max[W];
     __shared__ K s_red[W];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
-    const uint32_t nmed = *a.nmed < a.medcap ? *a.nmed : a.medcap;
-    const uint32_t nitems = a.nslots + nmed;
-    uint32_t* s_rel = (uint32_t*)s_c;
+    const uint32_t nwork = *a.nwork < a.workcap ? *a.nwork : a.workcap;
+    uint32_t* s_rel = (uint32_t*)s_w;
 
-    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    auto spill = [&](uint32_t item) {
+        if (tid == 0) {
+            const uint32_t m = atomicAdd(a.nspill, 1u);
+            if (m < a.spillcap) a.spill[m] = item;
+            else atomicOr(a.err, ERR_LIST_CAP);
+        }
+        __syncthreads();
+    };
+
+    for (uint32_t it = blockIdx.x; it < nwork; it += gridDim.x) {
+        const uint32_t item = a.work[it];
         Chunk ch;
-        if (!decode_chunk(a, item, nb, CAP, ch)) continue;
+        if (!decode_chunk(a, item, nb, LOCAL_CAP_ANY, ch)) continue;
+        if (ch.len > CAP) {  // larger than this kernel's tile: the general kernel sorts it
+            spill(item);
+            continue;
+        }
         const uint64_t start = ch.start;
         const uint32_t len = ch.len, nbk = ch.nbk;
         const int lo = ch.lo;
         const K* kin = (const K*)a.kin + start;
         const V* vin = (const V*)a.vin + start;
+        K* kout = (K*)a.kout + start;
+        V* vout = (V*)a.vout + start;
         const uint32_t iu = (len + THREADS - 1) / THREADS;
         const uint32_t wbase = (uint32_t)w * iu * 64;
 
-        K c[MAXI];
-        uint32_t rnk[MAXI];
+        uint64_t x[MAXI];
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
-            c[k] = ((uint32_t)k < iu && idx < len) ? kin[idx] : K(0);
+            x[k] = ((uint32_t)k < iu && idx < len) ? (uint64_t)kin[idx] : 0ull;
         }
-        for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[0][i] = 0;
+        for (int i = tid; i < NWORDS; i += THREADS) s_bin[i] = 0;
         const K lowmask = lo >= KBITS ? ~K(0) : (K)((K(1) << lo) - K(1));
         const K key0 = kin[0];
         K vary = 0;
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
-            if ((uint32_t)k < iu && idx < len) vary |= (c[k] ^ key0) & lowmask;
+            if ((uint32_t)k < iu && idx < len) vary |= ((K)x[k] ^ key0) & lowmask;
         }
         vary = wave_or(vary);
         if (lane == 0) s_red[w] = vary;
@@ -746,30 +789,23 @@ __global__ __launch_bounds__(THREADS, 4) void k_local_sort_packed(LocalArgs a) {
         while (h < KBITS && (all >> h) != 0) ++h;
         const int bb = nbk > 1 ? 32 - __clz(nbk - 1) : 0;
         const int B = h > 0 ? h + bb : 0;
-        if (B + IB > KBITS) {  // no room for the position: the general kernel takes it
-            if (tid == 0) {
-                const uint32_t m = atomicAdd(a.nspill, 1u);
-                if (m < a.spillcap) a.spill[m] = item;
-                else atomicOr(a.err, ERR_LIST_CAP);
-            }
-            __syncthreads();
+        if (B + IB > 64) {
+            spill(item);
             continue;
         }
-        K* kout = (K*)a.kout + start;
-        V* vout = (V*)a.vout + start;
         if (B == 0) {  // nothing varies: the chunk is in order already
 #pragma unroll
             for (int k = 0; k < MAXI; ++k) {
                 const uint32_t idx = wbase + k * 64 + lane;
                 if ((uint32_t)k < iu && idx < len) {
-                    kout[idx] = c[k];
+                    kout[idx] = (K)x[k];
                     if (VB) vout[idx] = vin[idx];
                 }
             }
             __syncthreads();
             continue;
         }
-        const K mask_h = (K)((K(1) << h) - K(1));  // h < KBITS here
+        const uint64_t mask_h = (1ull << h) - 1ull;  // h < 64 here
         if (nbk > 1) {
             for (uint32_t i = tid; i < nbk; i += THREADS) s_rel[i] = (uint32_t)(a.bstart[ch.f + i] - start);
             __syncthreads();
@@ -777,9 +813,9 @@ __global__ __launch_bounds__(THREADS, 4) void k_local_sort_packed(LocalArgs a) {
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
-            uint32_t bi = 0;
+            uint64_t bi = 0;
             if (nbk > 1) {
-                uint32_t lo_i = 0, hi_i = nbk;
+                uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
                 while (hi_i - lo_i > 1) {
                     const uint32_t mid = (lo_i + hi_i) >> 1;
                     if (s_rel[mid] <= idx) lo_i = mid;
@@ -787,80 +823,114 @@ __global__ __launch_bounds__(THREADS, 4) void k_local_sort_packed(LocalArgs a) {
                 }
                 bi = lo_i;
             }
-            c[k] = (c[k] & mask_h) | ((K)bi << h) | ((K)idx << B);
+            x[k] = ((((x[k] & mask_h) | (bi << h)) << IB) | idx);
         }
-        if (nbk > 1) __syncthreads();
-        const int npass = (B + RADIX_BITS - 1) / RADIX_BITS;
-        const int wd = (B + npass - 1) / npass;
-
-        for (int p = 0; p < npass; ++p) {
-            const int plo = p * wd;
-            const int pw = wd < B - plo ? wd : B - plo;
-            const uint32_t pmask = (1u << pw) - 1u;
-            uint32_t* cnt = s_wcnt[p & 1];
-            uint32_t* wc = cnt + w * RADIX;
-#pragma unroll
-            for (int k = 0; k < MAXI; ++k) {
-                if ((uint32_t)k < iu) {
-                    const uint32_t idx = wbase + k * 64 + lane;
-                    const bool ok = idx < len;
-                    const uint64_t act = __ballot(ok);
-                    const uint32_t d = (uint32_t)(c[k] >> plo) & pmask;
-                    const uint64_t m = same_digit_lanes_rt(d, act, pw);
-                    const uint32_t below = lanes_below(m);
-                    const uint32_t base = wc[d];
-                    if (ok && below == 0) wc[d] = base + (uint32_t)__popcll(m);
-                    rnk[k] = base + below;
-                }
-                __builtin_amdgcn_sched_barrier(0);  // one item at a time: bounded registers
-            }
-            __syncthreads();
-            wave0_offsets<W>(cnt, w, lane);
-            if (w != 0 && p + 1 < npass) {
-                uint32_t* nxt = s_wcnt[(p + 1) & 1];
-                for (int i = tid - 64; i < W * RADIX; i += THREADS - 64) nxt[i] = 0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < MAXI; ++k) {
-                const uint32_t idx = wbase + k * 64 + lane;
-                if ((uint32_t)k < iu && idx < len) {
-                    const uint32_t d = (uint32_t)(c[k] >> plo) & pmask;
-                    const uint32_t q = wc[d] + rnk[k];
-                    if (q < CAP) s_c[q] = c[k];
-                }
-            }
-            __syncthreads();
-            if (p + 1 < npass) {
-#pragma unroll
-                for (int k = 0; k < MAXI; ++k) {
-                    const uint32_t idx = wbase + k * 64 + lane;
-                    if ((uint32_t)k < iu && idx < len) c[k] = s_c[idx];
-                }
-            }
-        }
-        // Gather every value (and, for several buckets, the high key bits) before any
-        // write: the output may be the input buffer itself.
-        const K hi0 = key0 & ~mask_h;
-        V g[MAXI];
+        const int nbits = B < DB ? B : DB;
+        const uint32_t nbins = 1u << nbits;
+        const int dshift = IB + B - nbits;
+        const uint32_t nwords = nbins > 1 ? nbins / 2 : 1;
+        if (nbk > 1) __syncthreads();  // s_rel no longer needed
+        // Slots inside the bins.
+        uint32_t slot[MAXI];
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
+            slot[k] = 0;
             const uint32_t idx = wbase + k * 64 + lane;
             if ((uint32_t)k < iu && idx < len) {
-                const K C = s_c[idx];
-                const uint32_t src = (uint32_t)(C >> B) & ((1u << IB) - 1u);
-                const K hi = nbk > 1 ? (kin[idx] & ~mask_h) : hi0;
-                c[k] = (C & mask_h) | hi;
-                if (VB) g[k] = vin[src < len ? src : 0];
+                const uint32_t d = (uint32_t)(x[k] >> dshift) & (nbins - 1);
+                const uint32_t sh = 16 * (d & 1);
+                slot[k] = (atomicAdd(&s_bin[d >> 1], 1u << sh) >> sh) & 0xffffu;
             }
+        }
+        __syncthreads();
+        // Bin counts -> bin starts (exclusive scan, in place), and the largest bin.
+        {
+            const uint32_t per = (nwords + THREADS - 1) / THREADS;
+            const uint32_t w0 = tid * per, w1 = w0 + per < nwords ? w0 + per : nwords;
+            uint32_t sum = 0, mx = 0;
+            for (uint32_t i = w0; i < w1; ++i) {
+                const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
+                sum += c0 + c1;
+                mx = c0 > mx ? c0 : mx;
+                mx = c1 > mx ? c1 : mx;
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t y = __shfl_xor(mx, o, 64);
+                mx = y > mx ? y : mx;
+            }
+            if (lane == 63) s_part[w] = incl;
+            if (lane == 0) s_max[w] = mx;
+            __syncthreads();
+            uint32_t run = incl - sum;
+            for (int ww = 0; ww < w; ++ww) run += s_part[ww];
+            for (uint32_t i = w0; i < w1; ++i) {
+                const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
+                s_bin[i] = run | ((run + c0) << 16);
+                run += c0 + c1;
+            }
+        }
+        uint32_t gmax = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) gmax = s_max[ww] > gmax ? s_max[ww] : gmax;
+        if (gmax > GMAX) {  // a big group of near-equal keys: the stable kernel sorts it
+            spill(item);
+            continue;
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
             if ((uint32_t)k < iu && idx < len) {
-                kout[idx] = c[k];
-                if (VB) vout[idx] = g[k];
+                const uint32_t d = (uint32_t)(x[k] >> dshift) & (nbins - 1);
+                const uint32_t st = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
+                const uint32_t q = st + slot[k];
+                if (q < CAP) s_w[q] = x[k];
+            }
+        }
+        __syncthreads();
+        // Rank inside the bin (its start plus the smaller words in it), then gather the
+        // value and the key's high bits; all reads happen before any write, since the
+        // output may be the input buffer itself.
+        uint32_t pos[MAXI];
+        K ko[MAXI];
+        V vo[MAXI];
+        const uint64_t hi0 = (uint64_t)key0 & ~mask_h;
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t p = wbase + k * 64 + lane;
+            pos[k] = 0xffffffffu;
+            ko[k] = 0;
+            vo[k] = 0;
+            if ((uint32_t)k < iu && p < len) {
+                const uint64_t me = s_w[p];
+                const uint32_t d = (uint32_t)(me >> dshift) & (nbins - 1);
+                const uint32_t gs = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
+                const uint32_t dn = d + 1;
+                const uint32_t ge = dn < nbins ? (s_bin[dn >> 1] >> (16 * (dn & 1))) & 0xffffu : len;
+                uint32_t r = 0;
+                for (uint32_t q = gs; q < ge; ++q) r += s_w[q] < me;
+                const uint32_t at = gs + r < len ? gs + r : len - 1;
+                const uint32_t src = (uint32_t)me & ((1u << IB) - 1u);
+                const uint64_t hi = nbk > 1 ? ((uint64_t)kin[at] & ~mask_h) : hi0;
+                pos[k] = at;
+                ko[k] = (K)(((me >> IB) & mask_h) | hi);
+                if (VB) vo[k] = vin[src < len ? src : 0];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            if (pos[k] < len) {
+                kout[pos[k]] = ko[k];
+                if (VB) vout[pos[k]] = vo[k];
             }
         }
         __syncthreads();
@@ -900,11 +970,12 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
     const uint32_t nmed = *a.nmed < a.medcap ? *a.nmed : a.medcap;
     const uint32_t nspill = *a.nspill < a.spillcap ? *a.nspill : a.spillcap;
-    const uint32_t nitems = a.spill_only ? nspill : a.nslots + nmed;
+    const uint32_t nitems = nspill;
+    (void)nmed;
     uint32_t* s_rel = (uint32_t*)s_c;  // bucket starts, before records are staged
 
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint32_t item = a.spill_only ? a.spill[it] : it;
+        const uint32_t item = a.spill[it];
         Chunk ch;
         if (!decode_chunk(a, item, nb, CAP, ch)) continue;
         const uint64_t start = ch.start;
@@ -925,7 +996,8 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
             const uint32_t idx = wbase + k * 64 + lane;
             const bool ok = (uint32_t)k < iu && idx < len;
             key[k] = ok ? kin[idx] : K(0);
-            if (VB) val[k] = ok ? vin[idx] : V(0);
+            val[k] = (VB && ok) ? vin[idx] : V(0);
+            rnk[k] = 0;
         }
         for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[0][i] = 0;
         // Bits below lo_bit that vary within the chunk.
@@ -1137,6 +1209,12 @@ constexpr int LOCAL_CAP_LARGE = DFR_LOCAL_CAP_LARGE;
 constexpr int COPY_THREADS = 256;
 constexpr int HEAD_THREADS = 512;
 constexpr int GENERAL_THREADS = 256;
+#ifndef DFR_BUCKET_CAP_SMALL  // records per bucketed local-sort chunk (8-byte records)
+#define DFR_BUCKET_CAP_SMALL 5120
+#endif
+#ifndef DFR_BUCKET_CAP_LARGE
+#define DFR_BUCKET_CAP_LARGE 4096
+#endif
 static_assert(DEAL_TILE_SMALL % DEAL_THREADS == 0 && DEAL_TILE_LARGE % DEAL_THREADS == 0, "tile");
 static_assert(DEAL_TILE_SMALL >= DEAL_TILE_LARGE, "head kernel covers the larger tile");
 
@@ -1207,9 +1285,10 @@ hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s
 template <int KB, int VB>
 static void local_kb_vb(const LocalArgs& a, uint32_t blocks, hipStream_t s) {
     constexpr int CAP = KB + VB <= 8 ? LOCAL_CAP_SMALL : LOCAL_CAP_LARGE;
+    constexpr int BCAP = KB + VB <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE;
     LocalArgs pa = a;
     pa.spill_only = 0;
-    hipLaunchKernelGGL((k_local_sort_packed<KB, VB, LOCAL_THREADS, CAP>), dim3(blocks),
+    hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP>), dim3(blocks),
                        dim3(LOCAL_THREADS), 0, s, pa);
     LocalArgs ga = a;
     ga.spill_only = 1;
