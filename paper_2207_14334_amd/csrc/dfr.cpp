@@ -470,8 +470,12 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // --- 1. count ---------------------------------------------------------------
     // Region A of the arena (kept for the whole level): histograms and OR/AND.
     const size_t hist_n = S * ndig * RADIX;
+    // A single segment is dealt without look-back: the count also keeps every tile's
+    // own digit counts, from which a scan gives each tile its bucket bases.
+    const bool single = S == 1;
+    const size_t tcnt_n = single ? tiles.size() * ndig * RADIX : 0;
     dfr_status st = arena_reserve(c, asize<uint32_t>(hist_n) + 2 * asize<uint64_t>(S) +
-                                         asize<Tile>(tiles.size()), j.s);
+                                         asize<uint32_t>(tcnt_n) + asize<Tile>(tiles.size()), j.s);
     if (st) return st;
     const size_t off_hist = c->arena_used;
     aalloc<uint32_t>(c, hist_n);
@@ -479,6 +483,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     aalloc<uint64_t>(c, S);
     const size_t off_and = c->arena_used;
     aalloc<uint64_t>(c, S);
+    const size_t off_tcnt = c->arena_used;
+    aalloc<uint32_t>(c, tcnt_n);
     const size_t region_a = c->arena_used;
     Tile* dtiles = aalloc<Tile>(c, tiles.size());
     uint32_t* dhist = (uint32_t*)(c->arena + off_hist);
@@ -503,6 +509,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ca.hist = dhist;
         ca.seg_or = dor;
         ca.seg_and = dand;
+        ca.tile_hist = single ? (uint32_t*)(c->arena + off_tcnt) : nullptr;
         const uint32_t grid = (uint32_t)((tiles.size() + ca.tiles_per_block - 1) / ca.tiles_per_block);
         HIP_TRY(c, launch_count(kb, ca, grid, j.s));
     }
@@ -603,9 +610,25 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
                           2 * asize<Big>(bigcap) + 2 * asize<uint32_t>(nslots + medcap) +
                           asize<uint32_t>(8);
-    st = arena_need(c, need_b, j.s);  // keeps region A
+    const uint32_t scan_tpb = 128;
+    const uint32_t scan_nb = (uint32_t)((ntiles + scan_tpb - 1) / scan_tpb);
+    const size_t need_nolb = single ? asize<uint32_t>(ntiles * RADIX) * 2 +
+                                          asize<uint32_t>((size_t)scan_nb * RADIX) +
+                                          asize<uint32_t>(RADIX) + asize<uint64_t>(2)
+                                    : 0;
+    st = arena_need(c, need_b + need_nolb, j.s);  // keeps region A
     if (st) return st;
     dhist = (uint32_t*)(c->arena + off_hist);
+    uint32_t* tcnt = (uint32_t*)(c->arena + off_tcnt);
+    uint32_t *toff = nullptr, *tone = nullptr, *tpart = nullptr, *dummy_hist = nullptr;
+    uint64_t* dummy_oa = nullptr;
+    if (single) {
+        toff = aalloc<uint32_t>(c, ntiles * RADIX);
+        tone = aalloc<uint32_t>(c, ntiles * RADIX);
+        tpart = aalloc<uint32_t>(c, (size_t)scan_nb * RADIX);
+        dummy_hist = aalloc<uint32_t>(c, RADIX);
+        dummy_oa = aalloc<uint64_t>(c, 2);
+    }
     dtiles = aalloc<Tile>(c, ntiles);
     Seg* dsegs = aalloc<Seg>(c, S);
     uint32_t* lb = aalloc<uint32_t>(c, ntiles * RADIX + 1);
@@ -626,9 +649,52 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
 
     int cur = in;
     for (int p = 0; p < d; ++p) {
-        HIP_TRY(c, launch_fill_u32(lb, 0, ntiles * RADIX + 1, j.s));
+        if (single) {
+            // Per-tile counts of this pass's digit: from the count at the first pass,
+            // from a count of the current order afterwards; then the tiles' bases.
+            const Seg& g = hs[active[0]];
+            TileScanArgs ta{};
+            if (p == 0) {
+                ta.cnt = tcnt;
+                ta.ndig = ndig;
+                ta.slot = g.hslot[0];
+            } else {
+                Timed tc(c, j.s, ST_COUNT);
+                HIP_TRY(c, launch_fill_u32(dummy_hist, 0, RADIX, j.s));
+                HIP_TRY(c, launch_fill_u64(dummy_oa, 0, 2, j.s));
+                CountArgs ca{};
+                ca.keys = j.k[cur];
+                ca.tiles = dtiles;
+                ca.ntiles = (uint32_t)ntiles;
+                const uint32_t blocks = (uint32_t)std::min<size_t>(ntiles, 4096);
+                ca.tiles_per_block = (uint32_t)((ntiles + blocks - 1) / blocks);
+                ca.base_shift = g.shift[p];
+                ca.bits = g.width[p];
+                ca.ndig = 1;
+                ca.hist = dummy_hist;
+                ca.seg_or = dummy_oa;
+                ca.seg_and = dummy_oa + 1;
+                ca.tile_hist = tone;
+                const uint32_t grid = (uint32_t)((ntiles + ca.tiles_per_block - 1) / ca.tiles_per_block);
+                HIP_TRY(c, launch_count(kb, ca, grid, j.s));
+                ta.cnt = tone;
+                ta.ndig = 1;
+                ta.slot = 0;
+            }
+            ta.ntiles = (uint32_t)ntiles;
+            ta.tiles_per_block = scan_tpb;
+            ta.nblocks = scan_nb;
+            ta.partial = tpart;
+            ta.off = toff;
+            Timed ts(c, j.s, ST_OTHER);
+            HIP_TRY(c, launch_tile_scan(ta, j.s));
+            HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
+        } else {
+            HIP_TRY(c, launch_fill_u32(lb, 0, ntiles * RADIX + 1, j.s));
+        }
         Timed tm(c, j.s, ST_DEAL, true);
         DealArgs da{};
+        da.off = single ? toff : nullptr;
         da.kin = j.k[cur];
         da.vin = j.v[cur];
         da.kout = j.k[1 - cur];

@@ -69,6 +69,20 @@ struct CountArgs {
     uint32_t* hist;      // [seg][ndig][RADIX]
     void* seg_or;        // [seg] key type, OR of the segment's keys
     void* seg_and;       // [seg] key type, AND of the segment's keys
+    uint32_t* tile_hist; // optional [tile][ndig][RADIX]: each tile's own counts
+};
+
+// Per-tile bucket bases from per-tile digit counts (one segment): off[t][v] is the
+// position, relative to the segment start, of tile t's first record of digit v.
+struct TileScanArgs {
+    const uint32_t* cnt;  // cnt[(t * ndig + slot) * RADIX + v]
+    int32_t ndig;
+    int32_t slot;
+    uint32_t ntiles;
+    uint32_t tiles_per_block;
+    uint32_t nblocks;
+    uint32_t* partial;  // [nblocks][RADIX]
+    uint32_t* off;      // [ntiles][RADIX]
 };
 
 struct DealArgs {
@@ -84,6 +98,7 @@ struct DealArgs {
     int32_t pass;
     uint32_t* lookback;  // [ntiles][RADIX]
     uint32_t* ticket;
+    const uint32_t* off; // when set: per-tile bucket bases, and no look-back
     uint32_t* err;
 };
 
@@ -163,6 +178,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
+hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,

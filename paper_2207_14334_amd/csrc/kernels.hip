@@ -37,6 +37,13 @@ struct uint_of<8> {
 
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
+// Tile order of the look-back-free deal: 0 block index, 1 ticket, 2 one contiguous
+// range of tiles per XCD.
+#ifndef DFR_DEAL_ORDER
+#define DFR_DEAL_ORDER 2
+#endif
+constexpr int DEAL_ORDER = DFR_DEAL_ORDER;
+
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
@@ -172,11 +179,13 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     constexpr int PER_VEC = 16 / KB;  // keys per 16-byte load
     constexpr int VECS = 8;           // 16-byte loads in flight per thread
     __shared__ uint32_t s_h[W * SLICE];
+    __shared__ uint32_t s_tot[SLICE];  // the block's counts for the current segment
     __shared__ K s_or[W];
     __shared__ K s_and[W];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int i = tid; i < W * SLICE; i += THREADS) s_h[i] = 0;
+    for (int i = tid; i < SLICE; i += THREADS) s_tot[i] = 0;
     __syncthreads();
 
     const uint32_t t0 = blockIdx.x * a.tiles_per_block;
@@ -189,7 +198,9 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     uint32_t cur = a.tiles[t0].seg;
     K vor = 0, vand = ~K(0);
 
-    auto flush = [&](uint32_t seg) {
+    // End of a tile: fold the waves' bins into the block total (and write the tile's
+    // own counts when asked).  Each thread owns the same entries in both arrays.
+    auto end_tile = [&](uint32_t t) {
         __syncthreads();
         for (int idx = tid; idx < ndig * RADIX; idx += THREADS) {
             uint32_t sum = 0;
@@ -198,6 +209,15 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
                 sum += s_h[ww * SLICE + idx];
                 s_h[ww * SLICE + idx] = 0;
             }
+            s_tot[idx] += sum;
+            if (a.tile_hist) a.tile_hist[(size_t)t * ndig * RADIX + idx] = sum;
+        }
+    };
+    auto flush = [&](uint32_t seg) {
+        __syncthreads();
+        for (int idx = tid; idx < ndig * RADIX; idx += THREADS) {
+            const uint32_t sum = s_tot[idx];
+            s_tot[idx] = 0;
             if (sum) atomicAdd(&a.hist[(size_t)seg * ndig * RADIX + idx], sum);
         }
         const K o = wave_or(vor), n = wave_and(vand);
@@ -290,6 +310,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
                 }
             }
         }
+        end_tile(t);
     }
     flush(cur);
 }
@@ -302,7 +323,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
 // of lane l being record w*ITEMS*64 + k*64 + l, so a wave meets its records in input
 // order and the ballot ranks are stable.
 // ---------------------------------------------------------------------------------
-template <int KB, int VB, int THREADS, int ITEMS>
+template <int KB, int VB, int THREADS, int ITEMS, bool LOOKBACK>
 __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
@@ -319,10 +340,24 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     __shared__ uint32_t s_ticket;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
+    if ((LOOKBACK || DEAL_ORDER == 1) && tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
     for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[i] = 0;
     __syncthreads();
-    const uint32_t t = s_ticket;
+    uint32_t t;
+    if (LOOKBACK || DEAL_ORDER == 1) {
+        t = s_ticket;
+    } else if (DEAL_ORDER == 2) {
+        // Blocks are dealt to the 8 XCDs round-robin; give each XCD one contiguous
+        // range of tiles, so the lines a bucket receives from neighbouring tiles are
+        // written through one L2.
+        const uint32_t nx = 8, b = blockIdx.x, per = (a.ntiles + nx - 1) / nx;
+        const uint32_t full = a.ntiles - (per - 1) * nx;  // XCDs that get `per` tiles
+        const uint32_t x = b % nx, i = b / nx;
+        t = x < full ? x * per + i : full * per + (x - full) * (per - 1) + i;
+        if (i >= (x < full ? per : per - 1)) t = a.ntiles;
+    } else {
+        t = blockIdx.x;
+    }
     if (t >= a.ntiles) return;
 
     const Tile tl = a.tiles[t];
@@ -375,17 +410,25 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
             run += c;
         }
         tile_cnt = run;
-        __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid],
-                           (t == first_tile ? LB_PRE : LB_AGG) | run, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        if (LOOKBACK)
+            __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid],
+                               (t == first_tile ? LB_PRE : LB_AGG) | run, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
     }
-    const uint32_t hv =
-        tid < RADIX ? a.hist[((size_t)tl.seg * a.hist_digits + hslot) * RADIX + tid] : 0u;
     uint32_t total;
-    const uint32_t seg_excl = scan256_excl(hv, s_part, &total);
+    uint32_t seg_excl = 0;
+    if (LOOKBACK) {
+        const uint32_t hv =
+            tid < RADIX ? a.hist[((size_t)tl.seg * a.hist_digits + hslot) * RADIX + tid] : 0u;
+        seg_excl = scan256_excl(hv, s_part, &total);
+    }
     const uint32_t loc_excl = scan256_excl(tile_cnt, s_part, &total);
 
-    if (tid < RADIX) {
+    if (!LOOKBACK && tid < RADIX) {
+        s_local[tid] = loc_excl;
+        s_gdelta[tid] = seg_start + (uint64_t)a.off[(size_t)t * RADIX + tid] - (uint64_t)loc_excl;
+    }
+    if (LOOKBACK && tid < RADIX) {
         s_local[tid] = loc_excl;
         uint32_t excl = 0;
         if (t != first_tile) {
@@ -1248,8 +1291,97 @@ hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t
 template <int KB, int VB>
 static void deal_kb_vb(const DealArgs& a, hipStream_t s) {
     constexpr int ITEMS = (KB + VB <= 8 ? DEAL_TILE_SMALL : DEAL_TILE_LARGE) / DEAL_THREADS;
-    hipLaunchKernelGGL((k_deal<KB, VB, DEAL_THREADS, ITEMS>), dim3(a.ntiles), dim3(DEAL_THREADS),
-                       0, s, a);
+    if (a.off)
+        hipLaunchKernelGGL((k_deal<KB, VB, DEAL_THREADS, ITEMS, false>), dim3(a.ntiles),
+                           dim3(DEAL_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_deal<KB, VB, DEAL_THREADS, ITEMS, true>), dim3(a.ntiles),
+                           dim3(DEAL_THREADS), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------------
+// Per-tile bucket bases for one segment (reduce-then-scan): (a) each block of tiles
+// sums its tiles' counts per digit; (b) one block scans those sums over blocks, and
+// adds each digit's bucket start (exclusive scan of the digit totals); (c) each block
+// walks its tiles in order, writing every tile's bases.
+// ---------------------------------------------------------------------------------
+constexpr int SCAN_BATCH = 16;  // independent loads in flight per thread
+
+__global__ __launch_bounds__(RADIX) void k_tile_scan_a(TileScanArgs a) {
+    const uint32_t b = blockIdx.x, v = threadIdx.x;
+    const uint32_t t0 = b * a.tiles_per_block;
+    const uint32_t t1 = a.ntiles - t0 < a.tiles_per_block ? a.ntiles : t0 + a.tiles_per_block;
+    uint32_t sum = 0;
+    for (uint32_t tb = t0; tb < t1; tb += SCAN_BATCH) {
+        uint32_t c[SCAN_BATCH];
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i)
+            c[i] = tb + i < t1 ? a.cnt[((size_t)(tb + i) * a.ndig + a.slot) * RADIX + v] : 0u;
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i) sum += c[i];
+    }
+    a.partial[(size_t)b * RADIX + v] = sum;
+}
+
+// One block of 4 * RADIX threads: thread (q, v) scans part q of the block sums of
+// digit v; the parts are then chained, and the digit totals turned into bucket starts.
+__global__ __launch_bounds__(4 * RADIX) void k_tile_scan_b(TileScanArgs a) {
+    __shared__ uint32_t s_q[4][RADIX];
+    __shared__ uint32_t s_part[RADIX / 64];
+    const uint32_t v = threadIdx.x % RADIX, q = threadIdx.x / RADIX;
+    const uint32_t per = (a.nblocks + 3) / 4;
+    const uint32_t b0 = q * per, b1 = b0 + per < a.nblocks ? b0 + per : a.nblocks;
+    uint32_t run = 0;
+    for (uint32_t bb = b0; bb < b1; bb += SCAN_BATCH) {
+        uint32_t c[SCAN_BATCH];
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i) c[i] = bb + i < b1 ? a.partial[(size_t)(bb + i) * RADIX + v] : 0u;
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i) {
+            if (bb + i < b1) a.partial[(size_t)(bb + i) * RADIX + v] = run;
+            run += c[i];
+        }
+    }
+    s_q[q][v] = run;
+    __syncthreads();
+    uint32_t before = 0, total_v = 0;
+    for (uint32_t i = 0; i < 4; ++i) {
+        before += i < q ? s_q[i][v] : 0u;
+        total_v += s_q[i][v];
+    }
+    uint32_t all;
+    const uint32_t start = scan256_excl(threadIdx.x < RADIX ? total_v : 0u, s_part, &all);
+    __shared__ uint32_t s_start[RADIX];
+    if (threadIdx.x < RADIX) s_start[v] = start;
+    __syncthreads();
+    const uint32_t add = s_start[v] + before;
+    for (uint32_t bb = b0; bb < b1; ++bb) a.partial[(size_t)bb * RADIX + v] += add;
+}
+
+__global__ __launch_bounds__(RADIX) void k_tile_scan_c(TileScanArgs a) {
+    const uint32_t b = blockIdx.x, v = threadIdx.x;
+    const uint32_t t0 = b * a.tiles_per_block;
+    const uint32_t t1 = a.ntiles - t0 < a.tiles_per_block ? a.ntiles : t0 + a.tiles_per_block;
+    uint32_t run = a.partial[(size_t)b * RADIX + v];
+    for (uint32_t tb = t0; tb < t1; tb += SCAN_BATCH) {
+        uint32_t c[SCAN_BATCH];
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i)
+            c[i] = tb + i < t1 ? a.cnt[((size_t)(tb + i) * a.ndig + a.slot) * RADIX + v] : 0u;
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i) {
+            if (tb + i < t1) a.off[(size_t)(tb + i) * RADIX + v] = run;
+            run += c[i];
+        }
+    }
+}
+
+hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s) {
+    if (a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_scan_a, dim3(a.nblocks), dim3(RADIX), 0, s, a);
+    hipLaunchKernelGGL(k_tile_scan_b, dim3(1), dim3(4 * RADIX), 0, s, a);
+    hipLaunchKernelGGL(k_tile_scan_c, dim3(a.nblocks), dim3(RADIX), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s) {
