@@ -171,11 +171,11 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
 // first active lane's digit add their number in one LDS atomic -- and otherwise one
 // atomic per key.
 // ---------------------------------------------------------------------------------
-template <int KB, int THREADS>
+template <int KB, int THREADS, int NDIG>
 __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     using K = typename uint_of<KB>::type;
     constexpr int W = THREADS / 64;
-    constexpr int SLICE = MAX_PASSES * RADIX;
+    constexpr int SLICE = NDIG * RADIX;  // bins for up to NDIG digits
     constexpr int PER_VEC = 16 / KB;  // keys per 16-byte load
     constexpr int VECS = 8;           // 16-byte loads in flight per thread
     __shared__ uint32_t s_h[W * SLICE];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     const uint32_t t0 = blockIdx.x * a.tiles_per_block;
     if (t0 >= a.ntiles) return;
     const uint32_t t1 = a.ntiles - t0 < a.tiles_per_block ? a.ntiles : t0 + a.tiles_per_block;
-    const int ndig = a.ndig, bits = a.bits, base = a.base_shift;
+    const int ndig = a.ndig < NDIG ? a.ndig : NDIG, bits = a.bits, base = a.base_shift;
     const uint32_t dmask = (1u << bits) - 1u;
     uint32_t* hw = s_h + w * SLICE;
 
@@ -212,6 +212,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
             s_tot[idx] += sum;
             if (a.tile_hist) a.tile_hist[(size_t)t * ndig * RADIX + idx] = sum;
         }
+        __syncthreads();  // bins are clear before any wave counts the next tile
     };
     auto flush = [&](uint32_t seg) {
         __syncthreads();
@@ -1281,10 +1282,21 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int KB>
+static void count_kb(const CountArgs& a, uint32_t blocks, hipStream_t s) {
+    if (a.ndig <= 1)
+        hipLaunchKernelGGL((k_count<KB, COUNT_THREADS, 1>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
+    else if (a.ndig <= 4)
+        hipLaunchKernelGGL((k_count<KB, COUNT_THREADS, 4>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_count<KB, COUNT_THREADS, 8>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
+}
+
 hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s) {
     if (blocks == 0) return hipSuccess;
-    if (kb == 4) hipLaunchKernelGGL((k_count<4, COUNT_THREADS>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_count<8, COUNT_THREADS>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
+    if (a.ndig < 1 || a.ndig > MAX_PASSES) return hipErrorInvalidValue;
+    if (kb == 4) count_kb<4>(a, blocks, s);
+    else count_kb<8>(a, blocks, s);
     return hipGetLastError();
 }
 

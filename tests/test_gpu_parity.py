@@ -245,3 +245,19 @@ def test_argument_errors(torch, ctx):
     with pytest.raises(dfr.DfrError) as e:
         ctx.set_option("no_such_option", 1)
     assert e.value.status == dfr.E_UNSUPPORTED
+
+
+def test_repeat_stress_many_tiles(torch, ctx, o):
+    """Repeated large sorts must agree bit for bit (a race in a kernel shows up as a
+    difference between repeats) and match the oracle."""
+    for dist, n in (("uniform", (1 << 24) + 77), ("normal", 1 << 23)):
+        k = workloads.make_keys(dist, n, 32, 21)
+        v = workloads.index_payload(n)
+        say("stress", dist, n)
+        first = None
+        for _ in range(6):
+            sk, sv, _ = gpu_sort(torch, ctx, k, v)
+            if first is None:
+                first = (sk, sv)
+            assert np.array_equal(sk, first[0]) and np.array_equal(sv, first[1]), dist
+        assert o.check_index_payload(k, first[0], first[1]) is None, dist
