@@ -11,7 +11,8 @@ Key distributions (``make_keys``):
 * ``uniform``   -- i.i.d. uniform over the whole key range.
 * ``normal``    -- normal with mean 2^(w-1) and sd 2^(w-4), rounded and clipped to the
                    key range (w = key bits).  For 32-bit keys: mean 2^31, sd 2^28.
-* ``zipf``      -- Zipf(s=1.1) ranks r >= 1, redrawn while r > 2^32, key = r - 1.
+* ``zipf``      -- Zipf(s=1.1) ranks r >= 1, redrawn while r > 2^32, key = r - 1 (drawn
+                   in chunks of 2^22 from per-chunk child streams of the seed).
 * ``sorted`` / ``reverse`` -- the uniform draw sorted ascending / descending.
 * ``few``       -- 256 distinct values drawn uniformly, each key one of them.
 * ``skewed``    -- 64-bit keys whose top 16 bits take only 4 values (drawn uniformly)
@@ -20,6 +21,8 @@ Key distributions (``make_keys``):
 * ``narrow``    -- keys spread over only the low ``narrow_bits`` bits (default 20).
 """
 from __future__ import annotations
+
+import os
 
 import numpy as np
 
@@ -38,17 +41,29 @@ def _uniform(rng, n, bits):
     return rng.integers(0, np.iinfo(np.uint64).max, size=n, dtype=np.uint64, endpoint=True)
 
 
-def _zipf(rng, n, bits):
-    out = np.empty(n, dtype=np.uint32 if bits == 32 else np.uint64)
+def _zipf_chunk(seed, chunk, m, bits):
+    """m Zipf(1.1) keys from the chunk's own stream (redrawn while the rank is too big)."""
+    rng = _rng(seed, 1000 + chunk)
     limit = (1 << 32) if bits == 32 else (1 << 63)
-    filled = 0
-    while filled < n:
-        m = min(_CHUNK, n - filled)
-        r = rng.zipf(1.1, size=m + m // 8 + 16)
-        r = r[(r >= 1) & (r <= limit)][: n - filled]
-        out[filled: filled + r.size] = (r - 1).astype(out.dtype)
-        filled += r.size
-    return out
+    parts, got = [], 0
+    while got < m:
+        r = rng.zipf(1.1, size=m - got + (m - got) // 8 + 16)
+        r = r[(r >= 1) & (r <= limit)][: m - got]
+        parts.append(r)
+        got += r.size
+    return (np.concatenate(parts) - 1).astype(np.uint32 if bits == 32 else np.uint64)
+
+
+def _zipf(seed, n, bits):
+    # Chunks of 2^22 keys, each from its own child stream, drawn in parallel threads
+    # (numpy releases the GIL while drawing); the result depends only on (seed, n).
+    from concurrent.futures import ThreadPoolExecutor
+    nch = (n + _CHUNK - 1) // _CHUNK
+    sizes = [min(_CHUNK, n - c * _CHUNK) for c in range(nch)]
+    workers = max(1, min(16, os.cpu_count() or 1, nch))
+    with ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(lambda c: _zipf_chunk(seed, c, sizes[c], bits), range(nch)))
+    return np.concatenate(parts) if parts else np.empty(0, np.uint32 if bits == 32 else np.uint64)
 
 
 def make_keys(dist: str, n: int, key_bits: int = 32, seed: int = 0, *,
@@ -76,7 +91,7 @@ def make_keys(dist: str, n: int, key_bits: int = 32, seed: int = 0, *,
             return out
         return x.astype(np.uint32)
     if dist == "zipf":
-        return _zipf(rng, n, key_bits)
+        return _zipf(seed, n, key_bits)
     if dist == "sorted":
         return np.sort(_uniform(rng, n, key_bits))
     if dist == "reverse":
