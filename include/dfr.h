@@ -160,6 +160,9 @@ dfr_status dfr_poll(dfr_ctx* ctx, uint64_t ticket, double* latency_s);
  *                     first level (0 = estimate it, Sec. 3).  A value >= the number
  *                     of varying digits deals all of them (plain LSD, Sec. 2.1).
  *   "timing"          1 to record per-kernel durations with HIP events, 0 to stop.
+ *   "force_lookback"  1 to deal every level with decoupled look-back between tiles
+ *                     instead of scanning the tiles' bucket bases ahead of the deal
+ *                     (same result; for testing and measurement), 0 to restore.
  * Unknown names return DFR_E_UNSUPPORTED. */
 dfr_status dfr_set_option(dfr_ctx* ctx, const char* name, int64_t value);
 

@@ -49,6 +49,9 @@ struct LSeg {
 
 enum Stage { ST_COUNT = 0, ST_DEAL, ST_BUCKETS, ST_LOCAL, ST_OTHER, ST_N };
 
+// Largest segment, in tiles, whose bucket bases one block scans ahead of the deal.
+constexpr uint64_t kSegScanTiles = 1024;
+
 }  // namespace
 
 struct dfr_ctx {
@@ -74,6 +77,7 @@ struct dfr_ctx {
     size_t divert = 0;  // 0 = default N_d
     int force_d = 0;
     bool timing = false;
+    bool force_lookback = false;  // deal every level with decoupled look-back
 
     dfr_stats stats{};
     struct Ev {
@@ -470,10 +474,16 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // --- 1. count ---------------------------------------------------------------
     // Region A of the arena (kept for the whole level): histograms and OR/AND.
     const size_t hist_n = S * ndig * RADIX;
-    // A single segment is dealt without look-back: the count also keeps every tile's
-    // own digit counts, from which a scan gives each tile its bucket bases.
-    const bool single = S == 1;
-    const size_t tcnt_n = single ? tiles.size() * ndig * RADIX : 0;
+    // Levels are dealt without look-back where the tiles' bucket bases can be scanned
+    // ahead of the deal: the count also keeps every tile's own digit counts.  One
+    // segment: a three-kernel scan over all tiles; several segments of at most
+    // kSegScanTiles tiles each: one block per segment walks its tiles.
+    uint64_t max_seg_tiles = 0;
+    for (const LSeg& g : segs) max_seg_tiles = std::max<uint64_t>(max_seg_tiles, (g.len + j.tile - 1) / j.tile);
+    const bool single = S == 1 && !c->force_lookback;
+    const bool segscan = S > 1 && max_seg_tiles <= kSegScanTiles && !c->force_lookback;
+    const bool nolb = single || segscan;
+    const size_t tcnt_n = nolb ? tiles.size() * ndig * RADIX : 0;
     dfr_status st = arena_reserve(c, asize<uint32_t>(hist_n) + 2 * asize<uint64_t>(S) +
                                          asize<uint32_t>(tcnt_n) + asize<Tile>(tiles.size()), j.s);
     if (st) return st;
@@ -509,7 +519,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ca.hist = dhist;
         ca.seg_or = dor;
         ca.seg_and = dand;
-        ca.tile_hist = single ? (uint32_t*)(c->arena + off_tcnt) : nullptr;
+        ca.tile_hist = nolb ? (uint32_t*)(c->arena + off_tcnt) : nullptr;
         const uint32_t grid = (uint32_t)((tiles.size() + ca.tiles_per_block - 1) / ca.tiles_per_block);
         HIP_TRY(c, launch_count(kb, ca, grid, j.s));
     }
@@ -571,12 +581,14 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     std::vector<Seg> hs(S);
     bool all_full = true;
     uint64_t nslots = 0, medcap = 0, bcap = 0, bigcap = 0;
+    const std::vector<uint32_t> count_tile = first_tile;  // tiles of the counting list
     build_tiles(segs, active, j.tile, tiles, first_tile);
     for (uint32_t i : active) {
         Seg g{};
         g.start = segs[i].start;
         g.len = segs[i].len;
         g.first_tile = first_tile[i];
+        g.count_tile = count_tile[i];
         g.window_base = (uint32_t)nslots;
         g.npass = d;
         const std::vector<int>& v = V[i];
@@ -612,23 +624,19 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                           asize<uint32_t>(8);
     const uint32_t scan_tpb = 128;
     const uint32_t scan_nb = (uint32_t)((ntiles + scan_tpb - 1) / scan_tpb);
-    const size_t need_nolb = single ? asize<uint32_t>(ntiles * RADIX) * 2 +
-                                          asize<uint32_t>((size_t)scan_nb * RADIX) +
-                                          asize<uint32_t>(RADIX) + asize<uint64_t>(2)
-                                    : 0;
+    const size_t need_nolb = nolb ? asize<uint32_t>(ntiles * RADIX) * 2 +
+                                        (single ? asize<uint32_t>((size_t)scan_nb * RADIX) : 0)
+                                  : 0;
     st = arena_need(c, need_b + need_nolb, j.s);  // keeps region A
     if (st) return st;
     dhist = (uint32_t*)(c->arena + off_hist);
     uint32_t* tcnt = (uint32_t*)(c->arena + off_tcnt);
-    uint32_t *toff = nullptr, *tone = nullptr, *tpart = nullptr, *dummy_hist = nullptr;
-    uint64_t* dummy_oa = nullptr;
-    if (single) {
+    uint32_t *toff = nullptr, *tone = nullptr, *tpart = nullptr;
+    if (nolb) {
         toff = aalloc<uint32_t>(c, ntiles * RADIX);
         tone = aalloc<uint32_t>(c, ntiles * RADIX);
-        tpart = aalloc<uint32_t>(c, (size_t)scan_nb * RADIX);
-        dummy_hist = aalloc<uint32_t>(c, RADIX);
-        dummy_oa = aalloc<uint64_t>(c, 2);
     }
+    if (single) tpart = aalloc<uint32_t>(c, (size_t)scan_nb * RADIX);
     dtiles = aalloc<Tile>(c, ntiles);
     Seg* dsegs = aalloc<Seg>(c, S);
     uint32_t* lb = aalloc<uint32_t>(c, ntiles * RADIX + 1);
@@ -649,38 +657,31 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
 
     int cur = in;
     for (int p = 0; p < d; ++p) {
+        if (nolb && p > 0) {
+            // Per-tile counts of this pass's digit in the current order (the first
+            // pass takes them from the level's count).
+            Timed tc(c, j.s, ST_COUNT);
+            CountArgs ca{};
+            ca.keys = j.k[cur];
+            ca.tiles = dtiles;
+            ca.ntiles = (uint32_t)ntiles;
+            const uint32_t blocks = (uint32_t)std::min<size_t>(ntiles, 4096);
+            ca.tiles_per_block = (uint32_t)((ntiles + blocks - 1) / blocks);
+            ca.base_shift = hs[active[0]].shift[p];
+            ca.bits = RADIX_BITS;
+            ca.ndig = 1;
+            ca.tile_hist = tone;
+            ca.segs = single ? nullptr : dsegs;  // several segments: each its own digit
+            ca.pass = p;
+            const uint32_t grid = (uint32_t)((ntiles + ca.tiles_per_block - 1) / ca.tiles_per_block);
+            HIP_TRY(c, launch_count(kb, ca, grid, j.s));
+        }
         if (single) {
-            // Per-tile counts of this pass's digit: from the count at the first pass,
-            // from a count of the current order afterwards; then the tiles' bases.
             const Seg& g = hs[active[0]];
             TileScanArgs ta{};
-            if (p == 0) {
-                ta.cnt = tcnt;
-                ta.ndig = ndig;
-                ta.slot = g.hslot[0];
-            } else {
-                Timed tc(c, j.s, ST_COUNT);
-                HIP_TRY(c, launch_fill_u32(dummy_hist, 0, RADIX, j.s));
-                HIP_TRY(c, launch_fill_u64(dummy_oa, 0, 2, j.s));
-                CountArgs ca{};
-                ca.keys = j.k[cur];
-                ca.tiles = dtiles;
-                ca.ntiles = (uint32_t)ntiles;
-                const uint32_t blocks = (uint32_t)std::min<size_t>(ntiles, 4096);
-                ca.tiles_per_block = (uint32_t)((ntiles + blocks - 1) / blocks);
-                ca.base_shift = g.shift[p];
-                ca.bits = g.width[p];
-                ca.ndig = 1;
-                ca.hist = dummy_hist;
-                ca.seg_or = dummy_oa;
-                ca.seg_and = dummy_oa + 1;
-                ca.tile_hist = tone;
-                const uint32_t grid = (uint32_t)((ntiles + ca.tiles_per_block - 1) / ca.tiles_per_block);
-                HIP_TRY(c, launch_count(kb, ca, grid, j.s));
-                ta.cnt = tone;
-                ta.ndig = 1;
-                ta.slot = 0;
-            }
+            ta.cnt = p == 0 ? tcnt : tone;
+            ta.ndig = p == 0 ? ndig : 1;
+            ta.slot = p == 0 ? g.hslot[0] : 0;
             ta.ntiles = (uint32_t)ntiles;
             ta.tiles_per_block = scan_tpb;
             ta.nblocks = scan_nb;
@@ -689,12 +690,27 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             Timed ts(c, j.s, ST_OTHER);
             HIP_TRY(c, launch_tile_scan(ta, j.s));
             HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
+        } else if (segscan) {
+            SegScanArgs sa{};
+            sa.segs = dsegs;
+            sa.nsegs = (uint32_t)S;
+            sa.hist = dhist;
+            sa.hist_digits = ndig;
+            sa.cnt = p == 0 ? tcnt : tone;
+            sa.cnt_ndig = p == 0 ? ndig : 1;
+            sa.cnt_from_count_tiles = p == 0;
+            sa.pass = p;
+            sa.tile = j.tile;
+            sa.off = toff;
+            Timed ts(c, j.s, ST_OTHER);
+            HIP_TRY(c, launch_seg_scan(sa, j.s));
+            HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
         } else {
             HIP_TRY(c, launch_fill_u32(lb, 0, ntiles * RADIX + 1, j.s));
         }
         Timed tm(c, j.s, ST_DEAL, true);
         DealArgs da{};
-        da.off = single ? toff : nullptr;
+        da.off = nolb ? toff : nullptr;
         da.kin = j.k[cur];
         da.vin = j.v[cur];
         da.kout = j.k[1 - cur];
@@ -1289,6 +1305,10 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
     }
     if (!strcmp(name, "timing")) {
         c->timing = value != 0;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "force_lookback")) {
+        c->force_lookback = value != 0;
         return DFR_OK;
     }
     return DFR_E_UNSUPPORTED;

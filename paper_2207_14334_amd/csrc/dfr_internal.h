@@ -39,6 +39,7 @@ struct Seg {
     uint32_t window_base;  // first local-sort window slot of the segment
     int32_t lo_bit;        // after this level's deals, buckets agree on bits >= lo_bit
     int32_t npass;
+    uint32_t count_tile;   // index of the segment's first tile in the counting tile list
     int8_t shift[MAX_PASSES];  // digit of deal pass j: (key >> shift[j]) mod 2^width[j]
     int8_t width[MAX_PASSES];
     int8_t hslot[MAX_PASSES];  // histogram slot holding that digit's counts
@@ -70,6 +71,22 @@ struct CountArgs {
     void* seg_or;        // [seg] key type, OR of the segment's keys
     void* seg_and;       // [seg] key type, AND of the segment's keys
     uint32_t* tile_hist; // optional [tile][ndig][RADIX]: each tile's own counts
+    const Seg* segs;     // optional: digit shift per tile from segs[seg].shift[pass]
+    int32_t pass;
+};
+
+// Per-tile bucket bases for many segments: one block per segment walks its tiles.
+struct SegScanArgs {
+    const Seg* segs;
+    uint32_t nsegs;
+    const uint32_t* hist;  // per-segment digit histograms [seg][hist_digits][RADIX]
+    int32_t hist_digits;
+    const uint32_t* cnt;   // per-tile counts cnt[(t * cnt_ndig + slot) * RADIX + v]
+    int32_t cnt_ndig;
+    int32_t cnt_from_count_tiles;  // 1: tiles indexed as in the counting list, slot = hslot
+    int32_t pass;
+    uint32_t tile;         // records per tile
+    uint32_t* off;         // [tiles][RADIX], indexed by the deal's tile list
 };
 
 // Per-tile bucket bases from per-tile digit counts (one segment): off[t][v] is the
@@ -179,6 +196,7 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
 hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s);
+hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,

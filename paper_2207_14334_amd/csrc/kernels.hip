@@ -191,7 +191,8 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     const uint32_t t0 = blockIdx.x * a.tiles_per_block;
     if (t0 >= a.ntiles) return;
     const uint32_t t1 = a.ntiles - t0 < a.tiles_per_block ? a.ntiles : t0 + a.tiles_per_block;
-    const int ndig = a.ndig < NDIG ? a.ndig : NDIG, bits = a.bits, base = a.base_shift;
+    const int ndig = a.ndig < NDIG ? a.ndig : NDIG, bits = a.bits;
+    int base = a.base_shift;  // per tile from the segment when a.segs is set
     const uint32_t dmask = (1u << bits) - 1u;
     uint32_t* hw = s_h + w * SLICE;
 
@@ -219,7 +220,11 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
         for (int idx = tid; idx < ndig * RADIX; idx += THREADS) {
             const uint32_t sum = s_tot[idx];
             s_tot[idx] = 0;
-            if (sum) atomicAdd(&a.hist[(size_t)seg * ndig * RADIX + idx], sum);
+            if (sum && a.hist) atomicAdd(&a.hist[(size_t)seg * ndig * RADIX + idx], sum);
+        }
+        if (!a.seg_or) {  // per-tile counts only
+            __syncthreads();
+            return;
         }
         const K o = wave_or(vor), n = wave_and(vand);
         if (lane == 0) {
@@ -267,6 +272,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
             vor = 0;
             vand = ~K(0);
         }
+        if (a.segs) base = a.segs[tl.seg].shift[a.pass];
         const K* kp = (const K*)a.keys + tl.start;
         // Unaligned head, 16-byte aligned body, tail.
         uint32_t head = (uint32_t)(((16u - ((uintptr_t)kp & 15u)) & 15u) / KB);
@@ -1386,6 +1392,39 @@ __global__ __launch_bounds__(RADIX) void k_tile_scan_c(TileScanArgs a) {
             run += c[i];
         }
     }
+}
+
+__global__ __launch_bounds__(RADIX) void k_seg_scan(SegScanArgs a) {
+    __shared__ uint32_t s_part[RADIX / 64];
+    const uint32_t s = blockIdx.x, v = threadIdx.x;
+    const Seg* sg = a.segs + s;
+    const uint64_t len = sg->len;
+    if (len == 0) return;  // finished or empty segment: no tiles
+    const int slot = sg->hslot[a.pass];
+    uint32_t total;
+    const uint32_t start =
+        scan256_excl(a.hist[((size_t)s * a.hist_digits + slot) * RADIX + v], s_part, &total);
+    const uint32_t nt = (uint32_t)((len + a.tile - 1) / a.tile);
+    const uint32_t ct = a.cnt_from_count_tiles ? sg->count_tile : sg->first_tile;
+    const int cslot = a.cnt_from_count_tiles ? slot : 0;
+    uint32_t run = start;
+    for (uint32_t i0 = 0; i0 < nt; i0 += SCAN_BATCH) {
+        uint32_t c[SCAN_BATCH];
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i)
+            c[i] = i0 + i < nt ? a.cnt[((size_t)(ct + i0 + i) * a.cnt_ndig + cslot) * RADIX + v] : 0u;
+#pragma unroll
+        for (int i = 0; i < SCAN_BATCH; ++i) {
+            if (i0 + i < nt) a.off[(size_t)(sg->first_tile + i0 + i) * RADIX + v] = run;
+            run += c[i];
+        }
+    }
+}
+
+hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s) {
+    if (a.nsegs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_scan, dim3(a.nsegs), dim3(RADIX), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s) {

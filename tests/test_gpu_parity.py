@@ -261,3 +261,53 @@ def test_repeat_stress_many_tiles(torch, ctx, o):
                 first = (sk, sv)
             assert np.array_equal(sk, first[0]) and np.array_equal(sv, first[1]), dist
         assert o.check_index_payload(k, first[0], first[1]) is None, dist
+
+
+# --------------------------------------------------------------------------------------
+# Both ways of finding a tile's place in its buckets: scanned ahead of the deal from
+# per-tile counts, or decoupled look-back between tiles.  Same result either way.
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lookback", [0, 1])
+@pytest.mark.parametrize("case", ["single", "recursion", "segmented", "long_segment"])
+def test_deal_modes(torch, ctx, o, case, lookback):
+    kb = 4
+    opts = {"force_lookback": lookback}
+    if case == "single":
+        n = (1 << 21) + 333
+        off = None
+    elif case == "recursion":
+        n = (1 << 22) + 5
+        off = None
+        opts["force_top_digits"] = 1  # 256 large buckets: a multi-segment second level
+    elif case == "segmented":
+        lens = workloads.batch_lengths(300, 1, 1 << 18, 12)
+        off = workloads.segment_offsets(lens)
+        n = int(off[-1])
+    else:
+        # One segment over more tiles than a single block scans ahead: the level falls
+        # back to look-back between tiles even with the option off.
+        lens = np.array([5, (1 << 23) + 8192 * 3 + 11, 70000, 0, 9000], dtype=np.int64)
+        off = workloads.segment_offsets(lens)
+        n = int(off[-1])
+    k = workloads.make_keys("uniform", n, 8 * kb, 31)
+    v = workloads.index_payload(n)
+    say("deal_modes", case, lookback, n)
+    for name, val in opts.items():
+        ctx.set_option(name, val)
+    try:
+        dk, dv = dev(torch, k), dev(torch, v)
+        if off is None:
+            ctx.sort_(dk, dv)
+        else:
+            ctx.sort_segmented_(dk, dv, off)
+        torch.cuda.synchronize()
+        st = ctx.stats()
+    finally:
+        for name in opts:
+            ctx.set_option(name, 0)
+    if off is None:
+        rk, rv = o.stable_sort(k, v)
+    else:
+        rk, rv = o.segmented_sort(k, v, off)
+    assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), st
