@@ -267,25 +267,21 @@ std::vector<int> varying_digits(uint64_t vor, uint64_t vand, int kb) {
     return v;
 }
 
-// First level of a plain sort: the histograms of all digits are at hand.  The
-// collision probability of digit j, c_j = sum_v h_j[v]^2 / n^2, is the chance that
-// two random records share that digit; with digits taken as independent, a random
-// record's bucket after dealing the top digits holds about n * prod c_j records.  d is
-// the fewest top varying digits that bring this to N_d or below.  When dealing every
-// varying digit (plain LSD, Sec. 2.1) moves fewer bytes than DFR with that d, the plan
-// deals them all.
-int plan_first_level(const uint32_t* hist, size_t n, int kb, int vb, size_t divert,
-                     const std::vector<int>& V) {
+// Digits to deal for one segment of n records, from the collision probability of
+// each of its digits, coll[j] = sum_v h_j[v]^2 / n^2: the chance that two random
+// records share digit j.  With digits taken as independent, a random record's bucket
+// after dealing the top digits holds about n * prod coll[j] records; d is the fewest
+// top varying digits (V, most significant first) that bring this to N_d or below
+// (Sec. 3; Sec. 3.1 for N_d).  When dealing every varying digit (plain LSD, Sec. 2.1)
+// moves fewer bytes than DFR with that d, the plan deals them all.
+int plan_segment(const double* coll, size_t n, int kb, int vb, size_t divert,
+                 const std::vector<int>& V) {
     const int nv = (int)V.size();
     if (nv == 0) return 0;
     double expect = (double)n;
     int d = nv;
     for (int i = 0; i < nv; ++i) {
-        double c = 0;
-        const uint32_t* h = hist + (size_t)V[i] * RADIX;
-        for (int v = 0; v < RADIX; ++v) c += (double)h[v] * (double)h[v];
-        c /= (double)n * (double)n;
-        expect *= c;
+        expect *= coll[V[i]];
         if (expect <= (double)divert) {
             d = i + 1;
             break;
@@ -298,24 +294,16 @@ int plan_first_level(const uint32_t* hist, size_t n, int kb, int vb, size_t dive
     return d;
 }
 
-// Later levels and segmented sorts: the size-biased mean segment length, divided by
-// 256 per dealt digit (digits taken as uniform).
-int plan_later_level(const std::vector<uint64_t>& lens, size_t divert, int max_digits) {
-    double s1 = 0, s2 = 0;
-    for (uint64_t l : lens) {
-        s1 += (double)l;
-        s2 += (double)l * (double)l;
+// The same plan from the histograms of all kb digits (hist[j * 256 + v]).
+int plan_from_hist(const uint32_t* hist, size_t n, int kb, int vb, size_t divert,
+                   const std::vector<int>& V) {
+    double coll[8] = {0};
+    for (int j = 0; j < kb; ++j) {
+        double c = 0;
+        for (int v = 0; v < RADIX; ++v) c += (double)hist[j * RADIX + v] * (double)hist[j * RADIX + v];
+        coll[j] = n ? c / ((double)n * (double)n) : 0.0;
     }
-    double expect = s1 > 0 ? s2 / s1 : 0;
-    int d = max_digits;
-    for (int i = 0; i < max_digits; ++i) {
-        expect /= (double)RADIX;
-        if (expect <= (double)divert) {
-            d = i + 1;
-            break;
-        }
-    }
-    return std::max(1, d);
+    return plan_segment(coll, n, kb, vb, divert, V);
 }
 
 // ---------------------------------------------------------------------------------
@@ -485,10 +473,13 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const bool nolb = single || segscan;
     const size_t tcnt_n = nolb ? tiles.size() * ndig * RADIX : 0;
     dfr_status st = arena_reserve(c, asize<uint32_t>(hist_n) + 2 * asize<uint64_t>(S) +
-                                         asize<uint32_t>(tcnt_n) + asize<Tile>(tiles.size()), j.s);
+                                         asize<double>(S * ndig) + asize<uint32_t>(tcnt_n) +
+                                         asize<Tile>(tiles.size()), j.s);
     if (st) return st;
     const size_t off_hist = c->arena_used;
     aalloc<uint32_t>(c, hist_n);
+    const size_t off_coll = c->arena_used;
+    aalloc<double>(c, S * ndig);
     const size_t off_or = c->arena_used;
     aalloc<uint64_t>(c, S);
     const size_t off_and = c->arena_used;
@@ -523,18 +514,22 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         const uint32_t grid = (uint32_t)((tiles.size() + ca.tiles_per_block - 1) / ca.tiles_per_block);
         HIP_TRY(c, launch_count(kb, ca, grid, j.s));
     }
-    // Read back OR/AND (and, at the first level of a plain sort, the histograms).  The
-    // OR/AND words are key-sized: 32-bit keys use the low half of each 8-byte slot.
-    const bool want_hist = j.first_level && S == 1;
-    const size_t rb = S * 2 * sizeof(uint64_t) + (want_hist ? hist_n * sizeof(uint32_t) : 0) + 256;
+    // Each segment's digit collision probabilities, then read them back with OR/AND.
+    // The OR/AND words are key-sized: 32-bit keys use the low half of each 8-byte slot.
+    double* dcoll = (double*)(c->arena + off_coll);
+    {
+        Timed tm(c, j.s, ST_COUNT);
+        HIP_TRY(c, launch_collisions(dhist, (uint32_t)S, ndig, dcoll, j.s));
+    }
+    const size_t rb = S * 2 * sizeof(uint64_t) + S * ndig * sizeof(double) + 512;
     st = pin_reserve(c, rb, j.s);
     if (st) return st;
     uint64_t* h_or = palloc<uint64_t>(c, S);
     uint64_t* h_and = palloc<uint64_t>(c, S);
-    uint32_t* h_hist = want_hist ? palloc<uint32_t>(c, hist_n) : nullptr;
+    double* h_coll = palloc<double>(c, S * ndig);
     HIP_TRY(c, hipMemcpyAsync(h_or, dor, S * 8, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipMemcpyAsync(h_and, dand, S * 8, hipMemcpyDeviceToHost, j.s));
-    if (want_hist) HIP_TRY(c, hipMemcpyAsync(h_hist, dhist, hist_n * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipMemcpyAsync(h_coll, dcoll, S * ndig * sizeof(double), hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipStreamSynchronize(j.s));
     std::vector<uint64_t> vor(S), vand(S);
     for (size_t i = 0; i < S; ++i) {
@@ -546,25 +541,34 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             vand[i] = h_and[i];
         }
     }
-    std::vector<uint32_t> hist0;
-    if (want_hist) hist0.assign(h_hist, h_hist + hist_n);
+    const std::vector<double> coll(h_coll, h_coll + S * ndig);
     synced(c);
 
     // --- 2. plan ------------------------------------------------------------------
+    // Per segment: its varying digits (from OR/AND) and the digits d_s to deal (forced
+    // at the first level when asked).  The level deals d = max d_s passes.  A segment
+    // that needs fewer sits out the first passes in pairs, so that it ends in the same
+    // buffer as the others, and deals its lowest selected digit twice when d - d_s is
+    // odd (a second deal on one digit changes nothing: the deal is stable).
     std::vector<std::vector<int>> V(S);
     std::vector<std::pair<uint64_t, uint64_t>> finished;  // all-equal segments
     std::vector<uint32_t> active;
-    std::vector<uint64_t> lens;
-    int maxv = 0;
+    std::vector<int> dsel(S, 0);
+    int d = 1;
     for (size_t i = 0; i < S; ++i) {
         V[i] = varying_digits(vor[i], vand[i], kb);
         if (V[i].empty()) {
             finished.push_back({segs[i].start, segs[i].len});
-        } else {
-            active.push_back((uint32_t)i);
-            lens.push_back(segs[i].len);
-            maxv = std::max(maxv, (int)V[i].size());
+            continue;
         }
+        active.push_back((uint32_t)i);
+        const int nv = (int)V[i].size();
+        int di = (j.first_level && j.top_d_forced > 0)
+                     ? j.top_d_forced
+                     : plan_segment(&coll[i * ndig], segs[i].len, kb, j.vb, j.divert, V[i]);
+        di = std::max(1, std::min(std::min(di, nv), MAX_PASSES));
+        dsel[i] = di;
+        d = std::max(d, di);
     }
     c->arena_used = region_a;  // the counting tile list is no longer needed
     if (in == 1) {
@@ -572,53 +576,66 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         if (st) return st;
     }
     if (active.empty()) return DFR_OK;
-    int d = want_hist ? plan_first_level(hist0.data(), segs[0].len, kb, j.vb, j.divert, V[0])
-                      : plan_later_level(lens, j.divert, maxv);
-    if (j.first_level && j.top_d_forced > 0) d = j.top_d_forced;
-    d = std::max(1, std::min(std::min(d, maxv), MAX_PASSES));
     if (j.first_level) c->stats.top_digits = d;
+    auto skip_of = [&](uint32_t i) { return (d - dsel[i]) & ~1; };
+    // Segments that sit out more passes come later, so pass p deals a prefix of tiles.
+    std::stable_sort(active.begin(), active.end(),
+                     [&](uint32_t x, uint32_t y) { return skip_of(x) < skip_of(y); });
 
     std::vector<Seg> hs(S);
+    std::vector<char> full(S, 0);
     bool all_full = true;
     uint64_t nslots = 0, medcap = 0, bcap = 0, bigcap = 0;
     const std::vector<uint32_t> count_tile = first_tile;  // tiles of the counting list
     build_tiles(segs, active, j.tile, tiles, first_tile);
+    std::vector<uint32_t> pass_tiles(d, 0);  // tiles dealt in pass p
     for (uint32_t i : active) {
+        const uint64_t nt = (segs[i].len + j.tile - 1) / j.tile;
+        for (int p = skip_of(i); p < d; ++p) pass_tiles[p] += (uint32_t)nt;
         Seg g{};
         g.start = segs[i].start;
         g.len = segs[i].len;
         g.first_tile = first_tile[i];
         g.count_tile = count_tile[i];
-        g.window_base = (uint32_t)nslots;
-        g.npass = d;
+        const int skip = skip_of(i), np = d - skip, di = dsel[i];
+        g.first_pass = skip;
+        g.npass = np;
         const std::vector<int>& v = V[i];
         const int nv = (int)v.size();
-        // Selected digits, most significant first; the lowest repeats if fewer vary
-        // (dealing twice on one digit changes nothing: the deal is stable).
-        std::vector<int> sel;
-        for (int q = 0; q < d; ++q) sel.push_back(v[std::min(q, nv - 1)]);
+        // Selected digits, most significant first; the lowest once more if np > d_s.
+        std::vector<int> sel(v.begin(), v.begin() + di);
+        if (np > di) sel.push_back(sel.back());
         for (int p = 0; p < d; ++p) {  // LSD order: least significant selected first
-            const int dig = sel[d - 1 - p];
+            const int q = std::max(p, skip) - skip;
+            const int dig = sel[np - 1 - q];
             g.shift[p] = (int8_t)(8 * dig);
             g.width[p] = 8;
             g.hslot[p] = (int8_t)dig;
         }
-        const bool full = nv <= d;
-        g.lo_bit = full ? 0 : 8 * sel[d - 1];
-        all_full = all_full && full;
-        nslots += (segs[i].len + j.wsmall - 1) / j.wsmall;
-        medcap += segs[i].len / (j.wsmall + 1);
-        bigcap += segs[i].len / (j.cap + 1);
-        const int distinct = std::min(d, nv);
-        const uint64_t maxb = distinct >= 8 ? ~0ull : (1ull << (8 * distinct));
-        bcap += std::min<uint64_t>(segs[i].len, maxb);
+        full[i] = nv <= di;
+        g.lo_bit = full[i] ? 0 : 8 * v[di - 1];
+        if (!full[i]) {
+            all_full = false;
+            g.window_base = (uint32_t)nslots;
+            nslots += (segs[i].len + j.wsmall - 1) / j.wsmall;
+            medcap += segs[i].len / (j.wsmall + 1);
+            bigcap += segs[i].len / (j.cap + 1);
+            const uint64_t maxb = di >= 8 ? ~0ull : (1ull << (8 * di));
+            bcap += std::min<uint64_t>(segs[i].len, maxb);
+        }
         hs[i] = g;
     }
+    // Tiles whose buckets are found after the deals: those of segments not yet sorted.
+    std::vector<Tile> htiles;
+    for (const Tile& t : tiles)
+        if (!full[t.seg]) htiles.push_back(t);
+    const uint64_t nht = htiles.size();
 
     // --- 3. deal ------------------------------------------------------------------
     const uint64_t ntiles = tiles.size();
-    const size_t need_b = asize<Tile>(ntiles) + asize<Seg>(S) + asize<uint32_t>(ntiles * RADIX + 1) +
-                          asize<uint64_t>(ntiles + 1) + asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
+    const size_t need_b = asize<Tile>(ntiles) + asize<Tile>(nht) + asize<Seg>(S) +
+                          asize<uint32_t>(ntiles * RADIX + 1) +
+                          asize<uint64_t>(nht + 1) + asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
                           2 * asize<Big>(bigcap) + 2 * asize<uint32_t>(nslots + medcap) +
                           asize<uint32_t>(8);
@@ -638,9 +655,10 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     }
     if (single) tpart = aalloc<uint32_t>(c, (size_t)scan_nb * RADIX);
     dtiles = aalloc<Tile>(c, ntiles);
+    Tile* dhtiles = aalloc<Tile>(c, nht);
     Seg* dsegs = aalloc<Seg>(c, S);
     uint32_t* lb = aalloc<uint32_t>(c, ntiles * RADIX + 1);
-    uint64_t* lb64 = aalloc<uint64_t>(c, ntiles + 1);
+    uint64_t* lb64 = aalloc<uint64_t>(c, nht + 1);
     uint64_t* dbstart = aalloc<uint64_t>(c, bcap);
     uint32_t* dbseg = aalloc<uint32_t>(c, bcap);
     uint32_t* cfirst = aalloc<uint32_t>(c, nslots);
@@ -652,11 +670,13 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work
     st = upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
+    if (!st) st = upload(j, dhtiles, htiles.data(), nht * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
     if (st) return st;
 
     int cur = in;
     for (int p = 0; p < d; ++p) {
+        const uint32_t ntp = pass_tiles[p];
         if (nolb && p > 0) {
             // Per-tile counts of this pass's digit in the current order (the first
             // pass takes them from the level's count).
@@ -664,16 +684,16 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             CountArgs ca{};
             ca.keys = j.k[cur];
             ca.tiles = dtiles;
-            ca.ntiles = (uint32_t)ntiles;
-            const uint32_t blocks = (uint32_t)std::min<size_t>(ntiles, 4096);
-            ca.tiles_per_block = (uint32_t)((ntiles + blocks - 1) / blocks);
+            ca.ntiles = ntp;
+            const uint32_t blocks = std::min<uint32_t>(ntp, 4096);
+            ca.tiles_per_block = (ntp + blocks - 1) / blocks;
             ca.base_shift = hs[active[0]].shift[p];
             ca.bits = RADIX_BITS;
             ca.ndig = 1;
             ca.tile_hist = tone;
             ca.segs = single ? nullptr : dsegs;  // several segments: each its own digit
             ca.pass = p;
-            const uint32_t grid = (uint32_t)((ntiles + ca.tiles_per_block - 1) / ca.tiles_per_block);
+            const uint32_t grid = (ntp + ca.tiles_per_block - 1) / ca.tiles_per_block;
             HIP_TRY(c, launch_count(kb, ca, grid, j.s));
         }
         if (single) {
@@ -716,7 +736,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         da.kout = j.k[1 - cur];
         da.vout = j.v[1 - cur];
         da.tiles = dtiles;
-        da.ntiles = (uint32_t)ntiles;
+        da.ntiles = ntp;
         da.segs = dsegs;
         da.hist = dhist;
         da.hist_digits = ndig;
@@ -730,31 +750,30 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     }
     *next_in = cur;
 
-    if (all_full) {
-        // Every varying digit was dealt: the segments are sorted (plain LSD).
-        if (cur == 1) {
-            std::vector<std::pair<uint64_t, uint64_t>> r;
-            for (uint32_t i : active) r.push_back({segs[i].start, segs[i].len});
-            st = copy_back(j, r);
-            if (st) return st;
-        }
-        return DFR_OK;
+    // Segments whose every varying digit was dealt are sorted (plain LSD, Sec. 2.1).
+    if (cur == 1) {
+        std::vector<std::pair<uint64_t, uint64_t>> r;
+        for (uint32_t i : active)
+            if (full[i]) r.push_back({segs[i].start, segs[i].len});
+        st = copy_back(j, r);
+        if (st) return st;
     }
+    if (all_full) return DFR_OK;
 
     // --- 4. buckets ---------------------------------------------------------------
     {
         Timed tm(c, j.s, ST_BUCKETS);
         HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
-        HIP_TRY(c, launch_fill_u64(lb64, 0, ntiles + 1, j.s));
+        HIP_TRY(c, launch_fill_u64(lb64, 0, nht + 1, j.s));
         HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
         HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
         HeadArgs ha{};
         ha.keys = j.k[cur];
-        ha.tiles = dtiles;
-        ha.ntiles = (uint32_t)ntiles;
+        ha.tiles = dhtiles;
+        ha.ntiles = (uint32_t)nht;
         ha.segs = dsegs;
         ha.lookback = lb64;
-        ha.ticket = (uint32_t*)(lb64 + ntiles);
+        ha.ticket = (uint32_t*)(lb64 + nht);
         ha.bstart = dbstart;
         ha.bseg = dbseg;
         ha.bcap = bcap;
@@ -1333,7 +1352,7 @@ dfr_status dfr_plan_top_digits(const uint32_t* hist, size_t n, int key_bytes, in
     }
     const size_t cap = local_cap(key_bytes, val_bytes);
     const size_t divert = divert_records ? std::min(divert_records, cap) : default_divert(key_bytes, val_bytes);
-    *top_digits = n <= cap ? 0 : plan_first_level(hist, n, key_bytes, val_bytes, divert, V);
+    *top_digits = n <= cap ? 0 : plan_from_hist(hist, n, key_bytes, val_bytes, divert, V);
     if (varying) *varying = (int32_t)V.size();
     return DFR_OK;
 }

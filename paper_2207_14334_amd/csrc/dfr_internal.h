@@ -40,6 +40,7 @@ struct Seg {
     int32_t lo_bit;        // after this level's deals, buckets agree on bits >= lo_bit
     int32_t npass;
     uint32_t count_tile;   // index of the segment's first tile in the counting tile list
+    int32_t first_pass;    // deal passes before this one leave the segment where it is
     int8_t shift[MAX_PASSES];  // digit of deal pass j: (key >> shift[j]) mod 2^width[j]
     int8_t width[MAX_PASSES];
     int8_t hslot[MAX_PASSES];  // histogram slot holding that digit's counts
@@ -197,6 +198,9 @@ hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
 hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s);
 hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s);
+// coll[s * ndig + j] = sum_v h[v]^2 / (sum_v h[v])^2 for each segment's digit-j histogram.
+hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, double* coll,
+                             hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,

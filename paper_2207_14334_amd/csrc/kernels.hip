@@ -1399,7 +1399,7 @@ __global__ __launch_bounds__(RADIX) void k_seg_scan(SegScanArgs a) {
     const uint32_t s = blockIdx.x, v = threadIdx.x;
     const Seg* sg = a.segs + s;
     const uint64_t len = sg->len;
-    if (len == 0) return;  // finished or empty segment: no tiles
+    if (len == 0 || a.pass < sg->first_pass) return;  // no tiles in this pass
     const int slot = sg->hslot[a.pass];
     uint32_t total;
     const uint32_t start =
@@ -1419,6 +1419,42 @@ __global__ __launch_bounds__(RADIX) void k_seg_scan(SegScanArgs a) {
             run += c[i];
         }
     }
+}
+
+// Collision probability of each segment's digits (the chance that two records drawn
+// at random share the digit), the input of the plan's bucket-size estimate (Sec. 3).
+__global__ __launch_bounds__(RADIX) void k_collisions(const uint32_t* hist, int ndig, double* coll) {
+    __shared__ double s_sq[RADIX / 64], s_n[RADIX / 64];
+    const uint32_t s = blockIdx.x, v = threadIdx.x, lane = v & 63, w = v >> 6;
+    for (int j = 0; j < ndig; ++j) {
+        const double h = (double)hist[((size_t)s * ndig + j) * RADIX + v];
+        double sq = h * h, n = h;
+        for (int o = 32; o > 0; o >>= 1) {
+            sq += __shfl_xor(sq, o);
+            n += __shfl_xor(n, o);
+        }
+        if (lane == 0) {
+            s_sq[w] = sq;
+            s_n[w] = n;
+        }
+        __syncthreads();
+        if (v == 0) {
+            double tsq = 0, tn = 0;
+            for (int i = 0; i < RADIX / 64; ++i) {
+                tsq += s_sq[i];
+                tn += s_n[i];
+            }
+            coll[(size_t)s * ndig + j] = tn > 0 ? tsq / (tn * tn) : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, double* coll,
+                             hipStream_t s) {
+    if (nsegs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_collisions, dim3(nsegs), dim3(RADIX), 0, s, hist, ndig, coll);
+    return hipGetLastError();
 }
 
 hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s) {

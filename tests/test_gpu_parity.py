@@ -311,3 +311,27 @@ def test_deal_modes(torch, ctx, o, case, lookback):
     else:
         rk, rv = o.segmented_sort(k, v, off)
     assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), st
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_segmented_mixed_plans(torch, ctx, o, bits):
+    """Segments of different distributions get different digit plans in one level
+    (full LSD for some, one or two top digits for others, passes sat out in pairs
+    and an odd leftover dealt twice); every segment must still match the oracle."""
+    parts = [("zipf", 300000), ("uniform", 300000), ("few", 200000), ("narrow", 100000),
+             ("equal", 50000), ("sorted", 250000), ("uniform", 20000), ("normal", 9000),
+             ("zipf", 9000), ("reverse", 70000)]
+    if bits == 64:
+        parts.append(("skewed", 200000))
+    keys = [workloads.make_keys(dname, m, bits, 40 + i) for i, (dname, m) in enumerate(parts)]
+    lens = np.array([m for _, m in parts], dtype=np.int64)
+    off = workloads.segment_offsets(lens)
+    k = np.concatenate(keys)
+    n = k.size
+    v = workloads.index_payload(n, bits)
+    say("segmented_mixed", bits, n)
+    dk, dv = dev(torch, k), dev(torch, v)
+    ctx.sort_segmented_(dk, dv, off)
+    torch.cuda.synchronize()
+    rk, rv = o.segmented_sort(k, v, off)
+    assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), ctx.stats()
