@@ -163,7 +163,17 @@ dfr_status dfr_poll(dfr_ctx* ctx, uint64_t ticket, double* latency_s);
  *   "force_lookback"  1 to deal every level with decoupled look-back between tiles
  *                     instead of scanning the tiles' bucket bases ahead of the deal
  *                     (same result; for testing and measurement), 0 to restore.
- * Unknown names return DFR_E_UNSUPPORTED. */
+ *   "radix_bits"      digit width b of the deal passes, 4..8 with at most 8 digits
+ *                     per key (so 8 for 64-bit keys); the paper's digits are 8 bits
+ *                     (Sec. 4).  0 = tuned or default.
+ *   "tile_records"    records per deal tile: dfr_deal_tile_records(kb, vb) or half
+ *                     of it.  0 = tuned or default.
+ *   "window_records"  width of the windows that pack runs of small buckets into
+ *                     local-sort chunks (Sec. 3: runs of small buckets), 16 ..
+ *                     capacity / 2.  0 = tuned or default.
+ * The last three, with "divert_records", override a tuned setting (dfr_autotune);
+ * a combination that no kernel supports falls back to the defaults.  None of them
+ * changes the result.  Unknown names return DFR_E_UNSUPPORTED. */
 dfr_status dfr_set_option(dfr_ctx* ctx, const char* name, int64_t value);
 
 /* What the last sort call did.  Kernel times are in milliseconds and are filled
@@ -197,6 +207,50 @@ dfr_status dfr_plan_top_digits(const uint32_t* hist, size_t n, int key_bytes, in
 
 /* Records one local-sort work item may hold (its LDS capacity) for these widths. */
 size_t dfr_local_sort_capacity(int key_bytes, int val_bytes);
+
+/* Records per deal tile by default for these widths (half of it is also built). */
+size_t dfr_deal_tile_records(int key_bytes, int val_bytes);
+
+/* ---------------------------------------------------------------------------------
+ * Autotuning of the launch settings.  None of these settings changes the result;
+ * they trade deal passes against local-sort work (Sec. 3, Sec. 3.1) and pick tile
+ * shapes.  Settings are kept per (key bytes, value bytes, size class), where the size
+ * class of a call is floor(log2) of the size-biased mean length, sum(len^2)/sum(len),
+ * of its segments longer than one record (a plain sort is one segment).
+ * ------------------------------------------------------------------------------- */
+#define DFR_TUNE_CLASSES 32
+
+typedef struct {
+    int32_t radix_bits;       /* digit width b of the deal passes                 */
+    uint32_t tile_records;    /* records per deal tile                            */
+    uint64_t divert_records;  /* N_d                                              */
+    uint64_t window_records;  /* small-bucket window width                        */
+    double ms;                /* measured time of one sort (dfr_autotune), else 0 */
+    double ms_default;        /* same input with the default settings, else 0     */
+} dfr_tune;
+
+/* Size class of a segmented call (seg_offsets as for dfr_sort_segmented_*). */
+int32_t dfr_size_class(const uint64_t* seg_offsets, size_t num_segments);
+
+/* Time sorts of copies of the given data (keys/vals: device, vals NULL for key-only;
+ * seg_offsets: host, num_segments + 1 entries, {0, n} for a plain sort) under
+ * candidate settings, by coordinate descent from the defaults, `reps` timed sorts per
+ * candidate (minimum taken; <= 0 means 2).  The caller's buffers are only read.  The
+ * best setting is stored in the context for this (widths, size class) and returned in
+ * *out.  Allocates and frees two device buffers the size of the data, and uses the
+ * context's cached temp buffer.  Blocks the host until done. */
+dfr_status dfr_autotune(dfr_ctx* ctx, int key_bytes, int val_bytes, const void* keys,
+                        const void* vals, const uint64_t* seg_offsets, size_t num_segments,
+                        int reps, void* stream, dfr_tune* out);
+
+/* Read the stored setting for (widths, size class); DFR_E_NOT_FOUND if none. */
+dfr_status dfr_get_tune(const dfr_ctx* ctx, int key_bytes, int val_bytes, int32_t size_class,
+                        dfr_tune* out);
+
+/* Store a setting (e.g. one saved from an earlier process on the same GPU model);
+ * DFR_E_INVALID_ARG if no kernel supports it.  tune == NULL removes the entry. */
+dfr_status dfr_set_tune(dfr_ctx* ctx, int key_bytes, int val_bytes, int32_t size_class,
+                        const dfr_tune* tune);
 
 #ifdef __cplusplus
 }

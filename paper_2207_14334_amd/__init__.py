@@ -34,8 +34,11 @@ EXPORTED = [
     "dfr_create", "dfr_destroy", "dfr_status_string", "dfr_last_error", "dfr_temp_bytes",
     "dfr_sort_u32", "dfr_sort_u64", "dfr_sort_segmented_u32", "dfr_sort_segmented_u64",
     "dfr_count", "dfr_deal", "dfr_submit", "dfr_poll", "dfr_set_option", "dfr_get_stats",
-    "dfr_plan_top_digits", "dfr_local_sort_capacity",
+    "dfr_plan_top_digits", "dfr_local_sort_capacity", "dfr_deal_tile_records",
+    "dfr_size_class", "dfr_autotune", "dfr_get_tune", "dfr_set_tune",
 ]
+
+TUNE_CLASSES = 32
 
 
 class DfrError(RuntimeError):
@@ -56,6 +59,19 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("radix_bits", ctypes.c_int32), ("tile_records", ctypes.c_uint32),
+                ("divert_records", ctypes.c_uint64), ("window_records", ctypes.c_uint64),
+                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{f: d.get(f, 0) for f, _ in cls._fields_})
 
 
 class Request(ctypes.Structure):
@@ -110,6 +126,16 @@ def lib():
     L.dfr_get_stats.restype = S
     L.dfr_plan_top_digits.argtypes = [P, Z, I, I, Z, ctypes.POINTER(S), ctypes.POINTER(S)]
     L.dfr_plan_top_digits.restype = S
+    L.dfr_deal_tile_records.argtypes = [I, I]
+    L.dfr_deal_tile_records.restype = Z
+    L.dfr_size_class.argtypes = [P, Z]
+    L.dfr_size_class.restype = S
+    L.dfr_autotune.argtypes = [P, I, I, P, P, P, Z, I, P, ctypes.POINTER(Tune)]
+    L.dfr_autotune.restype = S
+    L.dfr_get_tune.argtypes = [P, I, I, S, ctypes.POINTER(Tune)]
+    L.dfr_get_tune.restype = S
+    L.dfr_set_tune.argtypes = [P, I, I, S, ctypes.POINTER(Tune)]
+    L.dfr_set_tune.restype = S
     _lib = L
     return L
 
@@ -124,6 +150,20 @@ def temp_bytes(n: int, key_bytes: int, val_bytes: int) -> int:
 
 def local_sort_capacity(key_bytes: int, val_bytes: int) -> int:
     return int(lib().dfr_local_sort_capacity(key_bytes, val_bytes))
+
+
+def deal_tile_records(key_bytes: int, val_bytes: int) -> int:
+    return int(lib().dfr_deal_tile_records(key_bytes, val_bytes))
+
+
+def size_class(offsets) -> int:
+    """Size class of a segmented call with host ``offsets`` (num_segments + 1 entries)."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    c = int(lib().dfr_size_class(off.ctypes.data, off.size - 1))
+    if c < 0:
+        raise DfrError(E_INVALID_ARG, "size_class: malformed offsets")
+    return c
 
 
 def plan_top_digits(hist, n: int, key_bytes: int, val_bytes: int, divert: int = 0):
@@ -242,6 +282,65 @@ class Context:
         self._raise(f(self._h, keys.data_ptr(), vp, off.ctypes.data, off.size - 1, tp, tb,
                       self._stream(stream)), "sort_segmented")
         return keys, vals
+
+    # -- tuning --------------------------------------------------------------------
+    def autotune(self, keys, vals=None, offsets=None, reps: int = 2, stream=None) -> dict:
+        """Tune the launch settings on copies of ``keys``/``vals`` (only read) split by
+        host ``offsets`` (None: one segment).  Stores the result in the context and
+        returns it as a dict."""
+        import numpy as np
+        _check_tensor(keys, "keys")
+        kb = _width(keys)
+        vb, vp = 0, None
+        if vals is not None:
+            _check_tensor(vals, "vals")
+            vb, vp = _width(vals), vals.data_ptr()
+        off = np.ascontiguousarray([0, keys.numel()] if offsets is None else offsets, dtype=np.uint64)
+        t = Tune()
+        self._raise(lib().dfr_autotune(self._h, kb, vb, keys.data_ptr(), vp, off.ctypes.data,
+                                       off.size - 1, int(reps), self._stream(stream),
+                                       ctypes.byref(t)), "autotune")
+        return t.as_dict()
+
+    def get_tune(self, key_bytes: int, val_bytes: int, size_class: int):
+        t = Tune()
+        st = lib().dfr_get_tune(self._h, key_bytes, val_bytes, size_class, ctypes.byref(t))
+        if st == E_NOT_FOUND:
+            return None
+        self._raise(st, "get_tune")
+        return t.as_dict()
+
+    def set_tune(self, key_bytes: int, val_bytes: int, size_class: int, tune):
+        t = None if tune is None else ctypes.byref(Tune.from_dict(tune))
+        self._raise(lib().dfr_set_tune(self._h, key_bytes, val_bytes, size_class, t), "set_tune")
+
+    def save_tuning(self, path: str):
+        """Write every stored setting, with the device's architecture name, as JSON."""
+        import json
+        import torch
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName
+        entries = []
+        for kb in (4, 8):
+            for vb in (0, 4, 8):
+                for c in range(TUNE_CLASSES):
+                    t = self.get_tune(kb, vb, c)
+                    if t is not None:
+                        entries.append({"key_bytes": kb, "val_bytes": vb, "size_class": c, **t})
+        with open(path, "w") as f:
+            json.dump({"arch": arch, "entries": entries}, f, indent=1)
+
+    def load_tuning(self, path: str) -> int:
+        """Load settings saved by save_tuning on the same architecture; returns how many."""
+        import json
+        import torch
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("arch") != arch:
+            return 0
+        for e in d["entries"]:
+            self.set_tune(e["key_bytes"], e["val_bytes"], e["size_class"], e)
+        return len(d["entries"])
 
     # -- stages --------------------------------------------------------------------
     def count(self, keys, bits: int = 8, num_digits: int | None = None, stream=None):

@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -78,6 +79,10 @@ struct dfr_ctx {
     int force_d = 0;
     bool timing = false;
     bool force_lookback = false;  // deal every level with decoupled look-back
+    int radix_bits = 0;           // 0 = tuned or default
+    uint32_t tile_records = 0;
+    size_t window = 0;
+    std::map<uint32_t, dfr_tune> tunes;  // tuned settings per (kb, vb, size class)
 
     dfr_stats stats{};
     struct Ev {
@@ -259,11 +264,16 @@ size_t default_divert(int kb, int vb) { return local_cap(kb, vb) * 3 / 4; }
 // ---------------------------------------------------------------------------------
 
 // Varying 8-bit digits of a segment, most significant first, from its OR and AND.
-std::vector<int> varying_digits(uint64_t vor, uint64_t vand, int kb) {
+// Digits of `rb` bits, digit j holding key bits [j*rb, min((j+1)*rb, 8*kb)).
+int num_digits(int kb, int rb) { return (8 * kb + rb - 1) / rb; }
+
+// Digits on which some two keys differ, most significant first.
+std::vector<int> varying_digits(uint64_t vor, uint64_t vand, int kb, int rb) {
     std::vector<int> v;
     const uint64_t var = vor ^ vand;
-    for (int j = kb - 1; j >= 0; --j)
-        if ((var >> (8 * j)) & 0xff) v.push_back(j);
+    const uint64_t mask = (1ull << rb) - 1;
+    for (int j = num_digits(kb, rb) - 1; j >= 0; --j)
+        if ((var >> (rb * j)) & mask) v.push_back(j);
     return v;
 }
 
@@ -307,6 +317,58 @@ int plan_from_hist(const uint32_t* hist, size_t n, int kb, int vb, size_t divert
 }
 
 // ---------------------------------------------------------------------------------
+// Tuning: digit width, deal tile, diversion threshold and window width per (key
+// bytes, value bytes, size class).  Explicit options override a tuned entry, which
+// overrides the defaults.
+// ---------------------------------------------------------------------------------
+uint32_t tune_key(int kb, int vb, int cls) { return (uint32_t)(kb << 16 | vb << 8 | cls); }
+
+dfr_tune default_tune(int kb, int vb) {
+    dfr_tune t{};
+    t.radix_bits = RADIX_BITS;
+    t.tile_records = deal_tile_records(kb, vb);
+    t.divert_records = default_divert(kb, vb);
+    t.window_records = local_cap(kb, vb) / 4;
+    return t;
+}
+
+// A tuning is usable when every kernel it selects exists and the local sort can hold
+// every chunk it makes: a window's chunk spans less than two windows.
+bool tune_valid(const dfr_tune& t, int kb, int vb) {
+    const size_t cap = local_cap(kb, vb);
+    return t.radix_bits >= 4 && t.radix_bits <= RADIX_BITS && num_digits(kb, t.radix_bits) <= MAX_PASSES &&
+           deal_tile_supported(kb, vb, t.tile_records) && t.divert_records >= 1 &&
+           t.divert_records <= cap && t.window_records >= 16 && t.window_records <= cap / 2;
+}
+
+// floor(log2) of the size-biased mean length of the segments that need sorting.
+int size_class(const std::vector<LSeg>& segs) {
+    double s1 = 0, s2 = 0;
+    for (const LSeg& g : segs)
+        if (g.len > 1) {
+            s1 += (double)g.len;
+            s2 += (double)g.len * (double)g.len;
+        }
+    if (s1 <= 0) return 0;
+    return std::max(0, std::min(DFR_TUNE_CLASSES - 1, (int)std::floor(std::log2(s2 / s1))));
+}
+
+dfr_tune effective_tune(const dfr_ctx* c, int kb, int vb, int cls) {
+    dfr_tune t = default_tune(kb, vb);
+    auto it = c->tunes.find(tune_key(kb, vb, cls));
+    if (it != c->tunes.end()) t = it->second;
+    if (c->radix_bits) t.radix_bits = c->radix_bits;
+    if (c->tile_records) t.tile_records = c->tile_records;
+    if (c->divert) t.divert_records = c->divert;
+    if (c->window) t.window_records = c->window;
+    const size_t cap = local_cap(kb, vb);
+    t.divert_records = std::min<uint64_t>(t.divert_records, cap);
+    t.window_records = std::min<uint64_t>(t.window_records, cap / 2);
+    if (!tune_valid(t, kb, vb)) t = default_tune(kb, vb);
+    return t;
+}
+
+// ---------------------------------------------------------------------------------
 // One sort (plain or segmented), level by level.
 // ---------------------------------------------------------------------------------
 struct Job {
@@ -316,6 +378,7 @@ struct Job {
     void* v[2];
     hipStream_t s;
     uint32_t tile;  // deal tile records
+    int rb = RADIX_BITS;  // digit width of the deal passes
     size_t cap;     // local sort capacity
     size_t wsmall;  // small bucket limit = window width
     size_t divert;
@@ -451,7 +514,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     dfr_ctx* c = j.c;
     const size_t S = segs.size();
     const int kb = j.kb;
-    const int ndig = kb;  // every 8-bit digit
+    const int rb = j.rb;
+    const int ndig = num_digits(kb, rb);  // every digit of the key
     *next_in = in;
     std::vector<uint32_t> all_ids(S);
     for (size_t i = 0; i < S; ++i) all_ids[i] = (uint32_t)i;
@@ -505,7 +569,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         const uint32_t blocks = (uint32_t)std::min<size_t>(tiles.size(), 2048);
         ca.tiles_per_block = (uint32_t)((tiles.size() + blocks - 1) / blocks);
         ca.base_shift = 0;
-        ca.bits = RADIX_BITS;
+        ca.bits = rb;
         ca.ndig = ndig;
         ca.hist = dhist;
         ca.seg_or = dor;
@@ -521,8 +585,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         Timed tm(c, j.s, ST_COUNT);
         HIP_TRY(c, launch_collisions(dhist, (uint32_t)S, ndig, dcoll, j.s));
     }
-    const size_t rb = S * 2 * sizeof(uint64_t) + S * ndig * sizeof(double) + 512;
-    st = pin_reserve(c, rb, j.s);
+    const size_t readback = S * 2 * sizeof(uint64_t) + S * ndig * sizeof(double) + 512;
+    st = pin_reserve(c, readback, j.s);
     if (st) return st;
     uint64_t* h_or = palloc<uint64_t>(c, S);
     uint64_t* h_and = palloc<uint64_t>(c, S);
@@ -556,7 +620,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     std::vector<int> dsel(S, 0);
     int d = 1;
     for (size_t i = 0; i < S; ++i) {
-        V[i] = varying_digits(vor[i], vand[i], kb);
+        V[i] = varying_digits(vor[i], vand[i], kb, rb);
         if (V[i].empty()) {
             finished.push_back({segs[i].start, segs[i].len});
             continue;
@@ -608,19 +672,19 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         for (int p = 0; p < d; ++p) {  // LSD order: least significant selected first
             const int q = std::max(p, skip) - skip;
             const int dig = sel[np - 1 - q];
-            g.shift[p] = (int8_t)(8 * dig);
-            g.width[p] = 8;
+            g.shift[p] = (int8_t)(rb * dig);
+            g.width[p] = (int8_t)std::min(rb, 8 * kb - rb * dig);
             g.hslot[p] = (int8_t)dig;
         }
         full[i] = nv <= di;
-        g.lo_bit = full[i] ? 0 : 8 * v[di - 1];
+        g.lo_bit = full[i] ? 0 : rb * v[di - 1];
         if (!full[i]) {
             all_full = false;
             g.window_base = (uint32_t)nslots;
             nslots += (segs[i].len + j.wsmall - 1) / j.wsmall;
             medcap += segs[i].len / (j.wsmall + 1);
             bigcap += segs[i].len / (j.cap + 1);
-            const uint64_t maxb = di >= 8 ? ~0ull : (1ull << (8 * di));
+            const uint64_t maxb = rb * di >= 64 ? ~0ull : (1ull << (rb * di));
             bcap += std::min<uint64_t>(segs[i].len, maxb);
         }
         hs[i] = g;
@@ -688,7 +752,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             const uint32_t blocks = std::min<uint32_t>(ntp, 4096);
             ca.tiles_per_block = (ntp + blocks - 1) / blocks;
             ca.base_shift = hs[active[0]].shift[p];
-            ca.bits = RADIX_BITS;
+            ca.bits = rb;
             ca.ndig = 1;
             ca.tile_hist = tone;
             ca.segs = single ? nullptr : dsegs;  // several segments: each its own digit
@@ -731,6 +795,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         Timed tm(c, j.s, ST_DEAL, true);
         DealArgs da{};
         da.off = nolb ? toff : nullptr;
+        da.tile = j.tile;
         da.kin = j.k[cur];
         da.vin = j.v[cur];
         da.kout = j.k[1 - cur];
@@ -885,16 +950,18 @@ dfr_status check_err(Job& j) {
 }
 
 dfr_status run_sort(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const std::vector<LSeg>& segs0,
-                    void* temp, hipStream_t s) {
+                    void* temp, hipStream_t s, const dfr_tune* forced = nullptr) {
     Job j;
     j.c = c;
     j.kb = kb;
     j.vb = vb;
     j.s = s;
-    j.tile = deal_tile_records(kb, vb);
     j.cap = local_cap(kb, vb);
-    j.wsmall = j.cap / 4;
-    j.divert = c->divert ? std::min(c->divert, j.cap) : default_divert(kb, vb);
+    const dfr_tune t = forced ? *forced : effective_tune(c, kb, vb, size_class(segs0));
+    j.tile = t.tile_records;
+    j.rb = t.radix_bits;
+    j.wsmall = t.window_records;
+    j.divert = t.divert_records;
     j.top_d_forced = c->force_d;
     uint64_t n = 0;
     for (auto& g : segs0) n = std::max(n, g.start + g.len);
@@ -1009,23 +1076,32 @@ dfr_status sort_plain(dfr_ctx* c, int kb, int vb, void* keys, void* vals, size_t
     return run_sort(c, kb, vb, keys, vb ? vals : nullptr, segs, temp, s);
 }
 
-dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const uint64_t* off,
-                          size_t S, void* temp, size_t temp_bytes, void* stream) {
-    if (!c) return DFR_E_INVALID_ARG;
+// Segments from host offsets (S + 1 entries, [0] = 0, non-decreasing).
+dfr_status parse_segments(const uint64_t* off, size_t S, int kb, std::vector<LSeg>& segs) {
     if (!off) return DFR_E_INVALID_ARG;
     if (off[0] != 0) return DFR_E_INVALID_ARG;
     for (size_t i = 0; i < S; ++i)
         if (off[i + 1] < off[i]) return DFR_E_INVALID_ARG;
-    const size_t n = off[S];
-    dfr_status st = validate(c, keys, vals, n, kb, vb, temp, temp_bytes);
-    if (st) return st;
-    std::vector<LSeg> segs;
+    segs.clear();
     segs.reserve(S);
     for (size_t i = 0; i < S; ++i) {
         const uint64_t len = off[i + 1] - off[i];
         if (len > DFR_MAX_SEGMENT_RECORDS) return DFR_E_TOO_LARGE;
         segs.push_back(LSeg{off[i], len, 8 * kb});
     }
+    return DFR_OK;
+}
+
+dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const uint64_t* off,
+                          size_t S, void* temp, size_t temp_bytes, void* stream) {
+    if (!c) return DFR_E_INVALID_ARG;
+    std::vector<LSeg> segs;
+    if (!off) return DFR_E_INVALID_ARG;
+    const size_t n = off[S];
+    dfr_status st = validate(c, keys, vals, n, kb, vb, temp, temp_bytes);
+    if (st) return st;
+    st = parse_segments(off, S, kb, segs);
+    if (st) return st;
     if (n <= 1) {
         c->stats = dfr_stats{};
         return DFR_OK;
@@ -1036,6 +1112,103 @@ dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, co
     st = get_temp(c, n, kb, vb, &temp, s);
     if (st) return st;
     return run_sort(c, kb, vb, keys, vb ? vals : nullptr, segs, temp, s);
+}
+
+// One timed sort of fresh copies of the caller's data under tuning t.
+dfr_status time_sort(dfr_ctx* c, int kb, int vb, const void* keys, const void* vals, void* kw,
+                     void* vw, size_t n, const std::vector<LSeg>& segs, void* temp, hipStream_t s,
+                     const dfr_tune& t, int reps, hipEvent_t e0, hipEvent_t e1, double* ms) {
+    double best = 1e30;
+    for (int r = 0; r < reps; ++r) {
+        HIP_TRY(c, hipMemcpyAsync(kw, keys, n * kb, hipMemcpyDeviceToDevice, s));
+        if (vb) HIP_TRY(c, hipMemcpyAsync(vw, vals, n * vb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, hipEventRecord(e0, s));
+        dfr_status st = run_sort(c, kb, vb, kw, vb ? vw : nullptr, segs, temp, s, &t);
+        if (st) return st;
+        HIP_TRY(c, hipEventRecord(e1, s));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float f = 0;
+        HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
+        best = std::min(best, (double)f);
+    }
+    *ms = best;
+    return DFR_OK;
+}
+
+// Coordinate descent over the settings, two sweeps, from the defaults.
+dfr_status autotune(dfr_ctx* c, int kb, int vb, const void* keys, const void* vals,
+                    const std::vector<LSeg>& segs, size_t n, int reps, hipStream_t s, dfr_tune* out) {
+    void* temp = nullptr;
+    dfr_status st = get_temp(c, n, kb, vb, &temp, s);
+    if (st) return st;
+    void *kw = nullptr, *vw = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        if (kw) (void)hipFree(kw);
+        if (vw) (void)hipFree(vw);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&kw, n * kb) != hipSuccess || (vb && hipMalloc(&vw, n * vb) != hipSuccess)) {
+        (void)hipGetLastError();
+        cleanup();
+        c->err = "autotune: copy buffers";
+        return DFR_E_NO_MEMORY;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail_hip(c, hipErrorUnknown, "autotune: events");
+    }
+    const bool timing = c->timing;
+    c->timing = false;
+    const size_t cap = local_cap(kb, vb);
+    const uint32_t tile = deal_tile_records(kb, vb);
+    std::vector<std::vector<uint64_t>> choices = {
+        kb == 4 ? std::vector<uint64_t>{6, 7, 8} : std::vector<uint64_t>{8},
+        {tile, tile / 2},
+        {cap / 4, cap / 2, cap * 3 / 4, cap},
+        {cap / 8, cap / 4, cap / 2},
+    };
+    auto with = [](dfr_tune t, int knob, uint64_t v) {
+        if (knob == 0) t.radix_bits = (int32_t)v;
+        else if (knob == 1) t.tile_records = (uint32_t)v;
+        else if (knob == 2) t.divert_records = v;
+        else t.window_records = v;
+        return t;
+    };
+    auto get = [](const dfr_tune& t, int knob) -> uint64_t {
+        return knob == 0 ? (uint64_t)t.radix_bits : knob == 1 ? t.tile_records
+                                                 : knob == 2 ? t.divert_records : t.window_records;
+    };
+    dfr_tune best = default_tune(kb, vb);
+    double best_ms = 0;
+    st = time_sort(c, kb, vb, keys, vals, kw, vw, n, segs, temp, s, best, reps, e0, e1, &best_ms);
+    const double default_ms = best_ms;
+    for (int sweep = 0; sweep < 2 && !st; ++sweep) {
+        for (int knob = 0; knob < 4 && !st; ++knob) {
+            for (uint64_t v : choices[knob]) {
+                if (v == get(best, knob)) continue;
+                const dfr_tune t = with(best, knob, v);
+                if (!tune_valid(t, kb, vb)) continue;
+                double ms = 0;
+                st = time_sort(c, kb, vb, keys, vals, kw, vw, n, segs, temp, s, t, reps, e0, e1, &ms);
+                if (st) break;
+                if (ms < best_ms * 0.99) {  // keep the incumbent on near ties
+                    best = t;
+                    best_ms = ms;
+                }
+            }
+        }
+    }
+    c->timing = timing;
+    cleanup();
+    if (st) return st;
+    best.ms = best_ms;
+    best.ms_default = default_ms;
+    c->tunes[tune_key(kb, vb, size_class(segs))] = best;
+    if (out) *out = best;
+    return DFR_OK;
 }
 
 }  // namespace
@@ -1115,6 +1288,62 @@ size_t dfr_local_sort_capacity(int key_bytes, int val_bytes) {
     if (!(key_bytes == 4 || key_bytes == 8) || !(val_bytes == 0 || val_bytes == 4 || val_bytes == 8))
         return 0;
     return local_cap(key_bytes, val_bytes);
+}
+
+size_t dfr_deal_tile_records(int key_bytes, int val_bytes) {
+    if (!(key_bytes == 4 || key_bytes == 8) || !(val_bytes == 0 || val_bytes == 4 || val_bytes == 8))
+        return 0;
+    return deal_tile_records(key_bytes, val_bytes);
+}
+
+int32_t dfr_size_class(const uint64_t* seg_offsets, size_t num_segments) {
+    std::vector<LSeg> segs;
+    if (parse_segments(seg_offsets, num_segments, 4, segs) != DFR_OK) return -1;
+    return size_class(segs);
+}
+
+dfr_status dfr_autotune(dfr_ctx* c, int key_bytes, int val_bytes, const void* keys,
+                        const void* vals, const uint64_t* seg_offsets, size_t num_segments,
+                        int reps, void* stream, dfr_tune* out) {
+    if (!c || !seg_offsets) return DFR_E_INVALID_ARG;
+    const size_t n = seg_offsets[num_segments];
+    dfr_status st = validate(c, keys, vals, n, key_bytes, val_bytes, nullptr, 0);
+    if (st) return st;
+    std::vector<LSeg> segs;
+    st = parse_segments(seg_offsets, num_segments, key_bytes, segs);
+    if (st) return st;
+    if (n <= 1) {
+        if (out) *out = default_tune(key_bytes, val_bytes);
+        return DFR_OK;
+    }
+    st = set_device(c);
+    if (st) return st;
+    return autotune(c, key_bytes, val_bytes, keys, val_bytes ? vals : nullptr, segs, n,
+                    reps > 0 ? reps : 2, (hipStream_t)stream, out);
+}
+
+dfr_status dfr_get_tune(const dfr_ctx* c, int key_bytes, int val_bytes, int32_t size_class,
+                        dfr_tune* out) {
+    if (!c || !out || size_class < 0 || size_class >= DFR_TUNE_CLASSES) return DFR_E_INVALID_ARG;
+    auto it = c->tunes.find(tune_key(key_bytes, val_bytes, size_class));
+    if (it == c->tunes.end()) return DFR_E_NOT_FOUND;
+    *out = it->second;
+    return DFR_OK;
+}
+
+dfr_status dfr_set_tune(dfr_ctx* c, int key_bytes, int val_bytes, int32_t size_class,
+                        const dfr_tune* tune) {
+    if (!c || size_class < 0 || size_class >= DFR_TUNE_CLASSES) return DFR_E_INVALID_ARG;
+    if (!(key_bytes == 4 || key_bytes == 8) || !(val_bytes == 0 || val_bytes == 4 || val_bytes == 8))
+        return DFR_E_INVALID_ARG;
+    const uint32_t k = tune_key(key_bytes, val_bytes, size_class);
+    if (!tune) {
+        c->tunes.erase(k);
+        return DFR_OK;
+    }
+    if (!tune_valid(*tune, key_bytes, val_bytes)) return DFR_E_INVALID_ARG;
+    c->tunes[k] = *tune;
+    return DFR_OK;
 }
 
 dfr_status dfr_sort_u32(dfr_ctx* c, uint32_t* keys, uint32_t* vals, size_t n, void* temp,
@@ -1277,6 +1506,7 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
     da.lookback = lb;
     da.ticket = lb + nt * RADIX;
     da.err = derr;
+    da.tile = deal_tile_records(key_bytes, val_bytes);
     {
         Timed tm(c, s, ST_DEAL, true);
         HIP_TRY(c, launch_deal(key_bytes, val_bytes, da, s));
@@ -1328,6 +1558,21 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
     }
     if (!strcmp(name, "force_lookback")) {
         c->force_lookback = value != 0;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "radix_bits")) {
+        if (value != 0 && (value < 4 || value > RADIX_BITS)) return DFR_E_INVALID_ARG;
+        c->radix_bits = (int)value;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "tile_records")) {
+        if (value < 0 || value > (1 << 20)) return DFR_E_INVALID_ARG;
+        c->tile_records = (uint32_t)value;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "window_records")) {
+        if (value < 0) return DFR_E_INVALID_ARG;
+        c->window = (size_t)value;
         return DFR_OK;
     }
     return DFR_E_UNSUPPORTED;

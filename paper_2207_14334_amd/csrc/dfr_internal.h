@@ -117,6 +117,7 @@ struct DealArgs {
     uint32_t* lookback;  // [ntiles][RADIX]
     uint32_t* ticket;
     const uint32_t* off; // when set: per-tile bucket bases, and no look-back
+    uint32_t tile;       // records per tile (selects the kernel; see deal_tile_supported)
     uint32_t* err;
 };
 
@@ -188,7 +189,8 @@ struct LocalArgs {
 };
 
 // Tile and capacity choices per (key bytes, value bytes).
-uint32_t deal_tile_records(int kb, int vb);
+uint32_t deal_tile_records(int kb, int vb);  // the default tile
+bool deal_tile_supported(int kb, int vb, uint32_t tile);  // the default or half of it
 uint32_t local_sort_capacity(int kb, int vb);
 
 // Launchers (kernels.hip).  Each returns the launch's hipError_t.

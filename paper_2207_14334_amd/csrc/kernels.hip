@@ -1271,6 +1271,10 @@ static_assert(DEAL_TILE_SMALL >= DEAL_TILE_LARGE, "head kernel covers the larger
 uint32_t deal_tile_records(int kb, int vb) {
     return kb + vb <= 8 ? (uint32_t)DEAL_TILE_SMALL : (uint32_t)DEAL_TILE_LARGE;
 }
+bool deal_tile_supported(int kb, int vb, uint32_t tile) {
+    const uint32_t t = deal_tile_records(kb, vb);
+    return tile == t || tile == t / 2;
+}
 uint32_t local_sort_capacity(int kb, int vb) {
     return kb + vb <= 8 ? (uint32_t)LOCAL_CAP_SMALL : (uint32_t)LOCAL_CAP_LARGE;
 }
@@ -1306,15 +1310,25 @@ hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t
     return hipGetLastError();
 }
 
-template <int KB, int VB>
-static void deal_kb_vb(const DealArgs& a, hipStream_t s) {
-    constexpr int ITEMS = (KB + VB <= 8 ? DEAL_TILE_SMALL : DEAL_TILE_LARGE) / DEAL_THREADS;
+template <int KB, int VB, int ITEMS>
+static void deal_items(const DealArgs& a, hipStream_t s) {
     if (a.off)
         hipLaunchKernelGGL((k_deal<KB, VB, DEAL_THREADS, ITEMS, false>), dim3(a.ntiles),
                            dim3(DEAL_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL((k_deal<KB, VB, DEAL_THREADS, ITEMS, true>), dim3(a.ntiles),
                            dim3(DEAL_THREADS), 0, s, a);
+}
+
+// Two tile sizes per record size: the default and half of it.
+template <int KB, int VB>
+static bool deal_kb_vb(const DealArgs& a, hipStream_t s) {
+    constexpr int ITEMS = (KB + VB <= 8 ? DEAL_TILE_SMALL : DEAL_TILE_LARGE) / DEAL_THREADS;
+    static_assert(ITEMS % 2 == 0, "half tile");
+    if (a.tile == (uint32_t)(ITEMS * DEAL_THREADS)) deal_items<KB, VB, ITEMS>(a, s);
+    else if (a.tile == (uint32_t)(ITEMS / 2 * DEAL_THREADS)) deal_items<KB, VB, ITEMS / 2>(a, s);
+    else return false;
+    return true;
 }
 
 // ---------------------------------------------------------------------------------
@@ -1473,15 +1487,17 @@ hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s) {
 
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s) {
     if (a.ntiles == 0) return hipSuccess;
+    bool ok;
     if (kb == 4) {
-        if (vb == 0) deal_kb_vb<4, 0>(a, s);
-        else if (vb == 4) deal_kb_vb<4, 4>(a, s);
-        else deal_kb_vb<4, 8>(a, s);
+        if (vb == 0) ok = deal_kb_vb<4, 0>(a, s);
+        else if (vb == 4) ok = deal_kb_vb<4, 4>(a, s);
+        else ok = deal_kb_vb<4, 8>(a, s);
     } else {
-        if (vb == 0) deal_kb_vb<8, 0>(a, s);
-        else if (vb == 4) deal_kb_vb<8, 4>(a, s);
-        else deal_kb_vb<8, 8>(a, s);
+        if (vb == 0) ok = deal_kb_vb<8, 0>(a, s);
+        else if (vb == 4) ok = deal_kb_vb<8, 4>(a, s);
+        else ok = deal_kb_vb<8, 8>(a, s);
     }
+    if (!ok) return hipErrorInvalidValue;  // no kernel for this tile size
     return hipGetLastError();
 }
 

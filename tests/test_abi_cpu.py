@@ -143,3 +143,25 @@ def test_plan_divert_option_changes_depth(L):
     assert dfr.plan_top_digits(h, 1 << 28, 4, 4, divert=64)[0] == 4  # LSD is cheaper
     assert dfr.plan_top_digits(h + np.uint32(3) * (np.arange(256) % 2).astype(np.uint32), 1 << 28, 4, 4)[0] == 2
     assert dfr.plan_top_digits(h, 1 << 28, 4, 4, divert=8192)[0] == 2
+
+
+def test_deal_tile_records(L):
+    assert dfr.deal_tile_records(4, 4) == 8192
+    assert dfr.deal_tile_records(4, 0) == 8192
+    assert dfr.deal_tile_records(8, 8) == 4096
+    assert dfr.deal_tile_records(3, 4) == 0
+
+
+def test_size_class_is_log2_of_size_biased_mean():
+    # One segment: floor(log2 n).
+    assert dfr.size_class([0, 1 << 20]) == 20
+    assert dfr.size_class([0, (1 << 20) - 1]) == 19
+    # Segments of one record or none do not count; the mean is weighted by length:
+    # lengths 1000 and 3000 give (1000^2 + 3000^2) / 4000 = 2500 -> 11.
+    assert dfr.size_class([0, 0, 1, 1001, 4001]) == 11
+    # Nothing to sort -> class 0.
+    assert dfr.size_class([0, 1, 2]) == 0
+    with pytest.raises(dfr.DfrError):
+        dfr.size_class([5, 10])
+    with pytest.raises(dfr.DfrError):
+        dfr.size_class([0, 10, 5])
