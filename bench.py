@@ -1,7 +1,15 @@
 #!/usr/bin/env python3
 """Benchmark of the DFR sort hot path on one MI355X.
 
-One step = one plain DFR sort (count, deals of the top digits, bucket finding, local
+Workloads (``--workload``):
+
+* ``plain`` (default) -- the headline configuration, below.
+* ``batched`` -- 20,000 independent uint32 arrays with lengths log-uniform in
+  [16, --max-len] (default 2^20) and a uint32 index payload, sorted by one segmented
+  call after the autotuner has picked its launch settings on the same data; the same
+  arrays sorted by one plain call each are timed beside it.
+
+Plain workload: one step = one plain DFR sort (count, deals of the top digits, bucket finding, local
 sort of runs of small buckets, recursion if any) of 2^28 uint32 keys drawn i.i.d.
 uniform over [0, 2^32) with a uint32 index payload, seed 0.  Every step sorts its own
 copy of that input, made resident in HBM before the timed region starts, so the timed
@@ -90,13 +98,132 @@ def cpu_baseline(dist, log2n_sample=24, seeds=(0, 1, 2)):
     }
 
 
+def check_segments(keys_in, keys_out, vals_out, off, segs):
+    """check_result on the listed segments (payload = global index)."""
+    for s in segs:
+        a, b = int(off[s]), int(off[s + 1])
+        r = check_result(keys_in[a:b], keys_out[a:b], vals_out[a:b] - vals_out.dtype.type(a))
+        if r != "pass":
+            return f"segment {s}: {r}"
+    return "pass"
+
+
+def run_batched(args):
+    """Batched segmented sort against one plain call per array."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2207_14334_amd as dfr
+    import workloads
+
+    torch.cuda.set_device(0)
+    lens = workloads.batch_lengths(args.arrays, 16, args.max_len, 0)
+    off = workloads.segment_offsets(lens)
+    n = int(off[-1])
+    log(f"generating {args.arrays} arrays, {n} {args.dist} keys")
+    keys_h = workloads.make_keys(args.dist, n, 32, 0)
+    vals_h = workloads.index_payload(n)
+    base_k = torch.from_numpy(keys_h).cuda()
+    base_v = torch.from_numpy(vals_h).cuda()
+    k = torch.empty_like(base_k)
+    v = torch.empty_like(base_v)
+    temp = torch.empty(dfr.temp_bytes(n, 4, 4), dtype=torch.uint8, device="cuda")
+    ctx = dfr.Context(0)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed_segmented():
+        k.copy_(base_k)
+        v.copy_(base_v)
+        ev[0].record(stream)
+        ctx.sort_segmented_(k, v, off, temp)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1])
+
+    tune = ctx.autotune(base_k, base_v, off, reps=1)
+    log(f"autotune: {tune}")
+    for _ in range(args.warmup):
+        timed_segmented()
+    times = [timed_segmented() for _ in range(args.steps)]
+    ctx.set_option("timing", 1)
+    timed_segmented()
+    stages = ctx.stats()
+    ctx.set_option("timing", 0)
+    ms = float(np.median(times))
+    gkeys = n / (ms * 1e-3) / 1e9
+    log(f"segmented: median {ms:.2f} ms over {args.steps}, {gkeys:.2f} Gkeys/s")
+    k_out, v_out = k.cpu().numpy(), v.cpu().numpy()
+    rng = np.random.default_rng(1)
+    sample = sorted(set(rng.integers(0, lens.size, 200).tolist()) | {int(np.argmax(lens))})
+    parity = check_segments(keys_h, k_out, v_out, off, sample)
+    log(f"result check on {len(sample)} segments: {parity}")
+    del k_out, v_out
+
+    # One plain call per array, on the same stream, the host waiting on nothing but
+    # what each call itself waits for.
+    plain = []
+    for _ in range(args.plain_runs):
+        k.copy_(base_k)
+        v.copy_(base_v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(lens.size):
+            a, b = int(off[i]), int(off[i + 1])
+            ctx.sort_(k[a:b], v[a:b], temp)
+        torch.cuda.synchronize()
+        plain.append((time.perf_counter() - t0) * 1e3)
+    plain_ms = min(plain)
+    log(f"plain calls: {plain_ms:.1f} ms, {n / plain_ms / 1e6:.3f} Gkeys/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        o = oracle.get()
+        m = int(np.searchsorted(off, 1 << 24))  # first arrays, about 2^24 keys
+        t0 = time.perf_counter()
+        o.segmented_sort(keys_h[: off[m]], vals_h[: off[m]], off[: m + 1])
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(int(off[m]) / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"the first {m} arrays ({int(off[m])} keys) of the same batch, "
+                         f"single-threaded, {dt:.1f} s"}
+
+    out = {
+        "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"batched segmented sort of {args.arrays} uint32 arrays, "
+                               f"lengths log-uniform in [16, {args.max_len}], {args.dist} "
+                               f"keys, uint32 index payload, seed 0",
+                   "n": n, "arrays": int(lens.size), "max_len": args.max_len,
+                   "distribution": args.dist, "parallelism": "single GPU"},
+        "plain_calls": {"ms": round(plain_ms, 2), "gkeys_per_s": round(n / plain_ms / 1e6, 4),
+                        "speedup_of_batched": round(plain_ms / ms, 2)},
+        "tune": tune, "untuned_ms": round(tune["ms_default"], 4),
+        "stage_ms": {kk: round(vv, 4) for kk, vv in stages.items() if kk.startswith("ms_")},
+        "plan": {kk: stages[kk] for kk in ("levels", "top_digits", "deal_passes", "large_buckets")},
+        "cpu_baseline": cpu,
+        "result_check": parity,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    if parity != "pass":
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("plain", "batched"), default="plain")
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--dist", default="uniform")
+    ap.add_argument("--arrays", type=int, default=20000)
+    ap.add_argument("--max-len", type=int, default=1 << 20)
+    ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -104,7 +231,12 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; the sort's "
                                    "multi-GPU path is not built (see DESIGN.md)"}), flush=True)
         sys.exit(2)
+    if args.workload == "batched":
+        return run_batched(args)
+    return run_plain(args)
 
+
+def run_plain(args):
     import numpy as np
     import torch
 

@@ -2,7 +2,8 @@
 
 2^28 uint32 keys with a uint32 index payload on each key distribution of that workload
 (uniform, normal, Zipf, sorted, reverse-sorted, 256 distinct values), and 2^27 uint64
-keys with a uint64 index payload (uniform, and top-16-bits-from-4-values skewed).
+keys with a uint64 index payload (uniform, and top-16-bits-from-4-values skewed); and the
+batched segmented sort of 20,000 uint32 arrays with lengths log-uniform in [16, 2^20].
 
 At these sizes the oracle checks the output by the properties that single out the stable
 sort under the index payload (permutation, key/payload agreement, order, ties in input
@@ -56,3 +57,35 @@ def test_full_size(env, bits, dist, n):
         assert o.rank_of(keys, int(ov[p])) == int(p), (dist, int(p))
     print(f"[done] {dist}: levels={st['levels']} top_digits={st['top_digits']} "
           f"deal_passes={st['deal_passes']} large={st['large_buckets']}", flush=True)
+
+
+# Batched segmented sort at its full size: 20,000 uint32 arrays, lengths log-uniform
+# in [16, 2^20] (about 1.9e9 keys in total), global index payload, uniform and Zipf keys.
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_batched_full_size(env, dist):
+    torch, dfr, ctx = env
+    o = oracle.get()
+    lens = workloads.batch_lengths(20000, 16, 1 << 20, 0)
+    off = workloads.segment_offsets(lens)
+    n = int(off[-1])
+    print(f"[case] batched full-size {dist} arrays={lens.size} n={n}", flush=True)
+    keys = workloads.make_keys(dist, n, 32, 0)
+    vals = workloads.index_payload(n)
+    dk = torch.from_numpy(keys).cuda()
+    dv = torch.from_numpy(vals).cuda()
+    ctx.sort_segmented_(dk, dv, off)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ok, ov = dk.cpu().numpy(), dv.cpu().numpy()
+    del dk, dv
+    torch.cuda.empty_cache()
+    for s in range(lens.size):
+        a, b = int(off[s]), int(off[s + 1])
+        bad = o.check_index_payload(keys[a:b], ok[a:b], ov[a:b] - np.uint32(a))
+        assert bad is None, (s, bad, st)
+    rng = np.random.default_rng(7)
+    for s in rng.integers(0, lens.size, size=3):
+        a, b = int(off[s]), int(off[s + 1])
+        p = int(rng.integers(a, b))
+        assert o.rank_of(keys[a:b], int(ov[p]) - a) == p - a, (s, p)
+    print(f"[done] batched {dist}: levels={st['levels']} deal_passes={st['deal_passes']}", flush=True)
