@@ -8,6 +8,12 @@ Workloads (``--workload``):
   [16, --max-len] (default 2^20) and a uint32 index payload, sorted by one segmented
   call after the autotuner has picked its launch settings on the same data; the same
   arrays sorted by one plain call each are timed beside it.
+* ``serving`` -- a Poisson stream of sort requests (sizes log-uniform in
+  [2^10, 2^24], 70% uint32 / 30% uint64 keys with a payload of the key's width,
+  uniform or Zipf keys), offered at a load rho of the mean service time of one plain
+  call, served (a) by FIFO plain calls on one stream and (b) by the context's
+  request queue (dfr_submit / dfr_poll: continuous batching into segmented sorts)
+  under a 32 GiB HBM budget.  Latency is arrival to completion; p50/p99 for both.
 
 Plain workload: one step = one plain DFR sort (count, deals of the top digits, bucket finding, local
 sort of runs of small buckets, recursion if any) of 2^28 uint32 keys drawn i.i.d.
@@ -213,12 +219,173 @@ def run_batched(args):
         sys.exit(1)
 
 
+def run_serving(args):
+    """Poisson request stream: FIFO plain calls against the batching request queue."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2207_14334_amd as dfr
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = workloads.request_stream(args.requests, 1.0, 1 << 10, 1 << 24, 0.3, 0.5, 0)
+    unit_arrivals = np.array([a for a, _, _, _ in stream])  # at rate 1 per second
+    log(f"generating {len(stream)} requests, {sum(r[1] for r in stream)} keys")
+    from concurrent.futures import ThreadPoolExecutor
+
+    def gen(i):
+        _, n, bits, dist = stream[i]
+        return workloads.make_keys(dist, n, bits, 1000 + i), workloads.index_payload(n, bits)
+
+    base, work = [], []
+    with ThreadPoolExecutor(8) as ex:  # numpy draws release the GIL
+        for kh, vh in ex.map(gen, range(len(stream))):
+            k = torch.from_numpy(kh).cuda()
+            v = torch.from_numpy(vh).cuda()
+            base.append((k, v))
+            work.append((torch.empty_like(k), torch.empty_like(v)))
+    total_keys = sum(r[1] for r in stream)
+    torch.cuda.synchronize()
+
+    def reset():
+        for (bk, bv), (wk, wv) in zip(base, work):
+            wk.copy_(bk)
+            wv.copy_(bv)
+        torch.cuda.synchronize()
+
+    ctx = dfr.Context(0, hbm_budget_bytes=args.budget_gib << 30)
+    # Mean service time of one plain call: the whole stream back to back.
+    sys.setswitchinterval(2e-4)  # the submitting thread must not wait long for the GIL
+    reset()
+    for i in range(min(len(work), 30)):
+        ctx.sort_(*work[i])
+    reset()
+    t0 = time.perf_counter()
+    for k, v in work:
+        ctx.sort_(k, v)
+    torch.cuda.synchronize()
+    svc_mean = (time.perf_counter() - t0) / len(work)
+    log(f"plain call: {svc_mean * 1e3:.3f} ms mean over the stream")
+
+    def spin_until(t):
+        while True:
+            d = t - time.perf_counter()
+            if d <= 0:
+                return
+            if d > 2e-4:
+                time.sleep(d - 1e-4)
+
+    def fifo(arrive):
+        reset()
+        lat = np.zeros(len(work))
+        t0 = time.perf_counter() + 0.01
+        done = 0.0
+        for i, (k, v) in enumerate(work):
+            spin_until(t0 + arrive[i])
+            ctx.sort_(k, v)
+            done = time.perf_counter()
+            lat[i] = done - (t0 + arrive[i])
+        return lat, done - t0
+
+    def served(arrive):
+        reset()
+        n = len(work)
+        tickets = [None] * n
+        sub_delay = np.zeros(n)
+        lat = np.full(n, np.nan)
+        submitted = threading.Event()
+        t0 = time.perf_counter() + 0.01
+
+        def submitter():
+            for i, (k, v) in enumerate(work):
+                spin_until(t0 + arrive[i])
+                sub_delay[i] = time.perf_counter() - (t0 + arrive[i])
+                tickets[i] = ctx.submit(k, v)
+            submitted.set()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        left = set()
+        nxt = 0
+        while nxt < n or left:
+            while nxt < n and tickets[nxt] is not None:
+                left.add(nxt)
+                nxt += 1
+            for i in list(left):
+                ok, l = ctx.poll(tickets[i])
+                if ok:
+                    lat[i] = l + sub_delay[i]
+                    left.discard(i)
+            time.sleep(2e-4)
+        th.join()
+        end = max(arrive[i] + lat[i] for i in range(n))
+        return lat, end
+
+    out_rho = {}
+    st0 = None
+    for rho in args.rho:
+        arrive = unit_arrivals * svc_mean / rho
+        lat_p, span_p = fifo(arrive)
+        lat_s, span_s = served(arrive)
+        st = ctx.serve_stats()
+        r = {
+            "offered_rate_per_s": round(rho / svc_mean, 1),
+            "fifo_plain": {"p50_ms": round(float(np.percentile(lat_p, 50)) * 1e3, 3),
+                           "p99_ms": round(float(np.percentile(lat_p, 99)) * 1e3, 3),
+                           "gkeys_per_s": round(total_keys / span_p / 1e9, 3)},
+            "served": {"p50_ms": round(float(np.percentile(lat_s, 50)) * 1e3, 3),
+                       "p99_ms": round(float(np.percentile(lat_s, 99)) * 1e3, 3),
+                       "gkeys_per_s": round(total_keys / span_s / 1e9, 3),
+                       "batches": st["batches"] - (st0["batches"] if st0 else 0),
+                       "max_batch_requests": st["max_batch_requests"]},
+        }
+        r["p99_ratio_plain_over_served"] = round(r["fifo_plain"]["p99_ms"] / r["served"]["p99_ms"], 3)
+        st0 = st
+        out_rho[str(rho)] = r
+        log(f"rho {rho}: {json.dumps(r)}")
+
+    # Results of the last served run: each request sorted (properties of the stable
+    # sort under the index payload) on a sample.
+    rng = np.random.default_rng(3)
+    parity = "pass"
+    for i in sorted(set(rng.integers(0, len(work), 40).tolist())):
+        kin = base[i][0].cpu().numpy()
+        r = check_result(kin, work[i][0].cpu().numpy(), work[i][1].cpu().numpy())
+        if r != "pass":
+            parity = f"request {i}: {r}"
+            break
+    head = out_rho[str(args.rho[-1] if 0.7 not in args.rho else 0.7)]
+    out = {
+        "metric": METRIC, "value": head["served"]["gkeys_per_s"], "unit": "Gkeys/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
+        "config": {"workload": f"serving: {len(stream)} Poisson sort requests, sizes log-uniform "
+                               f"in [2^10, 2^24], 70% uint32 / 30% uint64 keys with payload, "
+                               f"50% uniform / 50% Zipf, HBM budget {args.budget_gib} GiB",
+                   "requests": len(stream), "keys": total_keys,
+                   "plain_call_ms_mean": round(svc_mean * 1e3, 4), "headline_rho": 0.7,
+                   "parallelism": "single GPU"},
+        "p50_ms": head["served"]["p50_ms"], "p99_ms": head["served"]["p99_ms"],
+        "p99_plain_fifo_ms": head["fifo_plain"]["p99_ms"],
+        "by_rho": out_rho, "serve_stats": ctx.serve_stats(), "result_check": parity,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    if parity != "pass":
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("plain", "batched"), default="plain")
+    ap.add_argument("--workload", choices=("plain", "batched", "serving"), default="plain")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rho", type=float, nargs="+", default=[0.3, 0.5, 0.7, 0.9])
+    ap.add_argument("--budget-gib", type=int, default=32)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--dist", default="uniform")
     ap.add_argument("--arrays", type=int, default=20000)
@@ -233,6 +400,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "serving":
+        return run_serving(args)
     return run_plain(args)
 
 

@@ -129,24 +129,62 @@ dfr_status dfr_deal(dfr_ctx* ctx, const void* keys_in, const void* vals_in, void
                     int bits, void* stream);
 
 /* ---------------------------------------------------------------------------------
- * Request queue: submit sort requests and poll for completion.  (Continuous
- * batching of queued requests into segmented launches.)
+ * Serving: submit sort requests of any size and width, poll for completion.
+ *
+ * Requests are sorted by worker threads of the context (2 by default), each with its
+ * own HIP stream and scratch.  A worker takes the oldest queued request and every
+ * later queued request with the same widths, up to "serve_batch_records" records in
+ * all, and sorts them as one segmented sort (each request is one segment, so the
+ * result is the one a plain sort of that request alone gives): the records are
+ * gathered into a staging buffer, sorted, and scattered back into the requests' own
+ * buffers (a batch of one request is sorted in place).  Requests that arrive while
+ * batches run join the next batch; the workers' batches overlap on the device.
+ * Device memory the workers hold (staging, temp, scratch) stays within the
+ * context's HBM budget (dfr_create): batches shrink, or wait, to fit.
  * ------------------------------------------------------------------------------- */
 typedef struct {
     int key_bytes; /* 4 or 8 */
-    int val_bytes; /* 0, 4 or 8 */
+    int val_bytes; /* 0, or equal to key_bytes */
     void* keys;    /* device, sorted in place */
-    void* vals;    /* device or NULL */
-    size_t n;
+    void* vals;    /* device, or NULL with val_bytes 0 */
+    size_t n;      /* at most DFR_MAX_SEGMENT_RECORDS */
 } dfr_request;
 
-/* Queue a request; *ticket identifies it.  DFR_E_BUDGET if it can never fit. */
+/* Queue a request; *ticket identifies it.  The request's device memory must hold its
+ * data when this is called (all writes to it complete) and must stay alive and
+ * untouched until dfr_poll returns a status other than DFR_E_PENDING for it.
+ * DFR_E_INVALID_ARG for bad widths, pointers or overlapping keys/vals;
+ * DFR_E_TOO_LARGE beyond DFR_MAX_SEGMENT_RECORDS; DFR_E_BUDGET if the request alone
+ * needs more device memory than the budget.  Thread-safe with dfr_poll. */
 dfr_status dfr_submit(dfr_ctx* ctx, const dfr_request* req, uint64_t* ticket);
 
 /* DFR_OK once the request's result is in place (the ticket is then consumed and
- * *latency_s, if not NULL, receives submit-to-completion seconds); DFR_E_PENDING
- * while it is not; DFR_E_NOT_FOUND for an unknown ticket. */
+ * *latency_s, if not NULL, receives the seconds from its submit to the end of its
+ * batch on the device); DFR_E_PENDING while it is queued or running; DFR_E_NOT_FOUND
+ * for an unknown or consumed ticket; another status (consuming the ticket) if its
+ * batch failed, with detail in dfr_last_error.  Thread-safe with dfr_submit. */
 dfr_status dfr_poll(dfr_ctx* ctx, uint64_t ticket, double* latency_s);
+
+typedef struct {
+    uint64_t batches;            /* batches sorted                                */
+    uint64_t requests;           /* requests completed                            */
+    uint64_t records;            /* records sorted                                */
+    uint64_t max_batch_requests; /* most requests in one batch                    */
+    uint64_t peak_held_bytes;    /* most device memory held by the workers        */
+    uint64_t budget_bytes;       /* the context's HBM budget                      */
+    uint64_t held_bytes;         /* device memory the workers hold now            */
+    uint64_t queued;             /* requests waiting for a batch now              */
+    uint64_t allocs;             /* device allocations the workers made           */
+    double ms_alloc;             /* host time in those allocations (and frees)    */
+    double ms_batch_wall;        /* host time from batch start to its completion  */
+    double ms_gather;            /* device time gathering requests into batches   */
+    double ms_sort;              /* device time sorting batches                   */
+    double ms_scatter;           /* device time scattering results back           */
+    int32_t workers;             /* worker threads (0 before the first submit)    */
+} dfr_serve_stats;
+
+/* Counters of the serving workers (all zero before the first submit). */
+dfr_status dfr_get_serve_stats(dfr_ctx* ctx, dfr_serve_stats* out);
 
 /* ---------------------------------------------------------------------------------
  * Options, plan inspection and timing.
@@ -168,6 +206,9 @@ dfr_status dfr_poll(dfr_ctx* ctx, uint64_t ticket, double* latency_s);
  *                     (Sec. 4).  0 = tuned or default.
  *   "tile_records"    records per deal tile: dfr_deal_tile_records(kb, vb) or half
  *                     of it.  0 = tuned or default.
+ *   "serve_workers"   worker threads of the serving queue, 1..8 (default 2), and
+ *   "serve_batch_records" most records in one serving batch (default 2^25); both
+ *                     only before the first dfr_submit (DFR_E_UNSUPPORTED after).
  *   "window_records"  width of the windows that pack runs of small buckets into
  *                     local-sort chunks (Sec. 3: runs of small buckets), 16 ..
  *                     capacity / 2.  0 = tuned or default.

@@ -35,7 +35,7 @@ EXPORTED = [
     "dfr_sort_u32", "dfr_sort_u64", "dfr_sort_segmented_u32", "dfr_sort_segmented_u64",
     "dfr_count", "dfr_deal", "dfr_submit", "dfr_poll", "dfr_set_option", "dfr_get_stats",
     "dfr_plan_top_digits", "dfr_local_sort_capacity", "dfr_deal_tile_records",
-    "dfr_size_class", "dfr_autotune", "dfr_get_tune", "dfr_set_tune",
+    "dfr_size_class", "dfr_autotune", "dfr_get_tune", "dfr_set_tune", "dfr_get_serve_stats",
 ]
 
 TUNE_CLASSES = 32
@@ -72,6 +72,20 @@ class Tune(ctypes.Structure):
     @classmethod
     def from_dict(cls, d):
         return cls(**{f: d.get(f, 0) for f, _ in cls._fields_})
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("requests", ctypes.c_uint64),
+                ("records", ctypes.c_uint64), ("max_batch_requests", ctypes.c_uint64),
+                ("peak_held_bytes", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64),
+                ("held_bytes", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("allocs", ctypes.c_uint64), ("ms_alloc", ctypes.c_double),
+                ("ms_batch_wall", ctypes.c_double), ("ms_gather", ctypes.c_double),
+                ("ms_sort", ctypes.c_double), ("ms_scatter", ctypes.c_double),
+                ("workers", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Request(ctypes.Structure):
@@ -136,6 +150,8 @@ def lib():
     L.dfr_get_tune.restype = S
     L.dfr_set_tune.argtypes = [P, I, I, S, ctypes.POINTER(Tune)]
     L.dfr_set_tune.restype = S
+    L.dfr_get_serve_stats.argtypes = [P, ctypes.POINTER(ServeStats)]
+    L.dfr_get_serve_stats.restype = S
     _lib = L
     return L
 
@@ -372,11 +388,20 @@ class Context:
         return ko, vo
 
     # -- request queue -------------------------------------------------------------
+    # -- serving -------------------------------------------------------------------
     def submit(self, keys, vals=None) -> int:
+        """Queue an in-place sort of ``keys`` (and ``vals``).  The tensors' data must be
+        written (e.g. torch.cuda.synchronize()) and must stay alive until poll says done."""
         _check_tensor(keys, "keys")
         kb = _width(keys)
-        r = Request(kb, kb if vals is not None else 0, keys.data_ptr(),
-                    vals.data_ptr() if vals is not None else None, keys.numel())
+        vb = 0
+        if vals is not None:
+            _check_tensor(vals, "vals")
+            vb = _width(vals)
+            if vals.numel() != keys.numel():
+                raise ValueError("vals must match keys in length")
+        r = Request(kb, vb, keys.data_ptr(), vals.data_ptr() if vals is not None else None,
+                    keys.numel())
         t = ctypes.c_uint64(0)
         self._raise(lib().dfr_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "submit")
         return t.value
@@ -389,6 +414,11 @@ class Context:
             return False, None
         self._raise(st, "poll")
         return True, lat.value
+
+    def serve_stats(self) -> dict:
+        s = ServeStats()
+        self._raise(lib().dfr_get_serve_stats(self._h, ctypes.byref(s)), "serve_stats")
+        return s.as_dict()
 
 
 _default_ctx: Context | None = None

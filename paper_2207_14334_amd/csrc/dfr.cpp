@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -31,6 +32,8 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "dfr_internal.h"
@@ -69,6 +72,10 @@ struct dfr_ctx {
     // Cached temp buffer for calls with temp == NULL.
     void* tcache = nullptr;
     size_t tcache_cap = 0;
+    size_t temp_slack = 0;   // extra fraction (in 1/8) allocated when the cache grows
+    // Device (re)allocations made and host time spent in them.
+    uint64_t n_allocs = 0;
+    double ms_alloc = 0;
     // Pinned host staging (bump allocation, reset after each stream synchronisation).
     char* pin = nullptr;
     size_t pin_cap = 0;
@@ -93,17 +100,11 @@ struct dfr_ctx {
     std::vector<Ev> events;
     std::vector<hipEvent_t> event_pool;
 
-    // Request queue.
-    std::mutex qmu;
-    struct Req {
-        uint64_t ticket;
-        dfr_request r;
-        std::chrono::steady_clock::time_point t0;
-        bool done;
-        double latency;
-    };
-    std::deque<Req> queue;
-    uint64_t next_ticket = 1;
+    // Request serving (dfr_submit / dfr_poll), started by the first submit.
+    std::mutex serve_mu;
+    struct Server* server = nullptr;
+    int serve_workers = 2;
+    uint64_t serve_batch_records = 1ull << 25;
 };
 
 namespace {
@@ -130,6 +131,7 @@ dfr_status arena_need(dfr_ctx* c, size_t bytes, hipStream_t s) {
     const size_t need = c->arena_used + bytes;
     if (need <= c->arena_cap) return DFR_OK;
     const size_t cap = std::max<size_t>(round_up(need + need / 4, 1 << 20), 16 << 20);
+    const auto t0 = std::chrono::steady_clock::now();
     char* na = nullptr;
     hipError_t e = hipMalloc((void**)&na, cap);
     if (e != hipSuccess) {
@@ -143,6 +145,8 @@ dfr_status arena_need(dfr_ctx* c, size_t bytes, hipStream_t s) {
     if (c->arena) HIP_TRY(c, hipFree(c->arena));
     c->arena = na;
     c->arena_cap = cap;
+    c->n_allocs += 1;
+    c->ms_alloc += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return DFR_OK;
 }
 
@@ -1037,17 +1041,21 @@ dfr_status get_temp(dfr_ctx* c, size_t n, int kb, int vb, void** temp, hipStream
     if (*temp) return DFR_OK;
     const size_t need = dfr_temp_bytes(n, kb, vb);
     if (c->tcache_cap < need) {
+        const auto t0 = std::chrono::steady_clock::now();
         HIP_TRY(c, hipStreamSynchronize(s));
         if (c->tcache) HIP_TRY(c, hipFree(c->tcache));
         c->tcache = nullptr;
         c->tcache_cap = 0;
-        hipError_t e = hipMalloc(&c->tcache, need);
+        const size_t cap = round_up(need + need / 8 * c->temp_slack, 1 << 20);
+        hipError_t e = hipMalloc(&c->tcache, cap);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             c->err = "temp allocation failed";
             return DFR_E_NO_MEMORY;
         }
-        c->tcache_cap = need;
+        c->tcache_cap = cap;
+        c->n_allocs += 1;
+        c->ms_alloc += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     *temp = c->tcache;
     return DFR_OK;
@@ -1214,6 +1222,368 @@ dfr_status autotune(dfr_ctx* c, int kb, int vb, const void* keys, const void* va
 }  // namespace
 
 // =================================================================================
+// Request serving: continuous batching of queued sort requests.
+//
+// Worker threads, each with its own stream and its own scratch (an internal context),
+// take the oldest queued request and every later queued request of the same widths
+// up to a record limit, and sort them as one segmented sort: the requests' records
+// are gathered into one staging buffer, sorted segment by segment, and scattered back
+// (a batch of one request is sorted in place).  While one worker's batch is on the
+// device, another worker forms and launches the next one from requests that arrived
+// meanwhile, so batches overlap on the device.  Device memory held by the workers
+// (staging, temp and scratch) stays within the context's HBM budget: a batch shrinks,
+// or a worker frees its caches, or it waits for another to finish, before it
+// allocates past the budget.
+// =================================================================================
+struct Server {
+    struct Req {
+        uint64_t ticket;
+        dfr_request r;
+        std::chrono::steady_clock::time_point t_submit;
+    };
+    struct Done {
+        dfr_status st;
+        double latency;
+    };
+    struct Worker {
+        dfr_ctx* w = nullptr;  // internal context: arena, pinned staging, temp cache
+        hipStream_t s = nullptr;
+        void* sk = nullptr;    // staging for gathered batches
+        void* sv = nullptr;
+        size_t skcap = 0, svcap = 0;
+        size_t held = 0;       // device bytes counted against the budget
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // phase boundaries
+    };
+    dfr_ctx* owner = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req> pending;
+    std::unordered_map<uint64_t, Done> done;
+    std::unordered_map<uint64_t, char> running;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    size_t budget = 0;
+    uint64_t batch_records = 0;
+    size_t held = 0;
+    std::vector<Worker> workers;
+    std::vector<std::thread> threads;
+    dfr_serve_stats stats{};
+};
+
+namespace {
+
+size_t worker_bytes(const Server::Worker& wk) {
+    return wk.skcap + wk.svcap + (wk.w ? wk.w->arena_cap + wk.w->tcache_cap : 0);
+}
+
+// Device bytes a batch of `n` records may need: the temp buffer, staging when the
+// records are gathered, and the sort's own scratch (lists of tiles, buckets and
+// chunks: at most about 24 bytes per record, plus a fixed part).
+size_t batch_bytes(uint64_t n, int kb, int vb, bool gather) {
+    const size_t rec = (size_t)kb + vb;
+    return n * rec * (gather ? 2 : 1) + n * 24 + (64u << 20);
+}
+
+void free_worker_buffers(Server::Worker& wk) {
+    (void)hipStreamSynchronize(wk.s);
+    if (wk.sk) (void)hipFree(wk.sk);
+    if (wk.sv) (void)hipFree(wk.sv);
+    wk.sk = wk.sv = nullptr;
+    wk.skcap = wk.svcap = 0;
+    dfr_ctx* w = wk.w;
+    if (w->arena) (void)hipFree(w->arena);
+    if (w->tcache) (void)hipFree(w->tcache);
+    w->arena = nullptr;
+    w->arena_cap = w->arena_used = 0;
+    w->tcache = nullptr;
+    w->tcache_cap = 0;
+}
+
+dfr_status grow(dfr_ctx* w, void** p, size_t* cap, size_t need) {
+    if (need <= *cap) return DFR_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (*p) HIP_TRY(w, hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    const size_t c = round_up(need + need / 2, 1 << 20);
+    if (hipMalloc(p, c) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        w->err = "staging allocation failed";
+        return DFR_E_NO_MEMORY;
+    }
+    *cap = c;
+    w->n_allocs += 1;
+    w->ms_alloc += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return DFR_OK;
+}
+
+// Place of each request in the staging buffers: consecutive, each starting on a
+// 256-byte boundary (segments of a sort need not be adjacent), so that the copies
+// between a request's buffer and its place move aligned vectors.
+std::vector<uint64_t> batch_places(const std::vector<Server::Req>& b, uint64_t* end) {
+    std::vector<uint64_t> pos;
+    uint64_t p = 0;
+    for (const Server::Req& q : b) {
+        const uint64_t align = ALIGN / q.r.key_bytes;  // records per 256 bytes
+        p = (p + align - 1) / align * align;
+        pos.push_back(p);
+        p += q.r.n;
+    }
+    *end = p;
+    return pos;
+}
+
+// Chunks of at most 2^13 records over the batch's requests, between the requests'
+// buffers and their places in the staging buffers (one block copies one chunk).
+void batch_chunks(const std::vector<Server::Req>& b, void* sk, void* sv, bool to_staging,
+                  std::vector<CopyChunk>& out) {
+    out.clear();
+    uint64_t end = 0;
+    const std::vector<uint64_t> place = batch_places(b, &end);
+    for (size_t r = 0; r < b.size(); ++r) {
+        const Server::Req& q = b[r];
+        const int kb = q.r.key_bytes, vb = q.r.val_bytes;
+        const uint64_t pos = place[r];
+        for (uint64_t o = 0; o < q.r.n; o += 1u << 13) {
+            const uint32_t len = (uint32_t)std::min<uint64_t>(1u << 13, q.r.n - o);
+            char* rk = (char*)q.r.keys + o * kb;
+            char* rv = vb ? (char*)q.r.vals + o * vb : nullptr;
+            char* gk = (char*)sk + (pos + o) * kb;
+            char* gv = vb ? (char*)sv + (pos + o) * vb : nullptr;
+            CopyChunk ch{};
+            ch.ksrc = to_staging ? rk : gk;
+            ch.kdst = to_staging ? gk : rk;
+            ch.vsrc = to_staging ? rv : gv;
+            ch.vdst = to_staging ? gv : rv;
+            ch.len = len;
+            out.push_back(ch);
+        }
+    }
+}
+
+dfr_status copy_batch(Job& j, const std::vector<Server::Req>& b, void* sk, void* sv, bool to_staging) {
+    std::vector<CopyChunk> ch;
+    batch_chunks(b, sk, sv, to_staging, ch);
+    if (ch.empty()) return DFR_OK;
+    dfr_status st = arena_reserve(j.c, asize<CopyChunk>(ch.size()), j.s);
+    if (st) return st;
+    CopyChunk* d = aalloc<CopyChunk>(j.c, ch.size());
+    st = upload(j, d, ch.data(), ch.size() * sizeof(CopyChunk));
+    if (st) return st;
+    HIP_TRY(j.c, launch_copy_chunks(j.kb, j.vb, d, (uint32_t)ch.size(), j.s));
+    return DFR_OK;
+}
+
+// Sort one batch on the worker's stream and wait for it; ms[0..2] receive the device
+// time of the gather, the sort and the scatter.
+dfr_status run_batch(Server::Worker& wk, const std::vector<Server::Req>& b, double* ms) {
+    dfr_ctx* w = wk.w;
+    ms[0] = ms[1] = ms[2] = 0;
+    const int kb = b[0].r.key_bytes, vb = b[0].r.val_bytes;
+    uint64_t n = 0, records = 0;
+    const std::vector<uint64_t> place = batch_places(b, &n);
+    std::vector<LSeg> segs;
+    for (size_t r = 0; r < b.size(); ++r) {
+        segs.push_back(LSeg{place[r], b[r].r.n, 8 * kb});
+        records += b[r].r.n;
+    }
+    if (records <= 1) return DFR_OK;
+    void* temp = nullptr;
+    dfr_status st = get_temp(w, n, kb, vb, &temp, wk.s);
+    if (st) return st;
+    const bool gather = b.size() > 1;
+    if (!gather) {
+        HIP_TRY(w, hipEventRecord(wk.ev[1], wk.s));
+        st = run_sort(w, kb, vb, b[0].r.keys, vb ? b[0].r.vals : nullptr, segs, temp, wk.s);
+        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[2], wk.s));
+    } else {
+        st = grow(w, &wk.sk, &wk.skcap, n * kb);
+        if (!st && vb) st = grow(w, &wk.sv, &wk.svcap, n * vb);
+        if (st) return st;
+        Job j;
+        j.c = w;
+        j.kb = kb;
+        j.vb = vb;
+        j.s = wk.s;
+        HIP_TRY(w, hipEventRecord(wk.ev[0], wk.s));
+        st = copy_batch(j, b, wk.sk, wk.sv, true);
+        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[1], wk.s));
+        if (!st) st = run_sort(w, kb, vb, wk.sk, vb ? wk.sv : nullptr, segs, temp, wk.s);
+        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[2], wk.s));
+        if (!st) st = copy_batch(j, b, wk.sk, wk.sv, false);
+        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[3], wk.s));
+    }
+    if (!st) HIP_TRY(w, hipStreamSynchronize(wk.s));
+    synced(w);
+    if (!st) {
+        float f = 0;
+        if (gather && hipEventElapsedTime(&f, wk.ev[0], wk.ev[1]) == hipSuccess) ms[0] = f;
+        if (hipEventElapsedTime(&f, wk.ev[1], wk.ev[2]) == hipSuccess) ms[1] = f;
+        if (gather && hipEventElapsedTime(&f, wk.ev[2], wk.ev[3]) == hipSuccess) ms[2] = f;
+    }
+    return st;
+}
+
+void worker_loop(Server* sv, int wi) {
+    Server::Worker& wk = sv->workers[wi];
+    (void)hipSetDevice(sv->owner->device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        sv->cv.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
+        if (sv->stop) break;
+        // The oldest request, then later ones of the same widths, within the limit.
+        const Server::Req& head = sv->pending.front();
+        const int kb = head.r.key_bytes, vb = head.r.val_bytes;
+        std::vector<size_t> pick{0};
+        uint64_t total = head.r.n;
+        for (size_t i = 1; i < sv->pending.size(); ++i) {
+            const Server::Req& q = sv->pending[i];
+            if (q.r.key_bytes != kb || q.r.val_bytes != vb) continue;
+            if (total + q.r.n > sv->batch_records) continue;
+            pick.push_back(i);
+            total += q.r.n;
+        }
+        // Budget: drop the newest picks until the batch fits beside the other
+        // workers' memory; a lone request that does not fit frees this worker's
+        // caches, then waits for the others.
+        auto need_of = [&](uint64_t t, size_t cnt) { return batch_bytes(t, kb, vb, cnt > 1); };
+        bool fits = false;
+        while (!fits) {
+            const size_t others = sv->held - wk.held;
+            const size_t need = need_of(total, pick.size());
+            if (!sv->budget || others + std::max(need, wk.held) <= sv->budget) {
+                fits = true;
+            } else if (pick.size() > 1) {
+                total -= sv->pending[pick.back()].r.n;
+                pick.pop_back();
+            } else {
+                break;
+            }
+        }
+        if (!fits) {
+            if (wk.held) {
+                lk.unlock();
+                free_worker_buffers(wk);
+                lk.lock();
+                sv->held -= wk.held;
+                wk.held = 0;
+                sv->cv.notify_all();
+                continue;
+            }
+            sv->cv.wait(lk);
+            continue;
+        }
+        std::vector<Server::Req> batch;
+        for (size_t k = 0; k < pick.size(); ++k) batch.push_back(sv->pending[pick[k]]);
+        for (size_t k = pick.size(); k-- > 0;) sv->pending.erase(sv->pending.begin() + pick[k]);
+        for (const Server::Req& q : batch) sv->running[q.ticket] = 1;
+        // Count the batch's memory before it is allocated.
+        const size_t reserve = std::max(need_of(total, batch.size()), wk.held);
+        sv->held += reserve - wk.held;
+        wk.held = reserve;
+        sv->stats.peak_held_bytes = std::max<uint64_t>(sv->stats.peak_held_bytes, sv->held);
+        lk.unlock();
+
+        const auto t_start = std::chrono::steady_clock::now();
+        double ms[3];
+        const uint64_t allocs0 = wk.w->n_allocs;
+        const double ms_alloc0 = wk.w->ms_alloc;
+        const dfr_status st = run_batch(wk, batch, ms);
+        const auto t_end = std::chrono::steady_clock::now();
+
+        lk.lock();
+        const size_t actual = worker_bytes(wk);
+        sv->held = sv->held - wk.held + actual;
+        wk.held = actual;
+        sv->stats.peak_held_bytes = std::max<uint64_t>(sv->stats.peak_held_bytes, sv->held);
+        sv->stats.batches += 1;
+        sv->stats.requests += batch.size();
+        sv->stats.max_batch_requests = std::max<uint64_t>(sv->stats.max_batch_requests, batch.size());
+        sv->stats.records += total;
+        sv->stats.allocs += wk.w->n_allocs - allocs0;
+        sv->stats.ms_alloc += wk.w->ms_alloc - ms_alloc0;
+        sv->stats.ms_batch_wall += std::chrono::duration<double, std::milli>(t_end - t_start).count();
+        sv->stats.ms_gather += ms[0];
+        sv->stats.ms_sort += ms[1];
+        sv->stats.ms_scatter += ms[2];
+        for (const Server::Req& q : batch) {
+            sv->running.erase(q.ticket);
+            sv->done[q.ticket] = Server::Done{
+                st, std::chrono::duration<double>(t_end - q.t_submit).count()};
+        }
+        if (st) {
+            // Record the failure on the owner for dfr_last_error; the worker's context
+            // is rebuilt so later batches start clean.
+            sv->owner->err = "serving batch: " + wk.w->err;
+            wk.w->failed = false;
+        }
+        sv->cv.notify_all();
+    }
+}
+
+dfr_status start_server(dfr_ctx* c) {
+    Server* sv = new (std::nothrow) Server();
+    if (!sv) return DFR_E_NO_MEMORY;
+    sv->owner = c;
+    sv->budget = c->budget;
+    sv->batch_records = std::max<uint64_t>(c->serve_batch_records, 1);
+    const int nw = std::max(1, std::min(c->serve_workers, 8));
+    sv->workers.resize(nw);
+    for (int i = 0; i < nw; ++i) {
+        Server::Worker& wk = sv->workers[i];
+        wk.w = new dfr_ctx();
+        wk.w->device = c->device;
+        wk.w->divert = c->divert;
+        wk.w->radix_bits = c->radix_bits;
+        wk.w->tile_records = c->tile_records;
+        wk.w->window = c->window;
+        wk.w->tunes = c->tunes;
+        wk.w->temp_slack = 4;  // batches vary in size: grow the temp cache by half again
+        bool ok = hipStreamCreateWithFlags(&wk.s, hipStreamNonBlocking) == hipSuccess;
+        for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&wk.ev[e]) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            for (int k = 0; k <= i; ++k) {
+                if (sv->workers[k].s) (void)hipStreamDestroy(sv->workers[k].s);
+                for (auto e : sv->workers[k].ev)
+                    if (e) (void)hipEventDestroy(e);
+                delete sv->workers[k].w;
+            }
+            delete sv;
+            return DFR_E_HIP;
+        }
+    }
+    for (int i = 0; i < nw; ++i) sv->threads.emplace_back(worker_loop, sv, i);
+    c->server = sv;
+    return DFR_OK;
+}
+
+void stop_server(dfr_ctx* c) {
+    Server* sv = c->server;
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    for (auto& t : sv->threads) t.join();
+    for (auto& wk : sv->workers) {
+        free_worker_buffers(wk);
+        if (wk.w->err_dev) (void)hipFree(wk.w->err_dev);
+        if (wk.w->pin) (void)hipHostFree(wk.w->pin);
+        for (auto e : wk.w->event_pool) (void)hipEventDestroy(e);
+        for (auto e : wk.ev) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(wk.s);
+        delete wk.w;
+    }
+    delete sv;
+    c->server = nullptr;
+}
+
+}  // namespace
+
+// =================================================================================
 // C ABI
 // =================================================================================
 extern "C" {
@@ -1247,6 +1617,10 @@ dfr_status dfr_create(int hip_device, size_t hbm_budget_bytes, dfr_ctx** out) {
 void dfr_destroy(dfr_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    {
+        std::lock_guard<std::mutex> g(c->serve_mu);
+        stop_server(c);
+    }
     (void)hipDeviceSynchronize();
     if (c->arena) (void)hipFree(c->arena);
     if (c->err_dev) (void)hipFree(c->err_dev);
@@ -1527,17 +1901,68 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
 }
 
 dfr_status dfr_submit(dfr_ctx* c, const dfr_request* req, uint64_t* ticket) {
-    (void)c;
-    (void)req;
-    (void)ticket;
-    return DFR_E_UNSUPPORTED;
+    if (!c || !req || !ticket) return DFR_E_INVALID_ARG;
+    const int kb = req->key_bytes, vb = req->val_bytes;
+    if (!(kb == 4 || kb == 8) || !(vb == 0 || vb == 4 || vb == 8)) return DFR_E_INVALID_ARG;
+    if (vb && vb != kb) return DFR_E_INVALID_ARG;
+    if (req->n > DFR_MAX_SEGMENT_RECORDS) return DFR_E_TOO_LARGE;
+    if (req->n) {
+        if (!req->keys || (uintptr_t)req->keys % kb) return DFR_E_INVALID_ARG;
+        if (vb && (!req->vals || (uintptr_t)req->vals % vb)) return DFR_E_INVALID_ARG;
+        if (vb && overlap(req->keys, req->n * kb, req->vals, req->n * vb)) return DFR_E_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> g(c->serve_mu);
+    if (c->budget && batch_bytes(req->n, kb, vb, false) > c->budget) return DFR_E_BUDGET;
+    if (!c->server) {
+        dfr_status st = start_server(c);
+        if (st) return st;
+    }
+    Server* sv = c->server;
+    {
+        std::lock_guard<std::mutex> l(sv->mu);
+        Server::Req q;
+        q.ticket = sv->next_ticket++;
+        q.r = *req;
+        if (!vb) q.r.vals = nullptr;
+        q.t_submit = std::chrono::steady_clock::now();
+        sv->pending.push_back(q);
+        *ticket = q.ticket;
+    }
+    sv->cv.notify_all();
+    return DFR_OK;
 }
 
 dfr_status dfr_poll(dfr_ctx* c, uint64_t ticket, double* latency_s) {
-    (void)c;
-    (void)ticket;
-    (void)latency_s;
-    return DFR_E_UNSUPPORTED;
+    if (!c) return DFR_E_INVALID_ARG;
+    std::lock_guard<std::mutex> g(c->serve_mu);
+    Server* sv = c->server;
+    if (!sv) return DFR_E_NOT_FOUND;
+    std::lock_guard<std::mutex> l(sv->mu);
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) {
+        if (sv->running.count(ticket)) return DFR_E_PENDING;
+        for (const auto& q : sv->pending)
+            if (q.ticket == ticket) return DFR_E_PENDING;
+        return DFR_E_NOT_FOUND;
+    }
+    const Server::Done d = it->second;
+    sv->done.erase(it);
+    if (latency_s) *latency_s = d.latency;
+    return d.st;
+}
+
+dfr_status dfr_get_serve_stats(dfr_ctx* c, dfr_serve_stats* out) {
+    if (!c || !out) return DFR_E_INVALID_ARG;
+    std::lock_guard<std::mutex> g(c->serve_mu);
+    *out = dfr_serve_stats{};
+    if (!c->server) return DFR_OK;
+    std::lock_guard<std::mutex> l(c->server->mu);
+    *out = c->server->stats;
+    out->workers = (int32_t)c->server->workers.size();
+    out->budget_bytes = c->server->budget;
+    out->held_bytes = c->server->held;
+    out->queued = c->server->pending.size();
+    return DFR_OK;
 }
 
 dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
@@ -1558,6 +1983,18 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
     }
     if (!strcmp(name, "force_lookback")) {
         c->force_lookback = value != 0;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "serve_workers") || !strcmp(name, "serve_batch_records")) {
+        std::lock_guard<std::mutex> g(c->serve_mu);
+        if (c->server) return DFR_E_UNSUPPORTED;  // fixed once serving has started
+        if (!strcmp(name, "serve_workers")) {
+            if (value < 1 || value > 8) return DFR_E_INVALID_ARG;
+            c->serve_workers = (int)value;
+        } else {
+            if (value < 1) return DFR_E_INVALID_ARG;
+            c->serve_batch_records = (uint64_t)value;
+        }
         return DFR_OK;
     }
     if (!strcmp(name, "radix_bits")) {

@@ -188,6 +188,15 @@ struct LocalArgs {
     uint32_t* err;
 };
 
+// A run of at most 2^32 - 1 records copied between two places.
+struct CopyChunk {
+    const void* ksrc;
+    const void* vsrc;
+    void* kdst;
+    void* vdst;
+    uint32_t len;
+};
+
 // Tile and capacity choices per (key bytes, value bytes).
 uint32_t deal_tile_records(int kb, int vb);  // the default tile
 bool deal_tile_supported(int kb, int vb, uint32_t tile);  // the default or half of it
@@ -207,6 +216,8 @@ hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
                              hipStream_t s);
+hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t nchunks,
+                              hipStream_t s);
 hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, void* kout,
                              void* vout, const Tile* tiles, uint32_t ntiles, hipStream_t s);
 

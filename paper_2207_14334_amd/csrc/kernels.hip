@@ -1227,6 +1227,55 @@ __global__ __launch_bounds__(THREADS) void k_copy_tiles(const void* kin, const v
     }
 }
 
+// Copy of runs between arbitrary addresses (gathering requests into one batch and
+// scattering the sorted batch back).  Runs are whole 4-byte words; where source and
+// destination are both 16-byte aligned the body moves as 16-byte vectors, four in
+// flight per thread.
+template <int THREADS>
+__device__ __forceinline__ void copy_run(const void* src, void* dst, uint64_t bytes) {
+    const uint32_t tid = threadIdx.x;
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) {
+        const uint4* s4 = (const uint4*)src;
+        uint4* d4 = (uint4*)dst;
+        const uint64_t nvec = bytes >> 4;
+        for (uint64_t i = tid; i < nvec; i += 4 * THREADS) {
+            uint4 r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + u * THREADS < nvec) r[u] = s4[i + u * THREADS];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + u * THREADS < nvec) d4[i + u * THREADS] = r[u];
+        }
+        const uint64_t done = nvec << 4;
+        const uint32_t* sw = (const uint32_t*)((const char*)src + done);
+        uint32_t* dw = (uint32_t*)((char*)dst + done);
+        for (uint64_t i = tid; i < ((bytes - done) >> 2); i += THREADS) dw[i] = sw[i];
+    } else {
+        const uint32_t* sw = (const uint32_t*)src;
+        uint32_t* dw = (uint32_t*)dst;
+        const uint64_t nw = bytes >> 2;
+        for (uint64_t i = tid; i < nw; i += 4 * THREADS) {
+            uint32_t r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + u * THREADS < nw) r[u] = sw[i + u * THREADS];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + u * THREADS < nw) dw[i + u * THREADS] = r[u];
+        }
+    }
+}
+
+template <int KB, int VB, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_copy_chunks(const CopyChunk* chunks, uint32_t nchunks) {
+    for (uint32_t t = blockIdx.x; t < nchunks; t += gridDim.x) {
+        const CopyChunk ch = chunks[t];
+        copy_run<THREADS>(ch.ksrc, ch.kdst, (uint64_t)ch.len * KB);
+        if (VB) copy_run<THREADS>(ch.vsrc, ch.vdst, (uint64_t)ch.len * VB);
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Tile shapes and launchers.
 // ---------------------------------------------------------------------------------
@@ -1498,6 +1547,27 @@ hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s) {
         else ok = deal_kb_vb<8, 8>(a, s);
     }
     if (!ok) return hipErrorInvalidValue;  // no kernel for this tile size
+    return hipGetLastError();
+}
+
+template <int KB, int VB>
+static void copy_chunks_kb_vb(const CopyChunk* c, uint32_t n, hipStream_t s) {
+    const uint32_t blocks = n < 8192 ? n : 8192;
+    hipLaunchKernelGGL((k_copy_chunks<KB, VB, COPY_THREADS>), dim3(blocks), dim3(COPY_THREADS), 0, s, c, n);
+}
+
+hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t nchunks,
+                              hipStream_t s) {
+    if (nchunks == 0) return hipSuccess;
+    if (kb == 4) {
+        if (vb == 0) copy_chunks_kb_vb<4, 0>(chunks, nchunks, s);
+        else if (vb == 4) copy_chunks_kb_vb<4, 4>(chunks, nchunks, s);
+        else copy_chunks_kb_vb<4, 8>(chunks, nchunks, s);
+    } else {
+        if (vb == 0) copy_chunks_kb_vb<8, 0>(chunks, nchunks, s);
+        else if (vb == 4) copy_chunks_kb_vb<8, 4>(chunks, nchunks, s);
+        else copy_chunks_kb_vb<8, 8>(chunks, nchunks, s);
+    }
     return hipGetLastError();
 }
 

@@ -72,6 +72,14 @@ def test_null_context_and_bad_arguments(L):
     assert L.dfr_count(None, None, 4, 0, 8, 4, None, None) == dfr.E_INVALID_ARG
     off = (ctypes.c_uint64 * 3)(0, 5, 3)  # decreasing offsets
     assert L.dfr_sort_segmented_u32(None, P(4096), None, off, 2, None, 0, None) == dfr.E_INVALID_ARG
+    t = ctypes.c_uint64(0)
+    req = dfr.Request(4, 4, 4096, 8192, 10)
+    assert L.dfr_submit(None, ctypes.byref(req), ctypes.byref(t)) == dfr.E_INVALID_ARG
+    assert L.dfr_poll(None, 1, None) == dfr.E_INVALID_ARG
+    assert L.dfr_get_serve_stats(None, None) == dfr.E_INVALID_ARG
+    assert L.dfr_autotune(None, 4, 4, None, None, None, 0, 1, None, None) == dfr.E_INVALID_ARG
+    assert L.dfr_get_tune(None, 4, 4, 0, None) == dfr.E_INVALID_ARG
+    assert L.dfr_set_tune(None, 4, 4, 0, None) == dfr.E_INVALID_ARG
 
 
 def test_create_without_gpu_fails_cleanly(L):
