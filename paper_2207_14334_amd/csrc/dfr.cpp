@@ -703,7 +703,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const uint64_t ntiles = tiles.size();
     const size_t need_b = asize<Tile>(ntiles) + asize<Tile>(nht) + asize<Seg>(S) +
                           asize<uint32_t>(ntiles * RADIX + 1) +
-                          asize<uint64_t>(nht + 1) + asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
+                          asize<uint32_t>(nht) + asize<uint64_t>(nht) + asize<uint16_t>(nht * HEAD_SLOTS) +
+                          asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
                           2 * asize<Big>(bigcap) + 2 * asize<uint32_t>(nslots + medcap) +
                           asize<uint32_t>(8);
@@ -726,7 +727,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     Tile* dhtiles = aalloc<Tile>(c, nht);
     Seg* dsegs = aalloc<Seg>(c, S);
     uint32_t* lb = aalloc<uint32_t>(c, ntiles * RADIX + 1);
-    uint64_t* lb64 = aalloc<uint64_t>(c, nht + 1);
+    uint32_t* htcount = aalloc<uint32_t>(c, nht);
+    uint64_t* htbase = aalloc<uint64_t>(c, nht);
+    uint16_t* htslot = aalloc<uint16_t>(c, nht * HEAD_SLOTS);
     uint64_t* dbstart = aalloc<uint64_t>(c, bcap);
     uint32_t* dbseg = aalloc<uint32_t>(c, bcap);
     uint32_t* cfirst = aalloc<uint32_t>(c, nslots);
@@ -833,7 +836,6 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     {
         Timed tm(c, j.s, ST_BUCKETS);
         HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
-        HIP_TRY(c, launch_fill_u64(lb64, 0, nht + 1, j.s));
         HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
         HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
         HeadArgs ha{};
@@ -841,8 +843,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ha.tiles = dhtiles;
         ha.ntiles = (uint32_t)nht;
         ha.segs = dsegs;
-        ha.lookback = lb64;
-        ha.ticket = (uint32_t*)(lb64 + nht);
+        ha.tcount = htcount;
+        ha.tbase = htbase;
+        ha.tslot = htslot;
         ha.bstart = dbstart;
         ha.bseg = dbseg;
         ha.bcap = bcap;

@@ -121,13 +121,18 @@ struct DealArgs {
     uint32_t* err;
 };
 
+// Bucket heads per tile, at most HEAD_SLOTS of them kept per tile as tile-relative
+// positions; a tile with more is found again from its keys when the heads are listed.
+constexpr uint32_t HEAD_SLOTS = 256;
+
 struct HeadArgs {
     const void* keys;
     const Tile* tiles;
     uint32_t ntiles;
     const Seg* segs;
-    uint64_t* lookback;  // [ntiles]
-    uint32_t* ticket;
+    uint32_t* tcount;    // [ntiles] heads in each tile
+    uint64_t* tbase;     // [ntiles] index of each tile's first head in the bucket list
+    uint16_t* tslot;     // [ntiles][HEAD_SLOTS] tile-relative positions of the heads
     uint64_t* bstart;
     uint32_t* bseg;
     uint64_t bcap;

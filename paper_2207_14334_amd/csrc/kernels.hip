@@ -37,6 +37,7 @@ struct uint_of<8> {
 
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
+
 // Tile order of the look-back-free deal: 0 block index, 1 ticket, 2 one contiguous
 // range of tiles per XCD.
 #ifndef DFR_DEAL_ORDER
@@ -498,13 +499,9 @@ __global__ __launch_bounds__(THREADS) void k_heads(HeadArgs a) {
     constexpr int W = THREADS / 64;
     constexpr int KBITS = 8 * KB;
     __shared__ uint32_t s_wtot[W];
-    __shared__ uint32_t s_ticket;
-    __shared__ uint64_t s_excl;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const uint32_t t = s_ticket;
+    const uint32_t t = blockIdx.x;
     if (t >= a.ntiles) return;
     const Tile tl = a.tiles[t];
     const Seg* sg = a.segs + tl.seg;
@@ -548,67 +545,99 @@ __global__ __launch_bounds__(THREADS) void k_heads(HeadArgs a) {
     }
     if (lane == 0) s_wtot[w] = run;
     __syncthreads();
-    if (w == 0) {
-        // Wave 0 publishes the tile's count, then looks back 64 tiles per step: lane i
-        // reads tile j - i; the walk ends at the newest inclusive prefix once every
-        // word up to it is published.
-        uint32_t tot = 0;
-        for (int ww = 0; ww < W; ++ww) tot += s_wtot[ww];
-        if (lane == 0)
-            __hip_atomic_store(&a.lookback[t], (t == 0 ? LB64_PRE : LB64_AGG) | (uint64_t)tot,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t excl = 0;
-        int64_t j = (int64_t)t - 1;
-        uint32_t spins = 0;
-        while (j >= 0) {
-            const int64_t jj = j - lane;
-            const uint64_t x = jj >= 0 ? __hip_atomic_load(&a.lookback[jj], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : LB64_PRE;
-            const uint64_t pre = __ballot((x & LB64_PRE) != 0);
-            const int stop = pre ? (int)__builtin_ctzll(pre) : 63;  // last lane to take
-            const uint64_t upto = stop == 63 ? ~0ull : ((2ull << stop) - 1);
-            const uint64_t unready = __ballot((x & (LB64_AGG | LB64_PRE)) == 0) & upto;
-            if (unready) {
-                if (++spins > SPIN_LIMIT) {
-                    if (lane == 0) atomicOr(a.err, ERR_SPIN);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-                continue;
-            }
-            uint64_t c = ((uint64_t)lane <= (uint64_t)stop) ? (x & LB64_COUNT) : 0;
+    uint32_t tot = 0, wexcl = 0;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-            excl += c;
-            if (pre) break;
-            j -= 64;
-        }
-        if (lane == 0) {
-            if (t != 0)
-                __hip_atomic_store(&a.lookback[t], LB64_PRE | (excl + tot), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            if (t == a.ntiles - 1) {
-                const uint64_t nbk = excl + tot;
-                *a.nbuckets = nbk > 0xffffffffull ? 0xffffffffu : (uint32_t)nbk;
-            }
-            s_excl = excl;
-        }
+    for (int ww = 0; ww < W; ++ww) {
+        wexcl += ww < w ? s_wtot[ww] : 0u;
+        tot += s_wtot[ww];
     }
-    __syncthreads();
-    uint64_t wexcl = s_excl;
-    for (int ww = 0; ww < w; ++ww) wexcl += s_wtot[ww];
-    bool over = false;
+    if (tid == 0) a.tcount[t] = tot;
+    if (tot > HEAD_SLOTS) return;  // listed again from the keys (k_heads_emit)
+    uint16_t* slot = a.tslot + (size_t)t * HEAD_SLOTS;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        if (head[k]) {
-            const uint64_t gi = wexcl + off[k];
-            if (gi < a.bcap) {
-                a.bstart[gi] = tl.start + wbase + k * 64 + lane;
-                a.bseg[gi] = tl.seg;
-            } else {
-                over = true;
+    for (int k = 0; k < ITEMS; ++k)
+        if (head[k]) slot[wexcl + off[k]] = (uint16_t)(wbase + k * 64 + lane);
+}
+
+// Exclusive scan of the tiles' head counts (one block): tile bases in the bucket list.
+__global__ __launch_bounds__(1024) void k_heads_scan(HeadArgs a) {
+    __shared__ uint64_t s_part[1024 / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t per = (a.ntiles + 1023) / 1024;
+    const uint32_t t0 = tid * per < a.ntiles ? tid * per : a.ntiles;
+    const uint32_t t1 = t0 + per < a.ntiles ? t0 + per : a.ntiles;
+    uint64_t sum = 0;
+    for (uint32_t t = t0; t < t1; ++t) sum += a.tcount[t];
+    uint64_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(incl, o, 64);
+        if ((int)lane >= o) incl += y;
+    }
+    if (lane == 63) s_part[w] = incl;
+    __syncthreads();
+    uint64_t run = incl - sum, total = 0;
+    for (uint32_t ww = 0; ww < 1024 / 64; ++ww) {
+        run += ww < w ? s_part[ww] : 0ull;
+        total += s_part[ww];
+    }
+    for (uint32_t t = t0; t < t1; ++t) {
+        a.tbase[t] = run;
+        run += a.tcount[t];
+    }
+    if (tid == 0) *a.nbuckets = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
+}
+
+// The bucket list in position order: one wave per tile copies the tile's kept heads,
+// or finds them again from the keys when the tile had more than HEAD_SLOTS.
+template <int KB>
+__global__ __launch_bounds__(256) void k_heads_emit(HeadArgs a) {
+    using K = typename uint_of<KB>::type;
+    constexpr int KBITS = 8 * KB;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wid = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    const uint32_t nw = gridDim.x * 4;
+    bool over = false;
+    for (uint32_t t = wid; t < a.ntiles; t += nw) {
+        const uint32_t n = a.tcount[t];
+        const uint64_t base = a.tbase[t];
+        const Tile tl = a.tiles[t];
+        if (n <= HEAD_SLOTS) {
+            const uint16_t* slot = a.tslot + (size_t)t * HEAD_SLOTS;
+            for (uint32_t i = lane; i < n; i += 64) {
+                const uint64_t gi = base + i;
+                if (gi < a.bcap) {
+                    a.bstart[gi] = tl.start + slot[i];
+                    a.bseg[gi] = tl.seg;
+                } else {
+                    over = true;
+                }
             }
+            continue;
+        }
+        const Seg* sg = a.segs + tl.seg;
+        const int lo = sg->lo_bit;
+        const K* kp = (const K*)a.keys + tl.start;
+        uint64_t run = base;
+        for (uint32_t i0 = 0; i0 < tl.len; i0 += 64) {
+            const uint32_t idx = i0 + lane;
+            const uint64_t gpos = tl.start + idx;
+            bool h = false;
+            if (idx < tl.len) {
+                if (gpos == sg->start) h = true;
+                else if (lo < KBITS) h = (kp[idx] >> lo) != (kp[(int64_t)idx - 1] >> lo);
+            }
+            const uint64_t hb = __ballot(h);
+            if (h) {
+                const uint64_t gi = run + lanes_below(hb);
+                if (gi < a.bcap) {
+                    a.bstart[gi] = gpos;
+                    a.bseg[gi] = tl.seg;
+                } else {
+                    over = true;
+                }
+            }
+            run += (uint64_t)__popcll(hb);
         }
     }
     if (over) atomicOr(a.err, ERR_BUCKET_CAP);
@@ -763,8 +792,11 @@ __device__ __forceinline__ void wave0_offsets(uint32_t* cnt, int w, int lane) {
 // bits do not fit next to the position, or whose largest bin exceeds GMAX records,
 // goes to the spill list for the stable radix kernel below.
 // ---------------------------------------------------------------------------------
+#ifndef DFR_LOCAL_MIN_WAVES  // waves per SIMD the bucketed local sort must fit
+#define DFR_LOCAL_MIN_WAVES 6
+#endif
 template <int KB, int VB, int THREADS, int CAP>
-__global__ __launch_bounds__(THREADS, 3 * THREADS / 256) void k_local_sort_bucket(LocalArgs a) {
+__global__ __launch_bounds__(THREADS, DFR_LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
@@ -775,6 +807,8 @@ __global__ __launch_bounds__(THREADS, 3 * THREADS / 256) void k_local_sort_bucke
     constexpr int NWORDS = (1 << DB) / 2;  // two 16-bit bin counters per LDS word
     constexpr uint32_t GMAX = 64;
     static_assert(CAP % THREADS == 0 && CAP <= (1 << IB), "chunk layout");
+    static_assert(CAP < (1 << 16), "a destination and a source share one 32-bit word");
+    static_assert(VB <= 8, "values fit the word buffer");
 
     __shared__ uint64_t s_w[CAP];
     __shared__ uint32_t s_bin[NWORDS];
@@ -945,19 +979,19 @@ __global__ __launch_bounds__(THREADS, 3 * THREADS / 256) void k_local_sort_bucke
             }
         }
         __syncthreads();
-        // Rank inside the bin (its start plus the smaller words in it), then gather the
-        // value and the key's high bits; all reads happen before any write, since the
-        // output may be the input buffer itself.
-        uint32_t pos[MAXI];
+        // Rank inside the bin (its start plus the smaller words in it) and rebuild the
+        // key; then the values are loaded (coalesced), and with every word ranked the
+        // word buffer holds them by input position, so each is gathered from LDS by the
+        // position its word carries.  All reads of the input happen before the barrier
+        // that precedes the writes, since the output may be the input buffer itself.
+        uint32_t pos[MAXI];  // destination in the low 16 bits, source above
         K ko[MAXI];
-        V vo[MAXI];
         const uint64_t hi0 = (uint64_t)key0 & ~mask_h;
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
             const uint32_t p = wbase + k * 64 + lane;
             pos[k] = 0xffffffffu;
             ko[k] = 0;
-            vo[k] = 0;
             if ((uint32_t)k < iu && p < len) {
                 const uint64_t me = s_w[p];
                 const uint32_t d = (uint32_t)(me >> dshift) & (nbins - 1);
@@ -969,18 +1003,35 @@ __global__ __launch_bounds__(THREADS, 3 * THREADS / 256) void k_local_sort_bucke
                 const uint32_t at = gs + r < len ? gs + r : len - 1;
                 const uint32_t src = (uint32_t)me & ((1u << IB) - 1u);
                 const uint64_t hi = nbk > 1 ? ((uint64_t)kin[at] & ~mask_h) : hi0;
-                pos[k] = at;
+                pos[k] = at | (src << 16);
                 ko[k] = (K)(((me >> IB) & mask_h) | hi);
-                if (VB) vo[k] = vin[src < len ? src : 0];
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
+        V vx[MAXI];
+        if (VB) {
+#pragma unroll
+            for (int k = 0; k < MAXI; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                vx[k] = ((uint32_t)k < iu && idx < len) ? vin[idx] : V(0);
+            }
+        }
+        __syncthreads();  // every word ranked: the word buffer takes the values
+        V* s_v = (V*)s_w;
+        if (VB) {
+#pragma unroll
+            for (int k = 0; k < MAXI; ++k) {
+                const uint32_t idx = wbase + k * 64 + lane;
+                if ((uint32_t)k < iu && idx < len) s_v[idx] = vx[k];
+            }
+            __syncthreads();
+        }
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
-            if (pos[k] < len) {
-                kout[pos[k]] = ko[k];
-                if (VB) vout[pos[k]] = vo[k];
+            if (pos[k] != 0xffffffffu) {
+                const uint32_t at = pos[k] & 0xffffu, src = (pos[k] >> 16) < len ? pos[k] >> 16 : 0;
+                kout[at] = ko[k];
+                if (VB) vout[at] = s_v[src];
             }
         }
         __syncthreads();
@@ -1576,8 +1627,17 @@ hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s) {
     // Tiles are the deal tiles of the level; the head kernel's block covers the
     // largest of them (8192 records).
     constexpr int ITEMS = DEAL_TILE_SMALL / HEAD_THREADS;
-    if (kb == 4) hipLaunchKernelGGL((k_heads<4, HEAD_THREADS, ITEMS>), dim3(a.ntiles), dim3(HEAD_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_heads<8, HEAD_THREADS, ITEMS>), dim3(a.ntiles), dim3(HEAD_THREADS), 0, s, a);
+    static_assert(DEAL_TILE_SMALL <= 65536, "tile-relative head positions are 16-bit");
+    const uint32_t emit_blocks = std::min<uint32_t>((a.ntiles + 3) / 4, 4096);
+    if (kb == 4) {
+        hipLaunchKernelGGL((k_heads<4, HEAD_THREADS, ITEMS>), dim3(a.ntiles), dim3(HEAD_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_heads_emit<4>, dim3(emit_blocks), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_heads<8, HEAD_THREADS, ITEMS>), dim3(a.ntiles), dim3(HEAD_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_heads_emit<8>, dim3(emit_blocks), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
