@@ -197,7 +197,9 @@ dfr_status dfr_get_serve_stats(dfr_ctx* ctx, dfr_serve_stats* out);
  *   "force_top_digits" d, the number of top digits dealt before diversion at the
  *                     first level (0 = estimate it, Sec. 3).  A value >= the number
  *                     of varying digits deals all of them (plain LSD, Sec. 2.1).
- *   "timing"          1 to record per-kernel durations with HIP events, 0 to stop.
+ *   "timing"          1 to record per-stage kernel durations with HIP events, 2 to
+ *                     record only the deal launches (fewer events in the stream), 0
+ *                     to stop.
  *   "force_lookback"  1 to deal every level with decoupled look-back between tiles
  *                     instead of scanning the tiles' bucket bases ahead of the deal
  *                     (same result; for testing and measurement), 0 to restore.

@@ -84,7 +84,7 @@ struct dfr_ctx {
     // Options.
     size_t divert = 0;  // 0 = default N_d
     int force_d = 0;
-    bool timing = false;
+    int timing = 0;  // 1 every stage, 2 the deal launches only
     bool force_lookback = false;  // deal every level with decoupled look-back
     int radix_bits = 0;           // 0 = tuned or default
     uint32_t tile_records = 0;
@@ -220,7 +220,7 @@ struct Timed {
     bool deal;
     hipEvent_t a = nullptr;
     Timed(dfr_ctx* c_, hipStream_t s_, int st, bool d = false) : c(c_), s(s_), stage(st), deal(d) {
-        if (c->timing) {
+        if (c->timing == 1 || (c->timing == 2 && deal)) {
             a = get_event(c);
             if (a) (void)hipEventRecord(a, s);
         }
@@ -389,6 +389,7 @@ struct Job {
     bool first_level = true;
     int top_d_forced = 0;
     uint32_t err_word_host = 0;
+    bool err_known = false;  // err_word_host holds the word after the last error-setting kernel
     uint32_t* err_dev = nullptr;
 };
 
@@ -440,6 +441,7 @@ dfr_status copy_back(Job& j, const std::vector<std::pair<uint64_t, uint64_t>>& r
 // each segment is one bucket and one local-sort chunk of its own.
 dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     dfr_ctx* c = j.c;
+    j.err_known = false;
     const size_t S = segs.size();
     std::vector<Seg> hs(S);
     std::vector<uint64_t> bstart;
@@ -516,6 +518,7 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
 dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector<LSeg>& next,
                       int* next_in) {
     dfr_ctx* c = j.c;
+    j.err_known = false;
     const size_t S = segs.size();
     const int kb = j.kb;
     const int rb = j.rb;
@@ -554,8 +557,10 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     aalloc<uint64_t>(c, S);
     const size_t off_tcnt = c->arena_used;
     aalloc<uint32_t>(c, tcnt_n);
+    const size_t off_ctiles = c->arena_used;  // the counting tile list, kept for reuse
+    aalloc<Tile>(c, tiles.size());
     const size_t region_a = c->arena_used;
-    Tile* dtiles = aalloc<Tile>(c, tiles.size());
+    Tile* dtiles = (Tile*)(c->arena + off_ctiles);
     uint32_t* dhist = (uint32_t*)(c->arena + off_hist);
     uint64_t* dor = (uint64_t*)(c->arena + off_or);
     uint64_t* dand = (uint64_t*)(c->arena + off_and);
@@ -638,7 +643,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         dsel[i] = di;
         d = std::max(d, di);
     }
-    c->arena_used = region_a;  // the counting tile list is no longer needed
+    c->arena_used = region_a;  // the rest of the arena is free again
     if (in == 1) {
         st = copy_back(j, finished);
         if (st) return st;
@@ -655,7 +660,11 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     bool all_full = true;
     uint64_t nslots = 0, medcap = 0, bcap = 0, bigcap = 0;
     const std::vector<uint32_t> count_tile = first_tile;  // tiles of the counting list
-    build_tiles(segs, active, j.tile, tiles, first_tile);
+    // When every segment is dealt, in its original order, the deal's tile list is the
+    // counting list, already on the device.
+    bool same_tiles = active.size() == S;
+    for (size_t i = 0; same_tiles && i < S; ++i) same_tiles = active[i] == i;
+    if (!same_tiles) build_tiles(segs, active, j.tile, tiles, first_tile);
     std::vector<uint32_t> pass_tiles(d, 0);  // tiles dealt in pass p
     for (uint32_t i : active) {
         const uint64_t nt = (segs[i].len + j.tile - 1) / j.tile;
@@ -693,11 +702,15 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         }
         hs[i] = g;
     }
-    // Tiles whose buckets are found after the deals: those of segments not yet sorted.
+    // Tiles whose buckets are found after the deals: those of segments not yet sorted
+    // (the deal's list itself when no segment is).
+    bool any_full = false;
+    for (uint32_t i : active) any_full = any_full || full[i];
     std::vector<Tile> htiles;
-    for (const Tile& t : tiles)
-        if (!full[t.seg]) htiles.push_back(t);
-    const uint64_t nht = htiles.size();
+    if (any_full)
+        for (const Tile& t : tiles)
+            if (!full[t.seg]) htiles.push_back(t);
+    const uint64_t nht = any_full ? htiles.size() : tiles.size();
 
     // --- 3. deal ------------------------------------------------------------------
     const uint64_t ntiles = tiles.size();
@@ -723,8 +736,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         tone = aalloc<uint32_t>(c, ntiles * RADIX);
     }
     if (single) tpart = aalloc<uint32_t>(c, (size_t)scan_nb * RADIX);
-    dtiles = aalloc<Tile>(c, ntiles);
-    Tile* dhtiles = aalloc<Tile>(c, nht);
+    dtiles = same_tiles ? (Tile*)(c->arena + off_ctiles) : aalloc<Tile>(c, ntiles);
+    Tile* dhtiles = any_full ? aalloc<Tile>(c, nht) : dtiles;
     Seg* dsegs = aalloc<Seg>(c, S);
     uint32_t* lb = aalloc<uint32_t>(c, ntiles * RADIX + 1);
     uint32_t* htcount = aalloc<uint32_t>(c, nht);
@@ -740,8 +753,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work
-    st = upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
-    if (!st) st = upload(j, dhtiles, htiles.data(), nht * sizeof(Tile));
+    st = same_tiles ? DFR_OK : upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
+    if (!st && any_full) st = upload(j, dhtiles, htiles.data(), nht * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
     if (st) return st;
 
@@ -914,8 +927,14 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     st = pin_reserve(c, 8 * 4 + 2 * bigcap * sizeof(Big) + 256, j.s);
     if (st) return st;
     uint32_t* hc = palloc<uint32_t>(c, 8);
+    uint32_t* he = palloc<uint32_t>(c, 1);
     HIP_TRY(c, hipMemcpyAsync(hc, counters, 8 * 4, hipMemcpyDeviceToHost, j.s));
+    // The error word comes back with the counters: no kernel after this point can set
+    // it unless another level runs (which clears err_known).
+    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, 4, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipStreamSynchronize(j.s));
+    j.err_word_host = *he;
+    j.err_known = true;
     const uint32_t nbig = std::min<uint32_t>(hc[2], (uint32_t)bigcap);
     const uint32_t ndone = std::min<uint32_t>(hc[3], (uint32_t)bigcap);
     c->stats.chunks += hc[0];
@@ -940,13 +959,16 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
 
 dfr_status check_err(Job& j) {
     dfr_ctx* c = j.c;
-    dfr_status st = pin_reserve(c, 64, j.s);
-    if (st) return st;
-    uint32_t* h = palloc<uint32_t>(c, 1);
-    HIP_TRY(c, hipMemcpyAsync(h, j.err_dev, 4, hipMemcpyDeviceToHost, j.s));
-    HIP_TRY(c, hipStreamSynchronize(j.s));
-    const uint32_t e = *h;
-    synced(c);
+    uint32_t e = j.err_word_host;
+    if (!j.err_known) {
+        dfr_status st = pin_reserve(c, 64, j.s);
+        if (st) return st;
+        uint32_t* h = palloc<uint32_t>(c, 1);
+        HIP_TRY(c, hipMemcpyAsync(h, j.err_dev, 4, hipMemcpyDeviceToHost, j.s));
+        HIP_TRY(c, hipStreamSynchronize(j.s));
+        e = *h;
+        synced(c);
+    }
     if (e) {
         char buf[128];
         snprintf(buf, sizeof buf, "device error word 0x%x", e);
@@ -1171,8 +1193,8 @@ dfr_status autotune(dfr_ctx* c, int kb, int vb, const void* keys, const void* va
         cleanup();
         return fail_hip(c, hipErrorUnknown, "autotune: events");
     }
-    const bool timing = c->timing;
-    c->timing = false;
+    const int timing = c->timing;
+    c->timing = 0;
     const size_t cap = local_cap(kb, vb);
     const uint32_t tile = deal_tile_records(kb, vb);
     std::vector<std::vector<uint64_t>> choices = {
@@ -1981,7 +2003,8 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
         return DFR_OK;
     }
     if (!strcmp(name, "timing")) {
-        c->timing = value != 0;
+        if (value < 0 || value > 2) return DFR_E_INVALID_ARG;
+        c->timing = (int)value;
         return DFR_OK;
     }
     if (!strcmp(name, "force_lookback")) {

@@ -560,32 +560,57 @@ __global__ __launch_bounds__(THREADS) void k_heads(HeadArgs a) {
 }
 
 // Exclusive scan of the tiles' head counts (one block): tile bases in the bucket list.
+// Each wave owns a contiguous range of tiles and reads it 64 tiles wide, eight loads in
+// flight per lane.
 __global__ __launch_bounds__(1024) void k_heads_scan(HeadArgs a) {
-    __shared__ uint64_t s_part[1024 / 64];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t per = (a.ntiles + 1023) / 1024;
-    const uint32_t t0 = tid * per < a.ntiles ? tid * per : a.ntiles;
-    const uint32_t t1 = t0 + per < a.ntiles ? t0 + per : a.ntiles;
+    constexpr uint32_t NW = 1024 / 64, U = 8;
+    __shared__ uint64_t s_part[NW];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t per = ((a.ntiles + NW - 1) / NW + 63) / 64 * 64;
+    const uint32_t w0 = w * per < a.ntiles ? w * per : a.ntiles;
+    const uint32_t w1 = w0 + per < a.ntiles ? w0 + per : a.ntiles;
     uint64_t sum = 0;
-    for (uint32_t t = t0; t < t1; ++t) sum += a.tcount[t];
-    uint64_t incl = sum;
+    for (uint32_t b = w0; b < w1; b += 64 * U) {
+        uint32_t c[U];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t y = __shfl_up(incl, o, 64);
-        if ((int)lane >= o) incl += y;
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = b + u * 64 + lane;
+            c[u] = i < w1 ? a.tcount[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) sum += c[u];
     }
-    if (lane == 63) s_part[w] = incl;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (lane == 0) s_part[w] = sum;
     __syncthreads();
-    uint64_t run = incl - sum, total = 0;
-    for (uint32_t ww = 0; ww < 1024 / 64; ++ww) {
+    uint64_t run = 0, total = 0;
+#pragma unroll
+    for (uint32_t ww = 0; ww < NW; ++ww) {
         run += ww < w ? s_part[ww] : 0ull;
         total += s_part[ww];
     }
-    for (uint32_t t = t0; t < t1; ++t) {
-        a.tbase[t] = run;
-        run += a.tcount[t];
+    for (uint32_t b = w0; b < w1; b += 64 * U) {
+        uint32_t c[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = b + u * 64 + lane;
+            c[u] = i < w1 ? a.tcount[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            uint64_t incl = c[u];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint64_t y = __shfl_up(incl, o, 64);
+                if ((int)lane >= o) incl += y;
+            }
+            const uint32_t i = b + u * 64 + lane;
+            if (i < w1) a.tbase[i] = run + incl - c[u];
+            run += __shfl(incl, 63, 64);
+        }
     }
-    if (tid == 0) *a.nbuckets = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
+    if (threadIdx.x == 0) *a.nbuckets = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
 }
 
 // The bucket list in position order: one wave per tile copies the tile's kept heads,
