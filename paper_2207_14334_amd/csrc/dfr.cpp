@@ -461,9 +461,10 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     if (nb == 0) return DFR_OK;
     std::vector<uint32_t> med(nb);
     for (uint64_t i = 0; i < nb; ++i) med[i] = (uint32_t)i;
-    uint32_t counts3[4] = {(uint32_t)nb, (uint32_t)nb, 0, (uint32_t)nb};  // buckets, medium, spills, work
-    const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + 3 * asize<uint32_t>(nb) +
-                        asize<uint32_t>(4) + asize<uint32_t>(1);
+    // buckets, medium, spills, work, wide
+    uint32_t counts3[5] = {(uint32_t)nb, (uint32_t)nb, 0, (uint32_t)nb, 0};
+    const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + 4 * asize<uint32_t>(nb) +
+                        asize<uint32_t>(5) + asize<uint32_t>(1);
     dfr_status st = arena_reserve(c, need, j.s);
     if (st) return st;
     Seg* dsegs = aalloc<Seg>(c, S);
@@ -471,7 +472,8 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     uint32_t* dbseg = aalloc<uint32_t>(c, nb);
     uint32_t* dmed = aalloc<uint32_t>(c, nb);
     uint32_t* dspill = aalloc<uint32_t>(c, nb);
-    uint32_t* dcounts = aalloc<uint32_t>(c, 4);
+    uint32_t* dwide = aalloc<uint32_t>(c, nb);
+    uint32_t* dcounts = aalloc<uint32_t>(c, 5);
     uint32_t* dnone = aalloc<uint32_t>(c, 1);
     st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
     if (!st) st = upload(j, dbstart, bstart.data(), nb * sizeof(uint64_t));
@@ -503,6 +505,9 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         la.spill = dspill;
         la.nspill = dcounts + 2;
         la.spillcap = (uint32_t)nb;
+        la.wide = dwide;
+        la.nwide = dcounts + 4;
+        la.widecap = (uint32_t)nb;
         la.err = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nb, 8192);
         HIP_TRY(c, launch_local_sort(j.kb, j.vb, la, blocks, j.s));
@@ -719,7 +724,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                           asize<uint32_t>(nht) + asize<uint64_t>(nht) + asize<uint16_t>(nht * HEAD_SLOTS) +
                           asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
-                          2 * asize<Big>(bigcap) + 2 * asize<uint32_t>(nslots + medcap) +
+                          2 * asize<Big>(bigcap) + 3 * asize<uint32_t>(nslots + medcap) +
                           asize<uint32_t>(8);
     const uint32_t scan_tpb = 128;
     const uint32_t scan_nb = (uint32_t)((ntiles + scan_tpb - 1) / scan_tpb);
@@ -752,7 +757,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     Big* done = aalloc<Big>(c, bigcap);
     uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
-    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work
+    uint32_t* wide = aalloc<uint32_t>(c, nslots + medcap);
+    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work, wide
     st = same_tiles ? DFR_OK : upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
     if (!st && any_full) st = upload(j, dhtiles, htiles.data(), nht * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
@@ -917,6 +923,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         la.spill = spill;
         la.nspill = counters + 4;
         la.spillcap = (uint32_t)(nslots + medcap);
+        la.wide = wide;
+        la.nwide = counters + 6;
+        la.widecap = (uint32_t)(nslots + medcap);
         la.err = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 8192);
         HIP_TRY(c, launch_local_sort(kb, j.vb, la, blocks, j.s));

@@ -189,6 +189,9 @@ struct LocalArgs {
     uint32_t* spill;    // chunks the packed local sort hands to the general one
     uint32_t* nspill;   // zero before the launch
     uint32_t spillcap;
+    uint32_t* wide;     // chunks the 32-bit-word form hands to the 64-bit-word form
+    uint32_t* nwide;    // zero before the launch
+    uint32_t widecap;
     int32_t spill_only; // set by the launcher
     uint32_t* err;
 };

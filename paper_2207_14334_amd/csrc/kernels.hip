@@ -802,6 +802,171 @@ __device__ __forceinline__ void wave0_offsets(uint32_t* cnt, int w, int lane) {
     }
 }
 
+// The sort phase of the bucketed local sort, on words of type WT: 32-bit when the
+// sort bits and the position fit in 32 bits, else 64-bit.  x holds the chunk's keys
+// as loaded; s_rel the buckets' starts relative to the chunk (nbk > 1).  Returns
+// false, uniformly across the block, when the largest bin exceeds GMAX (the chunk then
+// goes to the stable kernel); otherwise the chunk is sorted into kout/vout.
+template <int MAXI>
+struct Words {
+    uint64_t v[MAXI];
+};
+
+template <typename WT, int KB, int VB, int THREADS, int CAP, int IB, int DB, int MAXI>
+__device__ __forceinline__ bool bucket_sort_chunk(
+    Words<MAXI> x, uint32_t len, uint32_t iu, uint32_t wbase, int lane, int w,
+    int tid, uint32_t nbk, int h, int B, typename uint_of<KB>::type key0,
+    const typename uint_of<KB>::type* kin, const typename uint_of<VB>::type* vin,
+    typename uint_of<KB>::type* kout, typename uint_of<VB>::type* vout, const uint32_t* s_rel,
+    WT* s_w, uint32_t* s_bin, uint32_t* s_part, uint32_t* s_max) {
+    using K = typename uint_of<KB>::type;
+    using V = typename uint_of<VB>::type;
+    constexpr int W = THREADS / 64;
+    constexpr uint32_t GMAX = 64;
+    const uint64_t mask_h = (1ull << h) - 1ull;  // h < 64 here
+    WT xw[MAXI];
+
+#pragma unroll
+    for (int k = 0; k < MAXI; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        uint64_t bi = 0;
+        if (nbk > 1) {
+            uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
+            while (hi_i - lo_i > 1) {
+                const uint32_t mid = (lo_i + hi_i) >> 1;
+                if (s_rel[mid] <= idx) lo_i = mid;
+                else hi_i = mid;
+            }
+            bi = lo_i;
+        }
+        xw[k] = (WT)((((x.v[k] & mask_h) | (bi << h)) << IB) | idx);
+    }
+    const int nbits = B < DB ? B : DB;
+    const uint32_t nbins = 1u << nbits;
+    const int dshift = IB + B - nbits;
+    const uint32_t nwords = nbins > 1 ? nbins / 2 : 1;
+    if (nbk > 1) __syncthreads();  // s_rel no longer needed
+    // Slots inside the bins.
+    uint32_t slot[MAXI];
+#pragma unroll
+    for (int k = 0; k < MAXI; ++k) {
+        slot[k] = 0;
+        const uint32_t idx = wbase + k * 64 + lane;
+        if ((uint32_t)k < iu && idx < len) {
+            const uint32_t d = (uint32_t)(xw[k] >> dshift) & (nbins - 1);
+            const uint32_t sh = 16 * (d & 1);
+            slot[k] = (atomicAdd(&s_bin[d >> 1], 1u << sh) >> sh) & 0xffffu;
+        }
+    }
+    __syncthreads();
+    // Bin counts -> bin starts (exclusive scan, in place), and the largest bin.
+    {
+        const uint32_t per = (nwords + THREADS - 1) / THREADS;
+        const uint32_t w0 = tid * per, w1 = w0 + per < nwords ? w0 + per : nwords;
+        uint32_t sum = 0, mx = 0;
+        for (uint32_t i = w0; i < w1; ++i) {
+            const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
+            sum += c0 + c1;
+            mx = c0 > mx ? c0 : mx;
+            mx = c1 > mx ? c1 : mx;
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t y = __shfl_xor(mx, o, 64);
+            mx = y > mx ? y : mx;
+        }
+        if (lane == 63) s_part[w] = incl;
+        if (lane == 0) s_max[w] = mx;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (int ww = 0; ww < w; ++ww) run += s_part[ww];
+        for (uint32_t i = w0; i < w1; ++i) {
+            const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
+            s_bin[i] = run | ((run + c0) << 16);
+            run += c0 + c1;
+        }
+    }
+    uint32_t gmax = 0;
+#pragma unroll
+    for (int ww = 0; ww < W; ++ww) gmax = s_max[ww] > gmax ? s_max[ww] : gmax;
+    if (gmax > GMAX) return false;  // a big group of near-equal keys
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXI; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        if ((uint32_t)k < iu && idx < len) {
+            const uint32_t d = (uint32_t)(xw[k] >> dshift) & (nbins - 1);
+            const uint32_t st = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
+            const uint32_t q = st + slot[k];
+            if (q < CAP) s_w[q] = xw[k];
+        }
+    }
+    __syncthreads();
+    // Rank inside the bin (its start plus the smaller words in it) and rebuild the
+    // key; then the values are loaded (coalesced), and with every word ranked the
+    // word buffer holds them by input position, so each is gathered from LDS by the
+    // position its word carries.  All reads of the input happen before the barrier
+    // that precedes the writes, since the output may be the input buffer itself.
+    uint32_t pos[MAXI];  // destination in the low 16 bits, source above
+    K ko[MAXI];
+    const uint64_t hi0 = (uint64_t)key0 & ~mask_h;
+#pragma unroll
+    for (int k = 0; k < MAXI; ++k) {
+        const uint32_t p = wbase + k * 64 + lane;
+        pos[k] = 0xffffffffu;
+        ko[k] = 0;
+        if ((uint32_t)k < iu && p < len) {
+            const WT me = s_w[p];
+            const uint32_t d = (uint32_t)(me >> dshift) & (nbins - 1);
+            const uint32_t gs = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
+            const uint32_t dn = d + 1;
+            const uint32_t ge = dn < nbins ? (s_bin[dn >> 1] >> (16 * (dn & 1))) & 0xffffu : len;
+            uint32_t r = 0;
+            for (uint32_t q = gs; q < ge; ++q) r += s_w[q] < me;
+            const uint32_t at = gs + r < len ? gs + r : len - 1;
+            const uint32_t src = (uint32_t)me & ((1u << IB) - 1u);
+            const uint64_t hi = nbk > 1 ? ((uint64_t)kin[at] & ~mask_h) : hi0;
+            pos[k] = at | (src << 16);
+            ko[k] = (K)((((uint64_t)me >> IB) & mask_h) | hi);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    V vx[MAXI];
+    if (VB) {
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            vx[k] = ((uint32_t)k < iu && idx < len) ? vin[idx] : V(0);
+        }
+    }
+    __syncthreads();  // every word ranked: the word buffer takes the values
+    V* s_v = (V*)s_w;
+    if (VB) {
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+            const uint32_t idx = wbase + k * 64 + lane;
+            if ((uint32_t)k < iu && idx < len) s_v[idx] = vx[k];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < MAXI; ++k) {
+        if (pos[k] != 0xffffffffu) {
+            const uint32_t at = pos[k] & 0xffffu, src = (pos[k] >> 16) < len ? pos[k] >> 16 : 0;
+            kout[at] = ko[k];
+            if (VB) vout[at] = s_v[src];
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
 // ---------------------------------------------------------------------------------
 // Local sort, bucketed form (the common case).
 //
@@ -820,7 +985,7 @@ __device__ __forceinline__ void wave0_offsets(uint32_t* cnt, int w, int lane) {
 #ifndef DFR_LOCAL_MIN_WAVES  // waves per SIMD the bucketed local sort must fit
 #define DFR_LOCAL_MIN_WAVES 6
 #endif
-template <int KB, int VB, int THREADS, int CAP>
+template <int KB, int VB, int THREADS, int CAP, int WORDS>
 __global__ __launch_bounds__(THREADS, DFR_LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
@@ -830,7 +995,6 @@ __global__ __launch_bounds__(THREADS, DFR_LOCAL_MIN_WAVES) void k_local_sort_buc
     constexpr int IB = CAP <= 4096 ? 12 : CAP <= 8192 ? 13 : 16;  // bits of a position
     constexpr int DB = IB - 1;                                     // most bin bits
     constexpr int NWORDS = (1 << DB) / 2;  // two 16-bit bin counters per LDS word
-    constexpr uint32_t GMAX = 64;
     static_assert(CAP % THREADS == 0 && CAP <= (1 << IB), "chunk layout");
     static_assert(CAP < (1 << 16), "a destination and a source share one 32-bit word");
     static_assert(VB <= 8, "values fit the word buffer");
@@ -873,7 +1037,8 @@ __global__ __launch_bounds__(THREADS, DFR_LOCAL_MIN_WAVES) void k_local_sort_buc
         const uint32_t iu = (len + THREADS - 1) / THREADS;
         const uint32_t wbase = (uint32_t)w * iu * 64;
 
-        uint64_t x[MAXI];
+        Words<MAXI> xs;
+        uint64_t* x = xs.v;
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
@@ -902,6 +1067,15 @@ __global__ __launch_bounds__(THREADS, DFR_LOCAL_MIN_WAVES) void k_local_sort_buc
             spill(item);
             continue;
         }
+        if (WORDS == 32 && B + IB > 32) {  // the 64-bit form sorts it
+            if (tid == 0) {
+                const uint32_t m = atomicAdd(a.nwide, 1u);
+                if (m < a.widecap) a.wide[m] = item;
+                else atomicOr(a.err, ERR_LIST_CAP);
+            }
+            __syncthreads();
+            continue;
+        }
         if (B == 0) {  // nothing varies: the chunk is in order already
 #pragma unroll
             for (int k = 0; k < MAXI; ++k) {
@@ -914,152 +1088,15 @@ __global__ __launch_bounds__(THREADS, DFR_LOCAL_MIN_WAVES) void k_local_sort_buc
             __syncthreads();
             continue;
         }
-        const uint64_t mask_h = (1ull << h) - 1ull;  // h < 64 here
         if (nbk > 1) {
             for (uint32_t i = tid; i < nbk; i += THREADS) s_rel[i] = (uint32_t)(a.bstart[ch.f + i] - start);
             __syncthreads();
         }
-#pragma unroll
-        for (int k = 0; k < MAXI; ++k) {
-            const uint32_t idx = wbase + k * 64 + lane;
-            uint64_t bi = 0;
-            if (nbk > 1) {
-                uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
-                while (hi_i - lo_i > 1) {
-                    const uint32_t mid = (lo_i + hi_i) >> 1;
-                    if (s_rel[mid] <= idx) lo_i = mid;
-                    else hi_i = mid;
-                }
-                bi = lo_i;
-            }
-            x[k] = ((((x[k] & mask_h) | (bi << h)) << IB) | idx);
-        }
-        const int nbits = B < DB ? B : DB;
-        const uint32_t nbins = 1u << nbits;
-        const int dshift = IB + B - nbits;
-        const uint32_t nwords = nbins > 1 ? nbins / 2 : 1;
-        if (nbk > 1) __syncthreads();  // s_rel no longer needed
-        // Slots inside the bins.
-        uint32_t slot[MAXI];
-#pragma unroll
-        for (int k = 0; k < MAXI; ++k) {
-            slot[k] = 0;
-            const uint32_t idx = wbase + k * 64 + lane;
-            if ((uint32_t)k < iu && idx < len) {
-                const uint32_t d = (uint32_t)(x[k] >> dshift) & (nbins - 1);
-                const uint32_t sh = 16 * (d & 1);
-                slot[k] = (atomicAdd(&s_bin[d >> 1], 1u << sh) >> sh) & 0xffffu;
-            }
-        }
-        __syncthreads();
-        // Bin counts -> bin starts (exclusive scan, in place), and the largest bin.
-        {
-            const uint32_t per = (nwords + THREADS - 1) / THREADS;
-            const uint32_t w0 = tid * per, w1 = w0 + per < nwords ? w0 + per : nwords;
-            uint32_t sum = 0, mx = 0;
-            for (uint32_t i = w0; i < w1; ++i) {
-                const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
-                sum += c0 + c1;
-                mx = c0 > mx ? c0 : mx;
-                mx = c1 > mx ? c1 : mx;
-            }
-            uint32_t incl = sum;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += y;
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const uint32_t y = __shfl_xor(mx, o, 64);
-                mx = y > mx ? y : mx;
-            }
-            if (lane == 63) s_part[w] = incl;
-            if (lane == 0) s_max[w] = mx;
-            __syncthreads();
-            uint32_t run = incl - sum;
-            for (int ww = 0; ww < w; ++ww) run += s_part[ww];
-            for (uint32_t i = w0; i < w1; ++i) {
-                const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
-                s_bin[i] = run | ((run + c0) << 16);
-                run += c0 + c1;
-            }
-        }
-        uint32_t gmax = 0;
-#pragma unroll
-        for (int ww = 0; ww < W; ++ww) gmax = s_max[ww] > gmax ? s_max[ww] : gmax;
-        if (gmax > GMAX) {  // a big group of near-equal keys: the stable kernel sorts it
-            spill(item);
-            continue;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < MAXI; ++k) {
-            const uint32_t idx = wbase + k * 64 + lane;
-            if ((uint32_t)k < iu && idx < len) {
-                const uint32_t d = (uint32_t)(x[k] >> dshift) & (nbins - 1);
-                const uint32_t st = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
-                const uint32_t q = st + slot[k];
-                if (q < CAP) s_w[q] = x[k];
-            }
-        }
-        __syncthreads();
-        // Rank inside the bin (its start plus the smaller words in it) and rebuild the
-        // key; then the values are loaded (coalesced), and with every word ranked the
-        // word buffer holds them by input position, so each is gathered from LDS by the
-        // position its word carries.  All reads of the input happen before the barrier
-        // that precedes the writes, since the output may be the input buffer itself.
-        uint32_t pos[MAXI];  // destination in the low 16 bits, source above
-        K ko[MAXI];
-        const uint64_t hi0 = (uint64_t)key0 & ~mask_h;
-#pragma unroll
-        for (int k = 0; k < MAXI; ++k) {
-            const uint32_t p = wbase + k * 64 + lane;
-            pos[k] = 0xffffffffu;
-            ko[k] = 0;
-            if ((uint32_t)k < iu && p < len) {
-                const uint64_t me = s_w[p];
-                const uint32_t d = (uint32_t)(me >> dshift) & (nbins - 1);
-                const uint32_t gs = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
-                const uint32_t dn = d + 1;
-                const uint32_t ge = dn < nbins ? (s_bin[dn >> 1] >> (16 * (dn & 1))) & 0xffffu : len;
-                uint32_t r = 0;
-                for (uint32_t q = gs; q < ge; ++q) r += s_w[q] < me;
-                const uint32_t at = gs + r < len ? gs + r : len - 1;
-                const uint32_t src = (uint32_t)me & ((1u << IB) - 1u);
-                const uint64_t hi = nbk > 1 ? ((uint64_t)kin[at] & ~mask_h) : hi0;
-                pos[k] = at | (src << 16);
-                ko[k] = (K)(((me >> IB) & mask_h) | hi);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        V vx[MAXI];
-        if (VB) {
-#pragma unroll
-            for (int k = 0; k < MAXI; ++k) {
-                const uint32_t idx = wbase + k * 64 + lane;
-                vx[k] = ((uint32_t)k < iu && idx < len) ? vin[idx] : V(0);
-            }
-        }
-        __syncthreads();  // every word ranked: the word buffer takes the values
-        V* s_v = (V*)s_w;
-        if (VB) {
-#pragma unroll
-            for (int k = 0; k < MAXI; ++k) {
-                const uint32_t idx = wbase + k * 64 + lane;
-                if ((uint32_t)k < iu && idx < len) s_v[idx] = vx[k];
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int k = 0; k < MAXI; ++k) {
-            if (pos[k] != 0xffffffffu) {
-                const uint32_t at = pos[k] & 0xffffu, src = (pos[k] >> 16) < len ? pos[k] >> 16 : 0;
-                kout[at] = ko[k];
-                if (VB) vout[at] = s_v[src];
-            }
-        }
-        __syncthreads();
+        using WT = typename uint_of<WORDS / 8>::type;
+        const bool ok = bucket_sort_chunk<WT, KB, VB, THREADS, CAP, IB, DB, MAXI>(
+            xs, len, iu, wbase, lane, w, tid, nbk, h, B, key0, kin, vin, kout, vout, s_rel,
+            (WT*)s_w, s_bin, s_part, s_max);
+        if (!ok) spill(item);
     }
 }
 
@@ -1676,10 +1713,20 @@ template <int KB, int VB>
 static void local_kb_vb(const LocalArgs& a, uint32_t blocks, hipStream_t s) {
     constexpr int CAP = KB + VB <= 8 ? LOCAL_CAP_SMALL : LOCAL_CAP_LARGE;
     constexpr int BCAP = KB + VB <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE;
+    // 32-bit words first; chunks whose sort bits and position need more go to the
+    // 64-bit form, and chunks neither can take to the general kernel.
     LocalArgs pa = a;
     pa.spill_only = 0;
-    hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP>), dim3(blocks),
+    hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 32>), dim3(blocks),
                        dim3(LOCAL_THREADS), 0, s, pa);
+    LocalArgs wa = a;
+    wa.spill_only = 0;
+    wa.work = a.wide;
+    wa.nwork = a.nwide;
+    wa.workcap = a.widecap;
+    const uint32_t wblocks = blocks < 4096 ? blocks : 4096;
+    hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 64>), dim3(wblocks),
+                       dim3(LOCAL_THREADS), 0, s, wa);
     LocalArgs ga = a;
     ga.spill_only = 1;
     const uint32_t gblocks = blocks < 2048 ? blocks : 2048;
