@@ -510,7 +510,10 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         la.widecap = (uint32_t)nb;
         la.err = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nb, 8192);
-        HIP_TRY(c, launch_local_sort(j.kb, j.vb, la, blocks, j.s));
+        int max_lo = 0;
+        for (const Seg& g : hs) max_lo = std::max(max_lo, (int)g.lo_bit);
+        HIP_TRY(c, launch_local_sort(j.kb, j.vb, la, blocks,
+                                     local_sort_narrow_first(j.kb, j.vb, max_lo), j.s));
         c->stats.chunks += nb;
     }
     c->stats.used_diversion = 1;
@@ -928,7 +931,11 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         la.widecap = (uint32_t)(nslots + medcap);
         la.err = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 8192);
-        HIP_TRY(c, launch_local_sort(kb, j.vb, la, blocks, j.s));
+        int max_lo = 0;
+        for (uint32_t i : active)
+            if (!full[i]) max_lo = std::max(max_lo, (int)hs[i].lo_bit);
+        HIP_TRY(c, launch_local_sort(kb, j.vb, la, blocks,
+                                     local_sort_narrow_first(kb, j.vb, max_lo), j.s));
     }
     c->stats.used_diversion = 1;
 

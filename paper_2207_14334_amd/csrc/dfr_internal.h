@@ -222,8 +222,11 @@ hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, dou
                              hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
+// Whether chunks whose buckets agree on every bit >= max_lo_bit may fit the 32-bit
+// word form of the local sort (which then runs first).
+bool local_sort_narrow_first(int kb, int vb, int max_lo_bit);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
-                             hipStream_t s);
+                             bool narrow_first, hipStream_t s);
 hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t nchunks,
                               hipStream_t s);
 hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, void* kout,

@@ -1710,21 +1710,25 @@ hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s
 }
 
 template <int KB, int VB>
-static void local_kb_vb(const LocalArgs& a, uint32_t blocks, hipStream_t s) {
+static void local_kb_vb(const LocalArgs& a, uint32_t blocks, bool narrow_first, hipStream_t s) {
     constexpr int CAP = KB + VB <= 8 ? LOCAL_CAP_SMALL : LOCAL_CAP_LARGE;
     constexpr int BCAP = KB + VB <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE;
-    // 32-bit words first; chunks whose sort bits and position need more go to the
-    // 64-bit form, and chunks neither can take to the general kernel.
-    LocalArgs pa = a;
-    pa.spill_only = 0;
-    hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 32>), dim3(blocks),
-                       dim3(LOCAL_THREADS), 0, s, pa);
+    // With narrow_first, 32-bit words first, and chunks whose sort bits and position
+    // need more go to the 64-bit form; otherwise the 64-bit form takes every chunk.
+    // Chunks neither can take go to the general kernel.
     LocalArgs wa = a;
     wa.spill_only = 0;
-    wa.work = a.wide;
-    wa.nwork = a.nwide;
-    wa.workcap = a.widecap;
-    const uint32_t wblocks = blocks < 4096 ? blocks : 4096;
+    uint32_t wblocks = blocks;
+    if (narrow_first) {
+        LocalArgs pa = a;
+        pa.spill_only = 0;
+        hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 32>), dim3(blocks),
+                           dim3(LOCAL_THREADS), 0, s, pa);
+        wa.work = a.wide;
+        wa.nwork = a.nwide;
+        wa.workcap = a.widecap;
+        wblocks = blocks < 4096 ? blocks : 4096;
+    }
     hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 64>), dim3(wblocks),
                        dim3(LOCAL_THREADS), 0, s, wa);
     LocalArgs ga = a;
@@ -1734,16 +1738,24 @@ static void local_kb_vb(const LocalArgs& a, uint32_t blocks, hipStream_t s) {
                        dim3(GENERAL_THREADS), 0, s, ga);
 }
 
-hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks, hipStream_t s) {
+bool local_sort_narrow_first(int kb, int vb, int max_lo_bit) {
+    // A chunk's sort bits are at most its lo_bit varying bits plus a few bits of bucket
+    // index; when even lo_bit and the position exceed 32 bits, no chunk fits 32-bit words.
+    const int ib = (kb + vb <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE) <= 4096 ? 12 : 13;
+    return max_lo_bit + ib <= 32;
+}
+
+hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
+                             bool narrow_first, hipStream_t s) {
     if (blocks == 0) return hipSuccess;
     if (kb == 4) {
-        if (vb == 0) local_kb_vb<4, 0>(a, blocks, s);
-        else if (vb == 4) local_kb_vb<4, 4>(a, blocks, s);
-        else local_kb_vb<4, 8>(a, blocks, s);
+        if (vb == 0) local_kb_vb<4, 0>(a, blocks, narrow_first, s);
+        else if (vb == 4) local_kb_vb<4, 4>(a, blocks, narrow_first, s);
+        else local_kb_vb<4, 8>(a, blocks, narrow_first, s);
     } else {
-        if (vb == 0) local_kb_vb<8, 0>(a, blocks, s);
-        else if (vb == 4) local_kb_vb<8, 4>(a, blocks, s);
-        else local_kb_vb<8, 8>(a, blocks, s);
+        if (vb == 0) local_kb_vb<8, 0>(a, blocks, narrow_first, s);
+        else if (vb == 4) local_kb_vb<8, 4>(a, blocks, narrow_first, s);
+        else local_kb_vb<8, 8>(a, blocks, narrow_first, s);
     }
     return hipGetLastError();
 }
