@@ -17,6 +17,8 @@ of the paper it follows, is stated in ``oracle.c``:
 * ``bucket_starts`` -- where the leading-digit prefix changes (Sec. 2.2 buckets).
 * ``check_index_payload`` -- the four properties that single out the stable sort
   when the payload is the input index.
+* ``stable_sort_typed`` -- the stable sort of signed-integer or floating-point keys
+  (two's-complement value; IEEE 754 totalOrder), beyond the paper's unsigned keys.
 """
 from __future__ import annotations
 
@@ -69,6 +71,7 @@ class Oracle:
         lib.oracle_dfr_sort.argtypes = [P, P, Z, I, I, I, Z, P, P]
         lib.oracle_check_index_payload.argtypes = [P, Z, I, P, P, I, ctypes.POINTER(I)]
         lib.oracle_check_index_payload.restype = ctypes.c_int64
+        lib.oracle_stable_sort_typed.argtypes = [P, P, Z, I, I, P, P]
         self.lib = lib
 
     # -- helpers ---------------------------------------------------------------
@@ -101,6 +104,27 @@ class Oracle:
         ov = np.empty_like(vals) if vals is not None else None
         self._rc(self.lib.oracle_stable_sort(self._p(keys), self._p(vals), keys.size, kb, vb,
                                              self._p(ok), self._p(ov)))
+        return ok, ov
+
+    # Key types of stable_sort_typed, by numpy dtype of the keys.
+    KEY_TYPES = {np.dtype(np.uint32): 0, np.dtype(np.uint64): 1, np.dtype(np.int32): 2,
+                 np.dtype(np.int64): 3, np.dtype(np.float32): 4, np.dtype(np.float64): 5}
+
+    def stable_sort_typed(self, keys, vals=None):
+        """Stable sort of uint/int/float keys (their raw encodings are sorted under the
+        type's order and returned unchanged)."""
+        keys = np.ascontiguousarray(keys)
+        kt = self.KEY_TYPES[keys.dtype]
+        vb = 0
+        if vals is not None:
+            vals = np.ascontiguousarray(vals)
+            if vals.dtype not in _KB or vals.shape != keys.shape:
+                raise TypeError("vals must be uint32/uint64 and match keys")
+            vb = _KB[vals.dtype]
+        ok = np.empty_like(keys)
+        ov = np.empty_like(vals) if vals is not None else None
+        self._rc(self.lib.oracle_stable_sort_typed(self._p(keys), self._p(vals), keys.size, kt, vb,
+                                                   self._p(ok), self._p(ov)))
         return ok, ov
 
     def segmented_sort(self, keys, vals, offsets):

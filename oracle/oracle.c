@@ -111,6 +111,98 @@ int oracle_stable_sort(const void* keys, const void* vals, size_t n, int kb, int
     return OR_OK;
 }
 
+/* ------------------------------------------------------------------------------ */
+/* Signed and floating-point keys (beyond the paper, which sorts unsigned integers). */
+/* The order is written out from its definition, comparing the decoded values:     */
+/* two's-complement integers by value; binary floats by IEEE 754 totalOrder:       */
+/* negative before positive (by the sign bit, so -0 < +0 and -NaN < +NaN), and      */
+/* within one sign by magnitude (the exponent-and-fraction field read as an        */
+/* unsigned integer, which orders zero < subnormals < normals < infinity < NaNs by  */
+/* payload), the larger magnitude first for negatives.                             */
+/* ------------------------------------------------------------------------------ */
+
+#define ORACLE_KEY_U32 0
+#define ORACLE_KEY_U64 1
+#define ORACLE_KEY_I32 2
+#define ORACLE_KEY_I64 3
+#define ORACLE_KEY_F32 4
+#define ORACLE_KEY_F64 5
+
+static int ties(const keyed_index* x, const keyed_index* y) {
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+static int cmp_i32(const void* a, const void* b) {
+    const keyed_index *x = (const keyed_index*)a, *y = (const keyed_index*)b;
+    const int32_t u = (int32_t)(uint32_t)x->key, v = (int32_t)(uint32_t)y->key;
+    if (u != v) return u < v ? -1 : 1;
+    return ties(x, y);
+}
+
+static int cmp_i64(const void* a, const void* b) {
+    const keyed_index *x = (const keyed_index*)a, *y = (const keyed_index*)b;
+    const int64_t u = (int64_t)x->key, v = (int64_t)y->key;
+    if (u != v) return u < v ? -1 : 1;
+    return ties(x, y);
+}
+
+/* totalOrder of two encodings of `bits` bits: sign, then magnitude. */
+static int total_order(uint64_t x, uint64_t y, int bits) {
+    const uint64_t sign = 1ull << (bits - 1), mag = sign - 1;
+    const int xn = (x & sign) != 0, yn = (y & sign) != 0;
+    if (xn != yn) return xn ? -1 : 1;
+    const uint64_t mx = x & mag, my = y & mag;
+    if (mx == my) return 0;
+#ifdef ORACLE_PLANT_FLOAT_NO_REVERSE
+    /* Planted mistake for the pin tests: negatives ordered by increasing magnitude. */
+    return mx < my ? -1 : 1;
+#else
+    if (xn) return mx > my ? -1 : 1;  /* both negative: larger magnitude is smaller */
+    return mx < my ? -1 : 1;
+#endif
+}
+
+static int cmp_f32(const void* a, const void* b) {
+    const keyed_index *x = (const keyed_index*)a, *y = (const keyed_index*)b;
+    const int c = total_order(x->key, y->key, 32);
+    return c ? c : ties(x, y);
+}
+
+static int cmp_f64(const void* a, const void* b) {
+    const keyed_index *x = (const keyed_index*)a, *y = (const keyed_index*)b;
+    const int c = total_order(x->key, y->key, 64);
+    return c ? c : ties(x, y);
+}
+
+/* Stable sort under the order of key_type (ORACLE_KEY_*); keys hold the raw encodings
+ * (4 bytes for the 32-bit types, 8 for the 64-bit ones). */
+int oracle_stable_sort_typed(const void* keys, const void* vals, size_t n, int key_type, int vb,
+                             void* out_keys, void* out_vals) {
+    if (key_type < ORACLE_KEY_U32 || key_type > ORACLE_KEY_F64) return OR_EARG;
+    const int kb = (key_type % 2 == 0) ? 4 : 8;
+    if (!widths_ok(kb, vb)) return OR_EARG;
+    if (key_type <= ORACLE_KEY_U64) return oracle_stable_sort(keys, vals, n, kb, vb, out_keys, out_vals);
+    if (n == 0) return OR_OK;
+    if (!keys || !out_keys || (vb && (!vals || !out_vals))) return OR_EARG;
+    keyed_index* r = (keyed_index*)malloc(n * sizeof(keyed_index));
+    if (!r) return OR_ENOMEM;
+    for (size_t i = 0; i < n; ++i) {
+        r[i].key = ld(keys, kb, i);
+        r[i].idx = i;
+    }
+    int (*cmp)(const void*, const void*) = key_type == ORACLE_KEY_I32   ? cmp_i32
+                                           : key_type == ORACLE_KEY_I64 ? cmp_i64
+                                           : key_type == ORACLE_KEY_F32 ? cmp_f32
+                                                                        : cmp_f64;
+    qsort(r, n, sizeof(keyed_index), cmp);
+    for (size_t i = 0; i < n; ++i) {
+        st(out_keys, kb, i, r[i].key);
+        if (vb) st(out_vals, vb, i, ld(vals, vb, r[i].idx));
+    }
+    free(r);
+    return OR_OK;
+}
+
 /* Segmented form: every segment [off[s], off[s+1]) is sorted on its own.
  * off has S+1 entries, off[0] == 0, non-decreasing, off[S] == n. */
 int oracle_segmented_sort(const void* keys, const void* vals, size_t n, int kb, int vb,

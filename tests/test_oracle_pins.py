@@ -167,8 +167,62 @@ def pin_rank_formula(o):
         assert o.rank_of(k, i) == inv[i]
 
 
+def load_typed_golden():
+    d = {}
+    for line in open(os.path.join(GOLDEN, "typed_keys_total_order.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split(":", 1)
+        d[k.strip()] = v.split()
+    return d
+
+
+def pin_typed_golden(o):
+    """Hand-worked orders of float (IEEE totalOrder) and signed keys."""
+    g = load_typed_golden()
+    for name, dt, raw in (("f32_keys", np.float32, np.uint32), ("f64_keys", np.float64, np.uint64)):
+        bits = np.array([int(x, 16) for x in g[name]], dtype=raw)
+        keys = bits.view(dt)
+        vals = np.arange(keys.size, dtype=np.uint32)
+        ok, ov = o.stable_sort_typed(keys, vals)
+        assert list(ov) == [int(x) for x in g["float_sorted_vals"]], name
+        assert np.array_equal(ok.view(raw), bits[ov]), name  # encodings come back unchanged
+    for name, dt in (("i32_keys", np.int32), ("i64_keys", np.int64)):
+        keys = np.array([int(x) for x in g[name]], dtype=dt)
+        vals = np.arange(keys.size, dtype=np.uint64)
+        ok, ov = o.stable_sort_typed(keys, vals)
+        assert list(ov) == [int(x) for x in g["int_sorted_vals"]], name
+        assert np.array_equal(ok, keys[ov.astype(np.int64)]), name
+
+
+def pin_typed_numpy(o):
+    """Signed keys, and finite nonzero floats (where totalOrder is the numeric order),
+    against numpy's stable argsort."""
+    rng = np.random.default_rng(11)
+    for dt in (np.int32, np.int64):
+        info = np.iinfo(dt)
+        k = rng.integers(info.min, info.max, size=5000, dtype=dt, endpoint=True)
+        k[:4] = [info.min, info.max, -1, 0]
+        k[4:400] = k[4:400] % 7  # repeats
+        ok, ov = o.stable_sort_typed(k, np.arange(k.size, dtype=np.uint32))
+        ref = np.argsort(k, kind="stable")
+        assert np.array_equal(ov, ref.astype(np.uint32)) and np.array_equal(ok, k[ref]), dt
+    for dt in (np.float32, np.float64):
+        k = (rng.standard_normal(5000) * rng.choice([1e-30, 1.0, 1e30], 5000)).astype(dt)
+        k[k == 0] = 1
+        k[:300] = np.round(k[:300])  # repeats
+        k[k == 0] = 2
+        ok, ov = o.stable_sort_typed(k, np.arange(k.size, dtype=np.uint32))
+        ref = np.argsort(k, kind="stable")
+        assert np.array_equal(ov, ref.astype(np.uint32)), dt
+    # Unsigned keys through the typed entry give the plain definition.
+    k = rng.integers(0, 1 << 32, size=3000, dtype=np.uint32)
+    assert np.array_equal(o.stable_sort_typed(k)[0], o.stable_sort(k)[0])
+
+
 ALL_PINS = [pin_bruteforce_small_alphabet, pin_bruteforce_extremes, pin_numpy,
-            pin_special_cases, pin_golden, pin_properties, pin_rank_formula]
+            pin_special_cases, pin_golden, pin_properties, pin_rank_formula,
+            pin_typed_golden, pin_typed_numpy]
 
 
 # --------------------------------------------------------------------------------------
@@ -271,7 +325,8 @@ def test_checker_catches_each_broken_property(o):
 # --------------------------------------------------------------------------------------
 
 MUTANTS = ["ORACLE_PLANT_REVERSED_TIES", "ORACLE_PLANT_SIGNED_COMPARE",
-           "ORACLE_PLANT_DROP_LAST", "ORACLE_PLANT_INCLUSIVE_SCAN"]
+           "ORACLE_PLANT_DROP_LAST", "ORACLE_PLANT_INCLUSIVE_SCAN",
+           "ORACLE_PLANT_FLOAT_NO_REVERSE"]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS)
