@@ -109,6 +109,33 @@ dfr_status dfr_sort_segmented_u64(dfr_ctx* ctx, uint64_t* keys, uint64_t* vals,
                                   void* temp, size_t temp_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------
+ * Signed and floating-point keys.  The paper sorts unsigned integer keys; these
+ * entry points map the keys in place to unsigned integers of the same order, sort
+ * those, and map them back, so the caller's keys end sorted in their own encoding:
+ *   DFR_KEY_I32/I64  two's-complement value order (sign bit flipped for the sort);
+ *   DFR_KEY_F32/F64  IEEE 754 totalOrder: -NaN < -inf < ... < -0 < +0 < ... < +inf
+ *                    < +NaN, NaNs by payload (negative encodings fully inverted,
+ *                    positive ones with the sign bit flipped, for the sort).
+ * DFR_KEY_U32/U64 sort as dfr_sort_u32/u64.  val_bytes is 0 (vals NULL), 4 or 8,
+ * independent of the key width.  Arguments, errors and temp as for the plain and
+ * segmented sorts; after an error past argument checking the keys are still mapped
+ * back.  Two extra passes over the keys (read and write) per call.
+ * ------------------------------------------------------------------------------- */
+#define DFR_KEY_U32 0
+#define DFR_KEY_U64 1
+#define DFR_KEY_I32 2
+#define DFR_KEY_I64 3
+#define DFR_KEY_F32 4
+#define DFR_KEY_F64 5
+
+dfr_status dfr_sort_keys(dfr_ctx* ctx, int32_t key_type, void* keys, void* vals, int val_bytes,
+                         size_t n, void* temp, size_t temp_bytes, void* stream);
+dfr_status dfr_sort_segmented_keys(dfr_ctx* ctx, int32_t key_type, void* keys, void* vals,
+                                   int val_bytes, const uint64_t* seg_offsets,
+                                   size_t num_segments, void* temp, size_t temp_bytes,
+                                   void* stream);
+
+/* ---------------------------------------------------------------------------------
  * Stages, in the paper's vocabulary (Sec. 2): a count and a deal on one digit.
  * ------------------------------------------------------------------------------- */
 

@@ -36,7 +36,11 @@ EXPORTED = [
     "dfr_count", "dfr_deal", "dfr_submit", "dfr_poll", "dfr_set_option", "dfr_get_stats",
     "dfr_plan_top_digits", "dfr_local_sort_capacity", "dfr_deal_tile_records",
     "dfr_size_class", "dfr_autotune", "dfr_get_tune", "dfr_set_tune", "dfr_get_serve_stats",
+    "dfr_sort_keys", "dfr_sort_segmented_keys",
 ]
+
+# Key types of dfr_sort_keys.
+KEY_U32, KEY_U64, KEY_I32, KEY_I64, KEY_F32, KEY_F64 = range(6)
 
 TUNE_CLASSES = 32
 
@@ -152,6 +156,10 @@ def lib():
     L.dfr_set_tune.restype = S
     L.dfr_get_serve_stats.argtypes = [P, ctypes.POINTER(ServeStats)]
     L.dfr_get_serve_stats.restype = S
+    L.dfr_sort_keys.argtypes = [P, S, P, P, I, Z, P, Z, P]
+    L.dfr_sort_keys.restype = S
+    L.dfr_sort_segmented_keys.argtypes = [P, S, P, P, I, P, Z, P, Z, P]
+    L.dfr_sort_segmented_keys.restype = S
     _lib = L
     return L
 
@@ -197,11 +205,29 @@ def plan_top_digits(hist, n: int, key_bytes: int, val_bytes: int, divert: int = 
 
 def _width(t) -> int:
     import torch
-    if t.dtype in (torch.uint32, torch.int32):
+    if t.dtype in (torch.uint32, torch.int32, torch.float32):
         return 4
-    if t.dtype in (torch.uint64, torch.int64):
+    if t.dtype in (torch.uint64, torch.int64, torch.float64):
         return 8
     raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _key_type(t) -> int:
+    import torch
+    kinds = {torch.uint32: KEY_U32, torch.uint64: KEY_U64, torch.int32: KEY_I32,
+             torch.int64: KEY_I64, torch.float32: KEY_F32, torch.float64: KEY_F64}
+    if t.dtype not in kinds:
+        raise TypeError(f"unsupported key dtype {t.dtype}")
+    return kinds[t.dtype]
+
+
+def _val_width(t) -> int:
+    import torch
+    if t.dtype in (torch.uint32, torch.int32, torch.float32):
+        return 4
+    if t.dtype in (torch.uint64, torch.int64, torch.float64):
+        return 8
+    raise TypeError(f"unsupported value dtype {t.dtype}")
 
 
 def _check_tensor(t, name):
@@ -267,19 +293,28 @@ class Context:
 
     # -- sorts ---------------------------------------------------------------------
     def sort_(self, keys, vals=None, temp=None, stream=None):
-        """Stable in-place ascending sort of ``keys`` (uint32/uint64); ``vals`` follows."""
+        """Stable in-place ascending sort of ``keys``; ``vals`` follows.  uint32/uint64
+        keys sort as unsigned integers (values of the same width), int32/int64 by value,
+        float32/float64 by IEEE totalOrder (values 4 or 8 bytes wide, any dtype)."""
         _check_tensor(keys, "keys")
-        kb = _width(keys)
+        kt = _key_type(keys)
         n = keys.numel()
-        vp = None
+        vp, vb = None, 0
         if vals is not None:
             _check_tensor(vals, "vals")
-            if vals.numel() != n or _width(vals) != kb:
-                raise ValueError("vals must match keys in length and width")
+            vb = _val_width(vals)
+            if vals.numel() != n:
+                raise ValueError("vals must match keys in length")
             vp = vals.data_ptr()
         tp, tb = (temp.data_ptr(), temp.numel() * temp.element_size()) if temp is not None else (None, 0)
-        f = lib().dfr_sort_u32 if kb == 4 else lib().dfr_sort_u64
-        self._raise(f(self._h, keys.data_ptr(), vp, n, tp, tb, self._stream(stream)), "sort")
+        if kt in (KEY_U32, KEY_U64):
+            if vals is not None and vb != _width(keys):
+                raise ValueError("vals of unsigned keys must match the key width")
+            f = lib().dfr_sort_u32 if kt == KEY_U32 else lib().dfr_sort_u64
+            self._raise(f(self._h, keys.data_ptr(), vp, n, tp, tb, self._stream(stream)), "sort")
+        else:
+            self._raise(lib().dfr_sort_keys(self._h, kt, keys.data_ptr(), vp, vb, n, tp, tb,
+                                            self._stream(stream)), "sort")
         return keys, vals
 
     def sort_segmented_(self, keys, vals, offsets, temp=None, stream=None):
@@ -287,16 +322,21 @@ class Context:
         ``offsets`` is a host sequence of num_segments + 1 integers."""
         import numpy as np
         _check_tensor(keys, "keys")
-        kb = _width(keys)
+        kt = _key_type(keys)
         off = np.ascontiguousarray(offsets, dtype=np.uint64)
-        vp = None
+        vp, vb = None, 0
         if vals is not None:
             _check_tensor(vals, "vals")
-            vp = vals.data_ptr()
+            vp, vb = vals.data_ptr(), _val_width(vals)
         tp, tb = (temp.data_ptr(), temp.numel() * temp.element_size()) if temp is not None else (None, 0)
-        f = lib().dfr_sort_segmented_u32 if kb == 4 else lib().dfr_sort_segmented_u64
-        self._raise(f(self._h, keys.data_ptr(), vp, off.ctypes.data, off.size - 1, tp, tb,
-                      self._stream(stream)), "sort_segmented")
+        if kt in (KEY_U32, KEY_U64) and (vals is None or vb == _width(keys)):
+            f = lib().dfr_sort_segmented_u32 if kt == KEY_U32 else lib().dfr_sort_segmented_u64
+            self._raise(f(self._h, keys.data_ptr(), vp, off.ctypes.data, off.size - 1, tp, tb,
+                          self._stream(stream)), "sort_segmented")
+        else:
+            self._raise(lib().dfr_sort_segmented_keys(self._h, kt, keys.data_ptr(), vp, vb,
+                                                      off.ctypes.data, off.size - 1, tp, tb,
+                                                      self._stream(stream)), "sort_segmented")
         return keys, vals
 
     # -- tuning --------------------------------------------------------------------

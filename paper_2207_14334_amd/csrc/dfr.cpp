@@ -1107,8 +1107,26 @@ dfr_status set_device(dfr_ctx* c) {
     return DFR_OK;
 }
 
+// run_sort between the in-place map of signed or float keys to unsigned ones and its
+// inverse (mode 0: unsigned keys, no map).
+dfr_status run_sort_mapped(dfr_ctx* c, int kb, int vb, int mode, void* keys, void* vals, size_t n,
+                           const std::vector<LSeg>& segs, void* temp, hipStream_t s) {
+    if (mode) {
+        Timed tm(c, s, ST_OTHER);
+        HIP_TRY(c, launch_key_transform(kb, mode, false, keys, n, s));
+    }
+    dfr_status st = run_sort(c, kb, vb, keys, vals, segs, temp, s);
+    if (mode) {
+        // Mapped back even after a failed sort, so the keys stay valid encodings.
+        Timed tm(c, s, ST_OTHER);
+        const hipError_t e = launch_key_transform(kb, mode, true, keys, n, s);
+        if (!st && e != hipSuccess) return fail_hip(c, e, "key map");
+    }
+    return st;
+}
+
 dfr_status sort_plain(dfr_ctx* c, int kb, int vb, void* keys, void* vals, size_t n, void* temp,
-                      size_t temp_bytes, void* stream) {
+                      size_t temp_bytes, void* stream, int mode = 0) {
     dfr_status st = validate(c, keys, vals, n, kb, vb, temp, temp_bytes);
     if (st) return st;
     if (n > DFR_MAX_SEGMENT_RECORDS) return DFR_E_TOO_LARGE;
@@ -1122,7 +1140,7 @@ dfr_status sort_plain(dfr_ctx* c, int kb, int vb, void* keys, void* vals, size_t
     st = get_temp(c, n, kb, vb, &temp, s);
     if (st) return st;
     std::vector<LSeg> segs{LSeg{0, n, 8 * kb}};
-    return run_sort(c, kb, vb, keys, vb ? vals : nullptr, segs, temp, s);
+    return run_sort_mapped(c, kb, vb, mode, keys, vb ? vals : nullptr, n, segs, temp, s);
 }
 
 // Segments from host offsets (S + 1 entries, [0] = 0, non-decreasing).
@@ -1142,7 +1160,7 @@ dfr_status parse_segments(const uint64_t* off, size_t S, int kb, std::vector<LSe
 }
 
 dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const uint64_t* off,
-                          size_t S, void* temp, size_t temp_bytes, void* stream) {
+                          size_t S, void* temp, size_t temp_bytes, void* stream, int mode = 0) {
     if (!c) return DFR_E_INVALID_ARG;
     std::vector<LSeg> segs;
     if (!off) return DFR_E_INVALID_ARG;
@@ -1160,7 +1178,16 @@ dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, co
     hipStream_t s = (hipStream_t)stream;
     st = get_temp(c, n, kb, vb, &temp, s);
     if (st) return st;
-    return run_sort(c, kb, vb, keys, vb ? vals : nullptr, segs, temp, s);
+    return run_sort_mapped(c, kb, vb, mode, keys, vb ? vals : nullptr, n, segs, temp, s);
+}
+
+// Key bytes and map mode (0 unsigned, 1 signed, 2 float) of a DFR_KEY_* code; false if
+// the code is unknown.
+bool key_type_info(int32_t key_type, int* kb, int* mode) {
+    if (key_type < DFR_KEY_U32 || key_type > DFR_KEY_F64) return false;
+    *kb = key_type % 2 == 0 ? 4 : 8;
+    *mode = key_type / 2;
+    return true;
 }
 
 // One timed sort of fresh copies of the caller's data under tuning t.
@@ -1769,6 +1796,26 @@ dfr_status dfr_sort_u32(dfr_ctx* c, uint32_t* keys, uint32_t* vals, size_t n, vo
 dfr_status dfr_sort_u64(dfr_ctx* c, uint64_t* keys, uint64_t* vals, size_t n, void* temp,
                         size_t temp_bytes, void* stream) {
     return sort_plain(c, 8, vals ? 8 : 0, keys, vals, n, temp, temp_bytes, stream);
+}
+
+dfr_status dfr_sort_keys(dfr_ctx* c, int32_t key_type, void* keys, void* vals, int val_bytes,
+                         size_t n, void* temp, size_t temp_bytes, void* stream) {
+    int kb = 0, mode = 0;
+    if (!key_type_info(key_type, &kb, &mode)) return DFR_E_INVALID_ARG;
+    if (!(val_bytes == 0 || val_bytes == 4 || val_bytes == 8)) return DFR_E_INVALID_ARG;
+    if ((val_bytes == 0) != (vals == nullptr)) return DFR_E_INVALID_ARG;
+    return sort_plain(c, kb, val_bytes, keys, vals, n, temp, temp_bytes, stream, mode);
+}
+
+dfr_status dfr_sort_segmented_keys(dfr_ctx* c, int32_t key_type, void* keys, void* vals,
+                                   int val_bytes, const uint64_t* seg_offsets, size_t num_segments,
+                                   void* temp, size_t temp_bytes, void* stream) {
+    int kb = 0, mode = 0;
+    if (!key_type_info(key_type, &kb, &mode)) return DFR_E_INVALID_ARG;
+    if (!(val_bytes == 0 || val_bytes == 4 || val_bytes == 8)) return DFR_E_INVALID_ARG;
+    if ((val_bytes == 0) != (vals == nullptr)) return DFR_E_INVALID_ARG;
+    return sort_segmented(c, kb, val_bytes, keys, vals, seg_offsets, num_segments, temp,
+                          temp_bytes, stream, mode);
 }
 
 dfr_status dfr_sort_segmented_u32(dfr_ctx* c, uint32_t* keys, uint32_t* vals,

@@ -220,6 +220,10 @@ hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s);
 // coll[s * ndig + j] = sum_v h[v]^2 / (sum_v h[v])^2 for each segment's digit-j histogram.
 hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, double* coll,
                              hipStream_t s);
+// In-place map of signed (mode 1) or floating-point (mode 2) keys to unsigned keys of
+// the same order, or back (inverse).  Mode 0 does nothing.
+hipError_t launch_key_transform(int kb, int mode, bool inverse, void* keys, size_t n,
+                                hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 // Whether chunks whose buckets agree on every bit >= max_lo_bit may fit the 32-bit

@@ -1389,6 +1389,36 @@ __global__ __launch_bounds__(THREADS) void k_copy_chunks(const CopyChunk* chunks
     }
 }
 
+// Order-preserving maps from signed and floating-point encodings to unsigned integers
+// (the paper sorts unsigned keys only).  Signed: flip the sign bit, so that negative
+// values come first in two's-complement order.  Float: flip every bit of a negative
+// value (larger magnitude first) and the sign bit of a positive one, which orders the
+// encodings by IEEE 754 totalOrder.  `inverse` maps back.
+template <int KB>
+__global__ __launch_bounds__(256) void k_key_transform(void* keys, uint64_t n, int mode, int inverse) {
+    using K = typename uint_of<KB>::type;
+    constexpr K SIGN = K(1) << (8 * KB - 1);
+    K* k = (K*)keys;
+    const uint64_t stride = (uint64_t)gridDim.x * 256 * 4;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * 256 * 4 + threadIdx.x; i0 < n; i0 += stride) {
+        K x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = i0 + u * 256 < n ? k[i0 + u * 256] : K(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (mode == 1) {
+                x[u] ^= SIGN;
+            } else {
+                const bool top = (x[u] & SIGN) != 0;
+                x[u] ^= (top != (inverse != 0)) ? ~K(0) : SIGN;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * 256 < n) k[i0 + u * 256] = x[u];
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Tile shapes and launchers.
 // ---------------------------------------------------------------------------------
@@ -1681,6 +1711,15 @@ hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t 
         else if (vb == 4) copy_chunks_kb_vb<8, 4>(chunks, nchunks, s);
         else copy_chunks_kb_vb<8, 8>(chunks, nchunks, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_key_transform(int kb, int mode, bool inverse, void* keys, size_t n,
+                                hipStream_t s) {
+    if (n == 0 || mode == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<size_t>((n + 1023) / 1024, 8192);
+    if (kb == 4) hipLaunchKernelGGL(k_key_transform<4>, dim3(blocks), dim3(256), 0, s, keys, (uint64_t)n, mode, inverse ? 1 : 0);
+    else hipLaunchKernelGGL(k_key_transform<8>, dim3(blocks), dim3(256), 0, s, keys, (uint64_t)n, mode, inverse ? 1 : 0);
     return hipGetLastError();
 }
 
