@@ -391,6 +391,9 @@ def main():
     ap.add_argument("--arrays", type=int, default=20000)
     ap.add_argument("--max-len", type=int, default=1 << 20)
     ap.add_argument("--plain-runs", type=int, default=2)
+    ap.add_argument("--key-type", default="u32", choices=("u32", "u64", "i32", "i64", "f32", "f64"))
+    ap.add_argument("--set", action="append", default=[], metavar="OPTION=VALUE",
+                    help="a library option (dfr_set_option) for the plain workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -414,9 +417,15 @@ def run_plain(args):
 
     torch.cuda.set_device(0)
     n = 1 << args.log2n
-    log(f"generating {n} {args.dist} keys")
-    keys_h = workloads.make_keys(args.dist, n, 32, 0)
-    vals_h = workloads.index_payload(n)
+    kt = args.key_type
+    kbits = 32 if kt.endswith("32") else 64
+    kb = vb = kbits // 8
+    log(f"generating {n} {args.dist} {kt} keys")
+    # Signed and float keys are the same seeded bit patterns viewed as that type.
+    bits_h = workloads.make_keys(args.dist, n, kbits, 0)
+    keys_h = bits_h.view({"u32": np.uint32, "u64": np.uint64, "i32": np.int32, "i64": np.int64,
+                          "f32": np.float32, "f64": np.float64}[kt])
+    vals_h = workloads.index_payload(n, kbits)
     base_k = torch.from_numpy(keys_h).cuda()
     base_v = torch.from_numpy(vals_h).cuda()
     copies = args.warmup + args.steps
@@ -425,8 +434,11 @@ def run_plain(args):
     for i in range(copies):
         ks[i].copy_(base_k)
         vs[i].copy_(base_v)
-    temp = torch.empty(dfr.temp_bytes(n, 4, 4), dtype=torch.uint8, device="cuda")
+    temp = torch.empty(dfr.temp_bytes(n, kb, vb), dtype=torch.uint8, device="cuda")
     ctx = dfr.Context(0)
+    for opt in args.set:
+        name, value = opt.split("=", 1)
+        ctx.set_option(name, int(value))
     torch.cuda.synchronize()
     log(f"{copies} resident copies ready")
 
@@ -465,32 +477,48 @@ def run_plain(args):
     gkeys = n * args.steps / elapsed / 1e9
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {gkeys:.2f} Gkeys/s")
 
-    parity = check_result(keys_h, ks[-1].cpu().numpy(), vs[-1].cpu().numpy())
+    # The check compares the keys as unsigned integers of the same order: the encodings
+    # themselves for unsigned keys, the sign bit flipped for signed ones, and for floats
+    # every bit of a negative encoding or the sign bit of a positive one (totalOrder).
+    def as_ordered(a):
+        raw = a.view(np.uint32 if kbits == 32 else np.uint64)
+        sign = raw.dtype.type(1 << (kbits - 1))
+        if kt[0] == "i":
+            return raw ^ sign
+        if kt[0] == "f":
+            neg = (raw & sign) != 0
+            return np.where(neg, ~raw, raw ^ sign)
+        return raw
+
+    parity = check_result(as_ordered(keys_h), as_ordered(ks[-1].cpu().numpy()), vs[-1].cpu().numpy())
     log(f"result check: {parity}")
 
-    rec_bytes = 4 + 4
+    rec_bytes = kb + vb
     deal_bytes = 2 * rec_bytes * n  # read + write of key and payload, one pass
     deal_ms = agg["ms_deal"] / max(agg["deal_launches_timed"], 1)
     deal_gbs = deal_bytes / (deal_ms * 1e-3) / 1e9
-    traffic = counter_traffic()
+    headline = kt == "u32" and args.log2n == 28 and args.dist == "uniform" and not args.set
+    traffic = counter_traffic() if headline else None
     # Algorithmic bytes of the whole sort: count (kb/key), d deals (2(kb+vb)/key),
     # bucket heads (kb/key), local sort (2(kb+vb)/key).
     d = plan["top_digits"] if plan else 0
-    sort_bytes = n * (4 + d * 2 * rec_bytes + (4 + 2 * rec_bytes if plan and plan["used_diversion"] else 0))
+    sort_bytes = n * (kb + d * 2 * rec_bytes + (kb + 2 * rec_bytes if plan and plan["used_diversion"] else 0))
     hbm_frac_sort = sort_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.dist)
+    cpu = None if args.no_cpu_baseline or kt != "u32" else cpu_baseline(args.dist)
 
     out = {
         "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": kt,
         "data": "synthetic",
-        "config": {"workload": f"plain DFR sort of 2^{args.log2n} uint32 keys, i.i.d. "
-                               f"{args.dist}, uint32 index payload, seed 0",
-                   "n": n, "key_bits": 32, "payload_bits": 32, "distribution": args.dist,
+        "config": {"workload": f"plain DFR sort of 2^{args.log2n} {kt} keys, i.i.d. "
+                               f"{args.dist} bit patterns, uint{kbits} index payload, seed 0",
+                   "n": n, "key_type": kt, "key_bits": kbits, "payload_bits": kbits,
+                   "distribution": args.dist, "options": args.set,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_deal<4,4,512,16>",
+        "roofline": {"bound": "hbm",
+                     "kernel": f"k_deal<{kb},{vb},512,{dfr.deal_tile_records(kb, vb) // 512}>",
                      "achieved": round(deal_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(deal_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": deal_bytes,

@@ -55,6 +55,11 @@ enum Stage { ST_COUNT = 0, ST_DEAL, ST_BUCKETS, ST_LOCAL, ST_OTHER, ST_N };
 
 // Largest segment, in tiles, whose bucket bases one block scans ahead of the deal.
 constexpr uint64_t kSegScanTiles = 1024;
+// Most segments of a level whose tiles are scanned segment by segment with the
+// one-segment scan when some segment is longer than kSegScanTiles.
+constexpr size_t kPerSegScanMax = 16;
+// Top digits with at most this many non-empty bins count as a skewed prefix.
+constexpr uint32_t kFewTopValues = 16;
 
 }  // namespace
 
@@ -549,16 +554,20 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     for (const LSeg& g : segs) max_seg_tiles = std::max<uint64_t>(max_seg_tiles, (g.len + j.tile - 1) / j.tile);
     const bool single = S == 1 && !c->force_lookback;
     const bool segscan = S > 1 && max_seg_tiles <= kSegScanTiles && !c->force_lookback;
-    const bool nolb = single || segscan;
+    const bool perseg = S > 1 && !segscan && S <= kPerSegScanMax && !c->force_lookback;
+    const bool nolb = single || segscan || perseg;
     const size_t tcnt_n = nolb ? tiles.size() * ndig * RADIX : 0;
     dfr_status st = arena_reserve(c, asize<uint32_t>(hist_n) + 2 * asize<uint64_t>(S) +
-                                         asize<double>(S * ndig) + asize<uint32_t>(tcnt_n) +
+                                         asize<double>(S * ndig) + asize<uint32_t>(S * ndig) +
+                                         asize<uint32_t>(tcnt_n) +
                                          asize<Tile>(tiles.size()), j.s);
     if (st) return st;
     const size_t off_hist = c->arena_used;
     aalloc<uint32_t>(c, hist_n);
     const size_t off_coll = c->arena_used;
     aalloc<double>(c, S * ndig);
+    const size_t off_nz = c->arena_used;
+    aalloc<uint32_t>(c, S * ndig);
     const size_t off_or = c->arena_used;
     aalloc<uint64_t>(c, S);
     const size_t off_and = c->arena_used;
@@ -598,19 +607,22 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // Each segment's digit collision probabilities, then read them back with OR/AND.
     // The OR/AND words are key-sized: 32-bit keys use the low half of each 8-byte slot.
     double* dcoll = (double*)(c->arena + off_coll);
+    uint32_t* dnz = (uint32_t*)(c->arena + off_nz);
     {
         Timed tm(c, j.s, ST_COUNT);
-        HIP_TRY(c, launch_collisions(dhist, (uint32_t)S, ndig, dcoll, j.s));
+        HIP_TRY(c, launch_collisions(dhist, (uint32_t)S, ndig, dcoll, dnz, j.s));
     }
-    const size_t readback = S * 2 * sizeof(uint64_t) + S * ndig * sizeof(double) + 512;
+    const size_t readback = S * 2 * sizeof(uint64_t) + S * ndig * (sizeof(double) + 4) + 512;
     st = pin_reserve(c, readback, j.s);
     if (st) return st;
     uint64_t* h_or = palloc<uint64_t>(c, S);
     uint64_t* h_and = palloc<uint64_t>(c, S);
     double* h_coll = palloc<double>(c, S * ndig);
+    uint32_t* h_nz = palloc<uint32_t>(c, S * ndig);
     HIP_TRY(c, hipMemcpyAsync(h_or, dor, S * 8, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipMemcpyAsync(h_and, dand, S * 8, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipMemcpyAsync(h_coll, dcoll, S * ndig * sizeof(double), hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipMemcpyAsync(h_nz, dnz, S * ndig * 4, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipStreamSynchronize(j.s));
     std::vector<uint64_t> vor(S), vand(S);
     for (size_t i = 0; i < S; ++i) {
@@ -623,6 +635,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         }
     }
     const std::vector<double> coll(h_coll, h_coll + S * ndig);
+    const std::vector<uint32_t> nonzero(h_nz, h_nz + S * ndig);
     synced(c);
 
     // --- 2. plan ------------------------------------------------------------------
@@ -647,6 +660,14 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         int di = (j.first_level && j.top_d_forced > 0)
                      ? j.top_d_forced
                      : plan_segment(&coll[i * ndig], segs[i].len, kb, j.vb, j.divert, V[i]);
+        // Skewed prefix: when the top varying digit takes only a few values and its
+        // buckets would still need several more digits, deal that digit alone and let
+        // each bucket plan the rest with its own constant digits (digits that vary only
+        // across the few groups of the prefix are then skipped; Sec. 3 recursion).
+        const uint32_t nz_top = nonzero[i * ndig + V[i][0]];
+        if (!(j.first_level && j.top_d_forced > 0) && nv > 1 && nz_top <= kFewTopValues &&
+            (double)segs[i].len / nz_top > (double)j.divert * (double)(1u << rb))
+            di = 1;
         di = std::max(1, std::min(std::min(di, nv), MAX_PASSES));
         dsel[i] = di;
         d = std::max(d, di);
@@ -732,7 +753,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const uint32_t scan_tpb = 128;
     const uint32_t scan_nb = (uint32_t)((ntiles + scan_tpb - 1) / scan_tpb);
     const size_t need_nolb = nolb ? asize<uint32_t>(ntiles * RADIX) * 2 +
-                                        (single ? asize<uint32_t>((size_t)scan_nb * RADIX) : 0)
+                                        (single || perseg ? asize<uint32_t>((size_t)scan_nb * RADIX) : 0)
                                   : 0;
     st = arena_need(c, need_b + need_nolb, j.s);  // keeps region A
     if (st) return st;
@@ -743,7 +764,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         toff = aalloc<uint32_t>(c, ntiles * RADIX);
         tone = aalloc<uint32_t>(c, ntiles * RADIX);
     }
-    if (single) tpart = aalloc<uint32_t>(c, (size_t)scan_nb * RADIX);
+    if (single || perseg) tpart = aalloc<uint32_t>(c, (size_t)scan_nb * RADIX);
     dtiles = same_tiles ? (Tile*)(c->arena + off_ctiles) : aalloc<Tile>(c, ntiles);
     Tile* dhtiles = any_full ? aalloc<Tile>(c, nht) : dtiles;
     Seg* dsegs = aalloc<Seg>(c, S);
@@ -802,6 +823,26 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ta.off = toff;
             Timed ts(c, j.s, ST_OTHER);
             HIP_TRY(c, launch_tile_scan(ta, j.s));
+            HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
+        } else if (perseg) {
+            // A few long segments: the one-segment scan over each segment's tiles.
+            Timed ts(c, j.s, ST_OTHER);
+            for (uint32_t i : active) {
+                const Seg& g = hs[i];
+                if (p < g.first_pass) continue;
+                const uint32_t nt = (uint32_t)((g.len + j.tile - 1) / j.tile);
+                TileScanArgs ta{};
+                ta.cnt = p == 0 ? tcnt + (size_t)g.count_tile * ndig * RADIX
+                                : tone + (size_t)g.first_tile * RADIX;
+                ta.ndig = p == 0 ? ndig : 1;
+                ta.slot = p == 0 ? g.hslot[0] : 0;
+                ta.ntiles = nt;
+                ta.tiles_per_block = scan_tpb;
+                ta.nblocks = (nt + scan_tpb - 1) / scan_tpb;
+                ta.partial = tpart;
+                ta.off = toff + (size_t)g.first_tile * RADIX;
+                HIP_TRY(c, launch_tile_scan(ta, j.s));
+            }
             HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
         } else if (segscan) {
             SegScanArgs sa{};

@@ -1629,37 +1629,45 @@ __global__ __launch_bounds__(RADIX) void k_seg_scan(SegScanArgs a) {
 
 // Collision probability of each segment's digits (the chance that two records drawn
 // at random share the digit), the input of the plan's bucket-size estimate (Sec. 3).
-__global__ __launch_bounds__(RADIX) void k_collisions(const uint32_t* hist, int ndig, double* coll) {
+__global__ __launch_bounds__(RADIX) void k_collisions(const uint32_t* hist, int ndig, double* coll,
+                                                      uint32_t* nonzero) {
     __shared__ double s_sq[RADIX / 64], s_n[RADIX / 64];
+    __shared__ uint32_t s_nz[RADIX / 64];
     const uint32_t s = blockIdx.x, v = threadIdx.x, lane = v & 63, w = v >> 6;
     for (int j = 0; j < ndig; ++j) {
-        const double h = (double)hist[((size_t)s * ndig + j) * RADIX + v];
+        const uint32_t hv = hist[((size_t)s * ndig + j) * RADIX + v];
+        const double h = (double)hv;
         double sq = h * h, n = h;
         for (int o = 32; o > 0; o >>= 1) {
             sq += __shfl_xor(sq, o);
             n += __shfl_xor(n, o);
         }
+        const uint32_t nz = (uint32_t)__popcll(__ballot(hv != 0));
         if (lane == 0) {
             s_sq[w] = sq;
             s_n[w] = n;
+            s_nz[w] = nz;
         }
         __syncthreads();
         if (v == 0) {
             double tsq = 0, tn = 0;
+            uint32_t tnz = 0;
             for (int i = 0; i < RADIX / 64; ++i) {
                 tsq += s_sq[i];
                 tn += s_n[i];
+                tnz += s_nz[i];
             }
             coll[(size_t)s * ndig + j] = tn > 0 ? tsq / (tn * tn) : 0.0;
+            nonzero[(size_t)s * ndig + j] = tnz;
         }
         __syncthreads();
     }
 }
 
 hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, double* coll,
-                             hipStream_t s) {
+                             uint32_t* nonzero, hipStream_t s) {
     if (nsegs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_collisions, dim3(nsegs), dim3(RADIX), 0, s, hist, ndig, coll);
+    hipLaunchKernelGGL(k_collisions, dim3(nsegs), dim3(RADIX), 0, s, hist, ndig, coll, nonzero);
     return hipGetLastError();
 }
 

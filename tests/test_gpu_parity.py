@@ -335,3 +335,23 @@ def test_segmented_mixed_plans(torch, ctx, o, bits):
     torch.cuda.synchronize()
     rk, rv = o.segmented_sort(k, v, off)
     assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), ctx.stats()
+
+
+@pytest.mark.parametrize("bits,n", [(32, (1 << 25) + 12345), (64, (1 << 23) + 77)])
+def test_skewed_prefix_recursion(torch, ctx, o, bits, n):
+    """The top digit takes 4 values: the level deals it alone and each of the 4 large
+    buckets is planned on its own (the 32-bit case puts more than 1024 tiles in each
+    bucket, so the next level scans each bucket's tiles with the one-segment scan)."""
+    rng = np.random.default_rng(bits)
+    dt = np.uint32 if bits == 32 else np.uint64
+    low_bits = bits - 8
+    top = rng.choice(256, size=4, replace=False).astype(dt)
+    low = workloads.make_keys("uniform", n, bits, 77) & dt((1 << low_bits) - 1)
+    k = (top[rng.integers(0, 4, n)] << dt(low_bits)) | low
+    v = workloads.index_payload(n, bits)
+    say("skewed prefix", bits, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v)
+    assert st["levels"] >= 2 and st["top_digits"] == 1, st
+    assert o.check_index_payload(k, sk, sv) is None, st
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
