@@ -19,6 +19,7 @@ of the paper it follows, is stated in ``oracle.c``:
   when the payload is the input index.
 * ``stable_sort_typed`` -- the stable sort of signed-integer or floating-point keys
   (two's-complement value; IEEE 754 totalOrder), beyond the paper's unsigned keys.
+* ``overflow_fraction`` -- Eq. 2, the expected overflow of Fast Radix's estimated buckets.
 """
 from __future__ import annotations
 
@@ -42,7 +43,7 @@ def build(out_path: str = _LIB, defines: tuple[str, ...] = ()) -> str:
     the oracle with a planted mistake and check that the pins catch it.
     """
     cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", _SRC, "-o",
-           out_path + ".tmp"]
+           out_path + ".tmp", "-lm"]
     cmd[1:1] = [f"-D{d}" for d in defines]
     subprocess.run(cmd, check=True)
     os.replace(out_path + ".tmp", out_path)
@@ -72,6 +73,8 @@ class Oracle:
         lib.oracle_check_index_payload.argtypes = [P, Z, I, P, P, I, ctypes.POINTER(I)]
         lib.oracle_check_index_payload.restype = ctypes.c_int64
         lib.oracle_stable_sort_typed.argtypes = [P, P, Z, I, I, P, P]
+        lib.oracle_overflow_fraction.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+        lib.oracle_overflow_fraction.restype = ctypes.c_double
         self.lib = lib
 
     # -- helpers ---------------------------------------------------------------
@@ -105,6 +108,11 @@ class Oracle:
         self._rc(self.lib.oracle_stable_sort(self._p(keys), self._p(vals), keys.size, kb, vb,
                                              self._p(ok), self._p(ov)))
         return ok, ov
+
+    def overflow_fraction(self, N: int, M: int) -> float:
+        """Eq. 2: expected overflow of N uniform records dealt into M buckets of N/M slots,
+        as a fraction of N (Sec. 3.1)."""
+        return float(self.lib.oracle_overflow_fraction(N, M))
 
     # Key types of stable_sort_typed, by numpy dtype of the keys.
     KEY_TYPES = {np.dtype(np.uint32): 0, np.dtype(np.uint64): 1, np.dtype(np.int32): 2,

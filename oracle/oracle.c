@@ -31,6 +31,7 @@
  * arrays are contiguous, little-endian, structure-of-arrays.  Functions return 0 on
  * success, -1 on a bad argument, -2 when host memory runs out.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -477,4 +478,32 @@ int64_t oracle_check_index_payload(const void* in_keys, size_t n, int kb, const 
     }
     free(seen);
     return -1;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Fast Radix's estimated buckets (Sec. 3.1, Eq. 2).  N uniform records dealt into M */
+/* buckets of N/M slots each: a bucket that receives k < N/M records leaves          */
+/* N/M - k slots empty, and as many records overflow elsewhere.  The expected        */
+/* overflow as a fraction of N is the sum over k < ceil(N/M) of Eq. 2's term          */
+/*     (N/M - k) (M/N) C(N, k) (1/M)^k (1 - 1/M)^(N-k),                              */
+/* the binomial probability of k records in one bucket times its empty slots, over   */
+/* the M buckets.  Terms are evaluated in log space (lgamma) so that N may be large. */
+/* ------------------------------------------------------------------------------ */
+double oracle_overflow_fraction(uint64_t N, uint32_t M) {
+    if (N == 0 || M < 2) return 0.0;
+    const double n = (double)N, m = (double)M, cap = n / m;
+#ifdef ORACLE_PLANT_OVERFLOW_EXTRA_TERM
+    /* Planted mistake for the pin tests: one term too many. */
+    const uint64_t kmax = (N + M - 1) / M + 1;
+#else
+    const uint64_t kmax = (N + M - 1) / M;  /* ceil(N/M): k runs over [0, kmax) */
+#endif
+    const double lp = log(1.0 / m), lq = log1p(-1.0 / m), lgn = lgamma(n + 1.0);
+    double sum = 0.0;
+    for (uint64_t k = 0; k < kmax; ++k) {
+        const double kk = (double)k;
+        const double lbin = lgn - lgamma(kk + 1.0) - lgamma(n - kk + 1.0) + kk * lp + (n - kk) * lq;
+        sum += (cap - kk) * (m / n) * exp(lbin);
+    }
+    return sum;
 }

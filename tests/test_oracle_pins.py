@@ -220,9 +220,38 @@ def pin_typed_numpy(o):
     assert np.array_equal(o.stable_sort_typed(k)[0], o.stable_sort(k)[0])
 
 
+def pin_overflow_enumeration(o):
+    """Eq. 2 against the expected overflow computed over every one of the M^N equally
+    likely ways to deal N records into M buckets of N/M slots (tiny N)."""
+    import itertools
+    from fractions import Fraction
+    for N, M in ((1, 2), (2, 2), (3, 2), (5, 2), (7, 2), (4, 3), (6, 3), (8, 2), (5, 4), (7, 4)):
+        cap = Fraction(N, M)
+        total = Fraction(0)
+        for deal in itertools.product(range(M), repeat=N):
+            counts = [deal.count(b) for b in range(M)]
+            total += sum(max(Fraction(0), c - cap) for c in counts)
+        exact = total / (M ** N) / N
+        assert abs(o.overflow_fraction(N, M) - float(exact)) < 1e-12, (N, M)
+
+
+def pin_overflow_monte_carlo(o):
+    """Eq. 2 against simulation (multinomial deals), and its large-N limit."""
+    import math
+    rng = np.random.default_rng(5)
+    for N, M, trials in ((1000, 256, 4000), (65536, 256, 400), (300, 16, 4000)):
+        counts = rng.multinomial(N, [1.0 / M] * M, size=trials)
+        frac = np.maximum(counts - N / M, 0).sum(axis=1) / N
+        mean, sem = frac.mean(), frac.std() / math.sqrt(trials)
+        assert abs(o.overflow_fraction(N, M) - mean) < 5 * sem + 1e-12, (N, M)
+    N = 1 << 24
+    assert abs(o.overflow_fraction(N, 256) / math.sqrt(255 / (2 * math.pi * N)) - 1) < 1e-3
+
+
 ALL_PINS = [pin_bruteforce_small_alphabet, pin_bruteforce_extremes, pin_numpy,
             pin_special_cases, pin_golden, pin_properties, pin_rank_formula,
-            pin_typed_golden, pin_typed_numpy]
+            pin_typed_golden, pin_typed_numpy, pin_overflow_enumeration,
+            pin_overflow_monte_carlo]
 
 
 # --------------------------------------------------------------------------------------
@@ -326,7 +355,7 @@ def test_checker_catches_each_broken_property(o):
 
 MUTANTS = ["ORACLE_PLANT_REVERSED_TIES", "ORACLE_PLANT_SIGNED_COMPARE",
            "ORACLE_PLANT_DROP_LAST", "ORACLE_PLANT_INCLUSIVE_SCAN",
-           "ORACLE_PLANT_FLOAT_NO_REVERSE"]
+           "ORACLE_PLANT_FLOAT_NO_REVERSE", "ORACLE_PLANT_OVERFLOW_EXTRA_TERM"]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS)
