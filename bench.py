@@ -528,7 +528,8 @@ def run_plain(args):
         "hbm_frac_sort": round(hbm_frac_sort, 4),
         "plan": {"top_digits": d, "levels": plan["levels"] if plan else 0,
                  "deal_passes": plan["deal_passes"] if plan else 0,
-                 "large_buckets": plan["large_buckets"] if plan else 0},
+                 "large_buckets": plan["large_buckets"] if plan else 0,
+                 "estimated_bucket_overflow": plan["estimated_overflow"] if plan else None},
         "stage_ms_one_sort": {k: round(v, 4) for k, v in stage.items() if k.startswith("ms_")},
         "result_check": parity,
     }

@@ -261,6 +261,10 @@ typedef struct {
     double ms_local_sort;
     double ms_other;
     int32_t deal_launches_timed; /* number of deal launches summed in ms_deal     */
+    double estimated_overflow; /* fraction of the records that Fast Radix's
+                                  estimated buckets (ceil(n / 2^b) slots each, Sec.
+                                  3.1) would have overflowed when dealing the first
+                                  level's top varying digit; measured from the counts */
 } dfr_stats;
 
 dfr_status dfr_get_stats(const dfr_ctx* ctx, dfr_stats* out);

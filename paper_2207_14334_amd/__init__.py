@@ -59,6 +59,7 @@ class Stats(ctypes.Structure):
         ("ms_count", ctypes.c_double), ("ms_deal", ctypes.c_double),
         ("ms_buckets", ctypes.c_double), ("ms_local_sort", ctypes.c_double),
         ("ms_other", ctypes.c_double), ("deal_launches_timed", ctypes.c_int32),
+        ("estimated_overflow", ctypes.c_double),
     ]
 
     def as_dict(self):

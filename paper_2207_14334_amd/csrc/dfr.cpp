@@ -558,7 +558,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const bool nolb = single || segscan || perseg;
     const size_t tcnt_n = nolb ? tiles.size() * ndig * RADIX : 0;
     dfr_status st = arena_reserve(c, asize<uint32_t>(hist_n) + 2 * asize<uint64_t>(S) +
-                                         asize<double>(S * ndig) + asize<uint32_t>(S * ndig) +
+                                         asize<double>(S * ndig) + 2 * asize<uint32_t>(S * ndig) +
                                          asize<uint32_t>(tcnt_n) +
                                          asize<Tile>(tiles.size()), j.s);
     if (st) return st;
@@ -567,6 +567,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const size_t off_coll = c->arena_used;
     aalloc<double>(c, S * ndig);
     const size_t off_nz = c->arena_used;
+    aalloc<uint32_t>(c, S * ndig);
+    const size_t off_ovf = c->arena_used;
     aalloc<uint32_t>(c, S * ndig);
     const size_t off_or = c->arena_used;
     aalloc<uint64_t>(c, S);
@@ -608,21 +610,24 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // The OR/AND words are key-sized: 32-bit keys use the low half of each 8-byte slot.
     double* dcoll = (double*)(c->arena + off_coll);
     uint32_t* dnz = (uint32_t*)(c->arena + off_nz);
+    uint32_t* dovf = (uint32_t*)(c->arena + off_ovf);
     {
         Timed tm(c, j.s, ST_COUNT);
-        HIP_TRY(c, launch_collisions(dhist, (uint32_t)S, ndig, dcoll, dnz, j.s));
+        HIP_TRY(c, launch_collisions(dhist, (uint32_t)S, ndig, rb, dcoll, dnz, dovf, j.s));
     }
-    const size_t readback = S * 2 * sizeof(uint64_t) + S * ndig * (sizeof(double) + 4) + 512;
+    const size_t readback = S * 2 * sizeof(uint64_t) + S * ndig * (sizeof(double) + 8) + 512;
     st = pin_reserve(c, readback, j.s);
     if (st) return st;
     uint64_t* h_or = palloc<uint64_t>(c, S);
     uint64_t* h_and = palloc<uint64_t>(c, S);
     double* h_coll = palloc<double>(c, S * ndig);
     uint32_t* h_nz = palloc<uint32_t>(c, S * ndig);
+    uint32_t* h_ovf = palloc<uint32_t>(c, S * ndig);
     HIP_TRY(c, hipMemcpyAsync(h_or, dor, S * 8, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipMemcpyAsync(h_and, dand, S * 8, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipMemcpyAsync(h_coll, dcoll, S * ndig * sizeof(double), hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipMemcpyAsync(h_nz, dnz, S * ndig * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipMemcpyAsync(h_ovf, dovf, S * ndig * 4, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipStreamSynchronize(j.s));
     std::vector<uint64_t> vor(S), vand(S);
     for (size_t i = 0; i < S; ++i) {
@@ -636,6 +641,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     }
     const std::vector<double> coll(h_coll, h_coll + S * ndig);
     const std::vector<uint32_t> nonzero(h_nz, h_nz + S * ndig);
+    const std::vector<uint32_t> overflow(h_ovf, h_ovf + S * ndig);
     synced(c);
 
     // --- 2. plan ------------------------------------------------------------------
@@ -673,6 +679,16 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         d = std::max(d, di);
     }
     c->arena_used = region_a;  // the rest of the arena is free again
+    if (j.first_level) {
+        // What Fast Radix's estimated buckets would have overflowed on the top varying
+        // digit of each segment (Sec. 3.1; Eq. 2 gives its expectation for uniform keys).
+        double ov = 0, len = 0;
+        for (uint32_t i : active) {
+            ov += overflow[i * ndig + V[i][0]];
+            len += (double)segs[i].len;
+        }
+        c->stats.estimated_overflow = len > 0 ? ov / len : 0.0;
+    }
     if (in == 1) {
         st = copy_back(j, finished);
         if (st) return st;

@@ -217,10 +217,11 @@ hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
 hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s);
 hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s);
-// coll[s * ndig + j] = sum_v h[v]^2 / (sum_v h[v])^2 for each segment's digit-j histogram,
-// and nonzero[s * ndig + j] = the number of its non-empty bins.
-hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, double* coll,
-                             uint32_t* nonzero, hipStream_t s);
+// For each segment's digit-j histogram h (digits of `bits` bits):
+// coll[s * ndig + j] = sum_v h[v]^2 / (sum_v h[v])^2, nonzero[...] = its non-empty bins,
+// overflow[...] = sum_v max(0, h[v] - ceil(len / 2^bits)).
+hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, int bits, double* coll,
+                             uint32_t* nonzero, uint32_t* overflow, hipStream_t s);
 // In-place map of signed (mode 1) or floating-point (mode 2) keys to unsigned keys of
 // the same order, or back (inverse).  Mode 0 does nothing.
 hipError_t launch_key_transform(int kb, int mode, bool inverse, void* keys, size_t n,

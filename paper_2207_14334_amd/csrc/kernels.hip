@@ -1629,10 +1629,13 @@ __global__ __launch_bounds__(RADIX) void k_seg_scan(SegScanArgs a) {
 
 // Collision probability of each segment's digits (the chance that two records drawn
 // at random share the digit), the input of the plan's bucket-size estimate (Sec. 3).
-__global__ __launch_bounds__(RADIX) void k_collisions(const uint32_t* hist, int ndig, double* coll,
-                                                      uint32_t* nonzero) {
+__global__ __launch_bounds__(RADIX) void k_collisions(const uint32_t* hist, int ndig, int bits,
+                                                      double* coll, uint32_t* nonzero,
+                                                      uint32_t* overflow) {
     __shared__ double s_sq[RADIX / 64], s_n[RADIX / 64];
     __shared__ uint32_t s_nz[RADIX / 64];
+    __shared__ uint32_t s_len;
+    __shared__ uint32_t s_ov[RADIX / 64];
     const uint32_t s = blockIdx.x, v = threadIdx.x, lane = v & 63, w = v >> 6;
     for (int j = 0; j < ndig; ++j) {
         const uint32_t hv = hist[((size_t)s * ndig + j) * RADIX + v];
@@ -1659,15 +1662,30 @@ __global__ __launch_bounds__(RADIX) void k_collisions(const uint32_t* hist, int 
             }
             coll[(size_t)s * ndig + j] = tn > 0 ? tsq / (tn * tn) : 0.0;
             nonzero[(size_t)s * ndig + j] = tnz;
+            s_len = (uint32_t)tn;
+        }
+        __syncthreads();
+        // Records that estimated buckets of ceil(len / 2^bits) slots would not hold
+        // (Fast Radix, Sec. 3.1): the measured counterpart of Eq. 2.
+        const uint32_t m = 1u << bits, cap = (s_len + m - 1) / m;
+        uint32_t ov = v < m && hv > cap ? hv - cap : 0u;
+        for (int o = 32; o > 0; o >>= 1) ov += __shfl_xor(ov, o);
+        if (lane == 0) s_ov[w] = ov;
+        __syncthreads();
+        if (v == 0) {
+            uint32_t t = 0;
+            for (int i = 0; i < RADIX / 64; ++i) t += s_ov[i];
+            overflow[(size_t)s * ndig + j] = t;
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, double* coll,
-                             uint32_t* nonzero, hipStream_t s) {
+hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, int bits, double* coll,
+                             uint32_t* nonzero, uint32_t* overflow, hipStream_t s) {
     if (nsegs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_collisions, dim3(nsegs), dim3(RADIX), 0, s, hist, ndig, coll, nonzero);
+    hipLaunchKernelGGL(k_collisions, dim3(nsegs), dim3(RADIX), 0, s, hist, ndig, bits, coll, nonzero,
+                       overflow);
     return hipGetLastError();
 }
 

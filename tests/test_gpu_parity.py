@@ -355,3 +355,23 @@ def test_skewed_prefix_recursion(torch, ctx, o, bits, n):
     assert o.check_index_payload(k, sk, sv) is None, st
     rk, rv = o.stable_sort(k, v)
     assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "normal"])
+def test_estimated_overflow(torch, ctx, o, dist):
+    """The overflow Fast Radix's estimated buckets would meet on the top varying digit
+    (Sec. 3.1): exactly the count the histogram gives, and for uniform keys close to the
+    expectation of Eq. 2."""
+    n = 1 << 24
+    k = workloads.make_keys(dist, n, 32, 8)
+    say("estimated overflow", dist, n)
+    _, _, st = gpu_sort(torch, ctx, k, None)
+    orv = np.bitwise_or.reduce(k) ^ np.bitwise_and.reduce(k)
+    top = max(j for j in range(4) if (int(orv) >> (8 * j)) & 0xFF)
+    h = np.bincount(((k >> np.uint32(8 * top)) & np.uint32(0xFF)).astype(np.int64), minlength=256)
+    cap = -(-n // 256)
+    expect = float(np.maximum(h - cap, 0).sum()) / float(n)
+    assert st["estimated_overflow"] == expect, (st["estimated_overflow"], expect)
+    if dist == "uniform":
+        eq2 = o.overflow_fraction(n, 256)
+        assert abs(st["estimated_overflow"] / eq2 - 1) < 0.25, (st["estimated_overflow"], eq2)
