@@ -985,21 +985,28 @@ __device__ __forceinline__ bool bucket_sort_chunk(
 #ifndef DFR_LOCAL_MIN_WAVES  // waves per SIMD the bucketed local sort must fit
 #define DFR_LOCAL_MIN_WAVES 6
 #endif
+#ifndef DFR_LOCAL_MIN_WAVES32  // the same for its 32-bit-word form
+#define DFR_LOCAL_MIN_WAVES32 8
+#endif
+#ifndef DFR_LOCAL_DB_LESS  // bin bits below the most the position width allows
+#define DFR_LOCAL_DB_LESS 0
+#endif
 template <int KB, int VB, int THREADS, int CAP, int WORDS>
-__global__ __launch_bounds__(THREADS, DFR_LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
+__global__ __launch_bounds__(THREADS, WORDS == 32 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
     constexpr int MAXI = CAP / THREADS;
     constexpr int KBITS = 8 * KB;
     constexpr int IB = CAP <= 4096 ? 12 : CAP <= 8192 ? 13 : 16;  // bits of a position
-    constexpr int DB = IB - 1;                                     // most bin bits
+    constexpr int DB = IB - 1 - DFR_LOCAL_DB_LESS;                                     // most bin bits
     constexpr int NWORDS = (1 << DB) / 2;  // two 16-bit bin counters per LDS word
     static_assert(CAP % THREADS == 0 && CAP <= (1 << IB), "chunk layout");
     static_assert(CAP < (1 << 16), "a destination and a source share one 32-bit word");
     static_assert(VB <= 8, "values fit the word buffer");
-
-    __shared__ uint64_t s_w[CAP];
+    // Words, then (once ranked) values, share one buffer sized for the wider of the two.
+    using SW = typename uint_of<(WORDS / 8 > VB ? WORDS / 8 : (VB > 4 ? 8 : 4))>::type;
+    __shared__ SW s_w[CAP];
     __shared__ uint32_t s_bin[NWORDS];
     __shared__ uint32_t s_part[W];
     __shared__ uint32_t s_max[W];
