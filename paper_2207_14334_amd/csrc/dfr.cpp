@@ -518,7 +518,7 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         int max_lo = 0;
         for (const Seg& g : hs) max_lo = std::max(max_lo, (int)g.lo_bit);
         HIP_TRY(c, launch_local_sort(j.kb, j.vb, la, blocks,
-                                     local_sort_narrow_first(j.kb, j.vb, max_lo), j.s));
+                                     local_sort_first_form(j.kb, j.vb, max_lo), j.s));
         c->stats.chunks += nb;
     }
     c->stats.used_diversion = 1;
@@ -992,7 +992,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         for (uint32_t i : active)
             if (!full[i]) max_lo = std::max(max_lo, (int)hs[i].lo_bit);
         HIP_TRY(c, launch_local_sort(kb, j.vb, la, blocks,
-                                     local_sort_narrow_first(kb, j.vb, max_lo), j.s));
+                                     local_sort_first_form(kb, j.vb, max_lo), j.s));
     }
     c->stats.used_diversion = 1;
 

@@ -228,11 +228,12 @@ hipError_t launch_key_transform(int kb, int mode, bool inverse, void* keys, size
                                 hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
-// Whether chunks whose buckets agree on every bit >= max_lo_bit may fit the 32-bit
-// word form of the local sort (which then runs first).
-bool local_sort_narrow_first(int kb, int vb, int max_lo_bit);
+// Which form of the local sort runs first for chunks whose buckets agree on every bit
+// >= max_lo_bit: 0 and 1 use 32-bit words (with and without the position inside), 2
+// 64-bit words.
+int local_sort_first_form(int kb, int vb, int max_lo_bit);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
-                             bool narrow_first, hipStream_t s);
+                             int first_form, hipStream_t s);
 hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t nchunks,
                               hipStream_t s);
 hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, void* kout,

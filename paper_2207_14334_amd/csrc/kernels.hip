@@ -45,6 +45,17 @@ constexpr uint32_t SPIN_LIMIT = 1u << 22;
 #endif
 constexpr int DEAL_ORDER = DFR_DEAL_ORDER;
 
+// Shapes of the bucketed local sort (overridable at build time for tuning sweeps).
+#ifndef DFR_LOCAL_MIN_WAVES  // waves per SIMD the bucketed local sort must fit
+#define DFR_LOCAL_MIN_WAVES 6
+#endif
+#ifndef DFR_LOCAL_MIN_WAVES32  // the same for its 32-bit-word form
+#define DFR_LOCAL_MIN_WAVES32 8
+#endif
+#ifndef DFR_LOCAL_DB_LESS  // bin bits below the most the position width allows
+#define DFR_LOCAL_DB_LESS 0
+#endif
+
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
@@ -812,17 +823,20 @@ struct Words {
     uint64_t v[MAXI];
 };
 
-template <typename WT, int KB, int VB, int THREADS, int CAP, int IB, int DB, int MAXI>
+template <typename WT, bool SEPPOS, int KB, int VB, int THREADS, int CAP, int IB, int DB, int MAXI>
 __device__ __forceinline__ bool bucket_sort_chunk(
     Words<MAXI> x, uint32_t len, uint32_t iu, uint32_t wbase, int lane, int w,
     int tid, uint32_t nbk, int h, int B, typename uint_of<KB>::type key0,
     const typename uint_of<KB>::type* kin, const typename uint_of<VB>::type* vin,
     typename uint_of<KB>::type* kout, typename uint_of<VB>::type* vout, const uint32_t* s_rel,
-    WT* s_w, uint32_t* s_bin, uint32_t* s_part, uint32_t* s_max) {
+    WT* s_w, uint16_t* s_pos, uint32_t* s_bin, uint32_t* s_part, uint32_t* s_max) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
     constexpr uint32_t GMAX = 64;
+    // With SEPPOS the words hold the sort bits only and the position sits beside them in
+    // s_pos (ties broken by it); otherwise the words carry it in their low IB bits.
+    constexpr int PB = SEPPOS ? 0 : IB;
     const uint64_t mask_h = (1ull << h) - 1ull;  // h < 64 here
     WT xw[MAXI];
 
@@ -839,11 +853,11 @@ __device__ __forceinline__ bool bucket_sort_chunk(
             }
             bi = lo_i;
         }
-        xw[k] = (WT)((((x.v[k] & mask_h) | (bi << h)) << IB) | idx);
+        xw[k] = (WT)((((x.v[k] & mask_h) | (bi << h)) << PB) | (SEPPOS ? 0u : idx));
     }
     const int nbits = B < DB ? B : DB;
     const uint32_t nbins = 1u << nbits;
-    const int dshift = IB + B - nbits;
+    const int dshift = PB + B - nbits;
     const uint32_t nwords = nbins > 1 ? nbins / 2 : 1;
     if (nbk > 1) __syncthreads();  // s_rel no longer needed
     // Slots inside the bins.
@@ -904,7 +918,10 @@ __device__ __forceinline__ bool bucket_sort_chunk(
             const uint32_t d = (uint32_t)(xw[k] >> dshift) & (nbins - 1);
             const uint32_t st = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
             const uint32_t q = st + slot[k];
-            if (q < CAP) s_w[q] = xw[k];
+            if (q < CAP) {
+                s_w[q] = xw[k];
+                if (SEPPOS) s_pos[q] = (uint16_t)idx;
+            }
         }
     }
     __syncthreads();
@@ -927,13 +944,21 @@ __device__ __forceinline__ bool bucket_sort_chunk(
             const uint32_t gs = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
             const uint32_t dn = d + 1;
             const uint32_t ge = dn < nbins ? (s_bin[dn >> 1] >> (16 * (dn & 1))) & 0xffffu : len;
-            uint32_t r = 0;
-            for (uint32_t q = gs; q < ge; ++q) r += s_w[q] < me;
+            uint32_t r = 0, src;
+            if (SEPPOS) {
+                src = s_pos[p];
+                for (uint32_t q = gs; q < ge; ++q) {
+                    const WT o = s_w[q];
+                    r += (o < me) | ((o == me) & (s_pos[q] < src));
+                }
+            } else {
+                for (uint32_t q = gs; q < ge; ++q) r += s_w[q] < me;
+                src = (uint32_t)me & ((1u << IB) - 1u);
+            }
             const uint32_t at = gs + r < len ? gs + r : len - 1;
-            const uint32_t src = (uint32_t)me & ((1u << IB) - 1u);
             const uint64_t hi = nbk > 1 ? ((uint64_t)kin[at] & ~mask_h) : hi0;
             pos[k] = at | (src << 16);
-            ko[k] = (K)((((uint64_t)me >> IB) & mask_h) | hi);
+            ko[k] = (K)((((uint64_t)me >> PB) & mask_h) | hi);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -982,17 +1007,11 @@ __device__ __forceinline__ bool bucket_sort_chunk(
 // bits do not fit next to the position, or whose largest bin exceeds GMAX records,
 // goes to the spill list for the stable radix kernel below.
 // ---------------------------------------------------------------------------------
-#ifndef DFR_LOCAL_MIN_WAVES  // waves per SIMD the bucketed local sort must fit
-#define DFR_LOCAL_MIN_WAVES 6
-#endif
-#ifndef DFR_LOCAL_MIN_WAVES32  // the same for its 32-bit-word form
-#define DFR_LOCAL_MIN_WAVES32 8
-#endif
-#ifndef DFR_LOCAL_DB_LESS  // bin bits below the most the position width allows
-#define DFR_LOCAL_DB_LESS 0
-#endif
-template <int KB, int VB, int THREADS, int CAP, int WORDS>
-__global__ __launch_bounds__(THREADS, WORDS == 32 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
+// FORM 0: 32-bit words with the position inside; 1: 32-bit words, position beside them;
+// 2: 64-bit words with the position inside.  Forms 0 and 1 hand chunks that do not fit
+// to the 64-bit form's list.
+template <int KB, int VB, int THREADS, int CAP, int FORM>
+__global__ __launch_bounds__(THREADS, FORM < 2 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
@@ -1005,8 +1024,10 @@ __global__ __launch_bounds__(THREADS, WORDS == 32 ? DFR_LOCAL_MIN_WAVES32 : DFR_
     static_assert(CAP < (1 << 16), "a destination and a source share one 32-bit word");
     static_assert(VB <= 8, "values fit the word buffer");
     // Words, then (once ranked) values, share one buffer sized for the wider of the two.
-    using SW = typename uint_of<(WORDS / 8 > VB ? WORDS / 8 : (VB > 4 ? 8 : 4))>::type;
+    constexpr int WB = FORM < 2 ? 4 : 8;  // word bytes
+    using SW = typename uint_of<(WB > VB ? WB : (VB > 4 ? 8 : 4))>::type;
     __shared__ SW s_w[CAP];
+    __shared__ uint16_t s_pos[FORM == 1 ? CAP : 1];
     __shared__ uint32_t s_bin[NWORDS];
     __shared__ uint32_t s_part[W];
     __shared__ uint32_t s_max[W];
@@ -1074,7 +1095,7 @@ __global__ __launch_bounds__(THREADS, WORDS == 32 ? DFR_LOCAL_MIN_WAVES32 : DFR_
             spill(item);
             continue;
         }
-        if (WORDS == 32 && B + IB > 32) {  // the 64-bit form sorts it
+        if (FORM < 2 && B + (FORM == 0 ? IB : 0) > 32) {  // the 64-bit form sorts it
             if (tid == 0) {
                 const uint32_t m = atomicAdd(a.nwide, 1u);
                 if (m < a.widecap) a.wide[m] = item;
@@ -1099,10 +1120,10 @@ __global__ __launch_bounds__(THREADS, WORDS == 32 ? DFR_LOCAL_MIN_WAVES32 : DFR_
             for (uint32_t i = tid; i < nbk; i += THREADS) s_rel[i] = (uint32_t)(a.bstart[ch.f + i] - start);
             __syncthreads();
         }
-        using WT = typename uint_of<WORDS / 8>::type;
-        const bool ok = bucket_sort_chunk<WT, KB, VB, THREADS, CAP, IB, DB, MAXI>(
+        using WT = typename uint_of<WB>::type;
+        const bool ok = bucket_sort_chunk<WT, FORM == 1, KB, VB, THREADS, CAP, IB, DB, MAXI>(
             xs, len, iu, wbase, lane, w, tid, nbk, h, B, key0, kin, vin, kout, vout, s_rel,
-            (WT*)s_w, s_bin, s_part, s_max);
+            (WT*)s_w, s_pos, s_bin, s_part, s_max);
         if (!ok) spill(item);
     }
 }
@@ -1782,26 +1803,30 @@ hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s
 }
 
 template <int KB, int VB>
-static void local_kb_vb(const LocalArgs& a, uint32_t blocks, bool narrow_first, hipStream_t s) {
+static void local_kb_vb(const LocalArgs& a, uint32_t blocks, int first_form, hipStream_t s) {
     constexpr int CAP = KB + VB <= 8 ? LOCAL_CAP_SMALL : LOCAL_CAP_LARGE;
     constexpr int BCAP = KB + VB <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE;
-    // With narrow_first, 32-bit words first, and chunks whose sort bits and position
-    // need more go to the 64-bit form; otherwise the 64-bit form takes every chunk.
-    // Chunks neither can take go to the general kernel.
+    // A 32-bit form first (first_form 0 or 1), handing chunks that need more to the
+    // 64-bit form; or the 64-bit form for every chunk (first_form 2).  Chunks none of
+    // them can take go to the general kernel.
     LocalArgs wa = a;
     wa.spill_only = 0;
     uint32_t wblocks = blocks;
-    if (narrow_first) {
+    if (first_form < 2) {
         LocalArgs pa = a;
         pa.spill_only = 0;
-        hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 32>), dim3(blocks),
-                           dim3(LOCAL_THREADS), 0, s, pa);
+        if (first_form == 0)
+            hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 0>), dim3(blocks),
+                               dim3(LOCAL_THREADS), 0, s, pa);
+        else
+            hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 1>), dim3(blocks),
+                               dim3(LOCAL_THREADS), 0, s, pa);
         wa.work = a.wide;
         wa.nwork = a.nwide;
         wa.workcap = a.widecap;
         wblocks = blocks < 4096 ? blocks : 4096;
     }
-    hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 64>), dim3(wblocks),
+    hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 2>), dim3(wblocks),
                        dim3(LOCAL_THREADS), 0, s, wa);
     LocalArgs ga = a;
     ga.spill_only = 1;
@@ -1810,24 +1835,26 @@ static void local_kb_vb(const LocalArgs& a, uint32_t blocks, bool narrow_first, 
                        dim3(GENERAL_THREADS), 0, s, ga);
 }
 
-bool local_sort_narrow_first(int kb, int vb, int max_lo_bit) {
+int local_sort_first_form(int kb, int vb, int max_lo_bit) {
     // A chunk's sort bits are at most its lo_bit varying bits plus a few bits of bucket
-    // index; when even lo_bit and the position exceed 32 bits, no chunk fits 32-bit words.
+    // index.  With room for the position as well, the 32-bit words carry it (form 0);
+    // else, up to 32 bits of lo_bit, the position goes beside them (form 1).
     const int ib = (kb + vb <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE) <= 4096 ? 12 : 13;
-    return max_lo_bit + ib <= 32;
+    if (max_lo_bit + ib <= 32) return 0;
+    return max_lo_bit <= 32 ? 1 : 2;
 }
 
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
-                             bool narrow_first, hipStream_t s) {
+                             int first_form, hipStream_t s) {
     if (blocks == 0) return hipSuccess;
     if (kb == 4) {
-        if (vb == 0) local_kb_vb<4, 0>(a, blocks, narrow_first, s);
-        else if (vb == 4) local_kb_vb<4, 4>(a, blocks, narrow_first, s);
-        else local_kb_vb<4, 8>(a, blocks, narrow_first, s);
+        if (vb == 0) local_kb_vb<4, 0>(a, blocks, first_form, s);
+        else if (vb == 4) local_kb_vb<4, 4>(a, blocks, first_form, s);
+        else local_kb_vb<4, 8>(a, blocks, first_form, s);
     } else {
-        if (vb == 0) local_kb_vb<8, 0>(a, blocks, narrow_first, s);
-        else if (vb == 4) local_kb_vb<8, 4>(a, blocks, narrow_first, s);
-        else local_kb_vb<8, 8>(a, blocks, narrow_first, s);
+        if (vb == 0) local_kb_vb<8, 0>(a, blocks, first_form, s);
+        else if (vb == 4) local_kb_vb<8, 4>(a, blocks, first_form, s);
+        else local_kb_vb<8, 8>(a, blocks, first_form, s);
     }
     return hipGetLastError();
 }
