@@ -483,6 +483,17 @@ def run_plain(args):
     torch.cuda.synchronize()
     stage = ctx.stats()
     ctx.set_option("timing", 0)
+    # Cold variant: the first sort on a fresh context, its scratch (temp buffer, arena,
+    # pinned staging) allocated inside the call, as a one-off caller would see it.
+    ks[0].copy_(base_k)
+    vs[0].copy_(base_v)
+    torch.cuda.synchronize()
+    cold_ctx = dfr.Context(0)
+    c0 = time.perf_counter()
+    cold_ctx.sort_(ks[0], vs[0])
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - c0) * 1e3
+    cold_ctx.close()
     elapsed = t1 - t0
     ms_step = elapsed / args.steps * 1e3
     gkeys = n * args.steps / elapsed / 1e9
@@ -542,6 +553,7 @@ def run_plain(args):
                  "large_buckets": plan["large_buckets"] if plan else 0,
                  "estimated_bucket_overflow": plan["estimated_overflow"] if plan else None},
         "stage_ms_one_sort": {k: round(v, 4) for k, v in stage.items() if k.startswith("ms_")},
+        "cold_first_sort_ms": round(cold_ms, 3),
         "result_check": parity,
     }
     print(json.dumps(out), flush=True)

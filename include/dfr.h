@@ -97,9 +97,11 @@ dfr_status dfr_sort_u64(dfr_ctx* ctx, uint64_t* keys, uint64_t* vals, size_t n, 
  * exactly as the plain sort would sort it (Sec. 3; large buckets are themselves
  * sorted by the same procedure).
  *
- * seg_offsets: HOST array of num_segments + 1 entries, seg_offsets[0] == 0,
- * non-decreasing, seg_offsets[num_segments] == n (total records).  Empty segments
- * are allowed.  keys/vals/temp as for the plain sort, covering all n records.
+ * seg_offsets: num_segments + 1 entries, seg_offsets[0] == 0, non-decreasing,
+ * seg_offsets[num_segments] == n (total records), in host memory or in device memory
+ * (then read back after the work already queued on `stream`, which blocks the host
+ * until that work is done).  Empty segments are allowed.  keys/vals/temp as for the
+ * plain sort, covering all n records.
  * ------------------------------------------------------------------------------- */
 dfr_status dfr_sort_segmented_u32(dfr_ctx* ctx, uint32_t* keys, uint32_t* vals,
                                   const uint64_t* seg_offsets, size_t num_segments,

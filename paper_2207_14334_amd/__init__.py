@@ -320,11 +320,23 @@ class Context:
 
     def sort_segmented_(self, keys, vals, offsets, temp=None, stream=None):
         """Sort each segment [offsets[i], offsets[i+1]) of keys/vals independently.
-        ``offsets`` is a host sequence of num_segments + 1 integers."""
+        ``offsets`` holds num_segments + 1 integers: a host sequence, or a contiguous
+        uint64/int64 GPU tensor (read back by the library after the queued work)."""
         import numpy as np
+        import torch
         _check_tensor(keys, "keys")
         kt = _key_type(keys)
-        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        if isinstance(offsets, torch.Tensor) and offsets.is_cuda:
+            if offsets.dtype not in (torch.uint64, torch.int64) or not offsets.is_contiguous():
+                raise ValueError("GPU offsets must be a contiguous 64-bit tensor")
+
+            class _DevOffsets:  # the pointer and count the C call needs
+                def __init__(self, t):
+                    self.ctypes = type("P", (), {"data": t.data_ptr()})()
+                    self.size = t.numel()
+            off = _DevOffsets(offsets)
+        else:
+            off = np.ascontiguousarray(offsets, dtype=np.uint64)
         vp, vb = None, 0
         if vals is not None:
             _check_tensor(vals, "vals")

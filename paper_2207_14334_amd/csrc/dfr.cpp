@@ -1216,11 +1216,35 @@ dfr_status parse_segments(const uint64_t* off, size_t S, int kb, std::vector<LSe
     return DFR_OK;
 }
 
-dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const uint64_t* off,
+// Segment offsets as a host array: device memory is copied back after the work already
+// queued on the stream (the caller's stream order), host memory is used as it is.
+dfr_status host_offsets(dfr_ctx* c, const uint64_t* off, size_t S, hipStream_t s,
+                        std::vector<uint64_t>& buf, const uint64_t** out) {
+    *out = off;
+    if (!off) return DFR_E_INVALID_ARG;
+    hipPointerAttribute_t attr{};
+    const hipError_t e = hipPointerGetAttributes(&attr, off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // ordinary host memory is not known to HIP
+        return DFR_OK;
+    }
+    if (attr.type != hipMemoryTypeDevice) return DFR_OK;
+    buf.resize(S + 1);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(buf.data(), off, (S + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    *out = buf.data();
+    return DFR_OK;
+}
+
+dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const uint64_t* off_in,
                           size_t S, void* temp, size_t temp_bytes, void* stream, int mode = 0) {
     if (!c) return DFR_E_INVALID_ARG;
     std::vector<LSeg> segs;
-    if (!off) return DFR_E_INVALID_ARG;
+    std::vector<uint64_t> off_buf;
+    const uint64_t* off = nullptr;
+    dfr_status st0 = host_offsets(c, off_in, S, (hipStream_t)stream, off_buf, &off);
+    if (st0) return st0;
     const size_t n = off[S];
     dfr_status st = validate(c, keys, vals, n, kb, vb, temp, temp_bytes);
     if (st) return st;

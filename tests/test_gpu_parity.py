@@ -375,3 +375,19 @@ def test_estimated_overflow(torch, ctx, o, dist):
     if dist == "uniform":
         eq2 = o.overflow_fraction(n, 256)
         assert abs(st["estimated_overflow"] / eq2 - 1) < 0.25, (st["estimated_overflow"], eq2)
+
+
+def test_segmented_device_offsets(torch, ctx, o):
+    """Offsets may live in device memory; the result is the same."""
+    lens = workloads.batch_lengths(200, 1, 30000, 9)
+    off = workloads.segment_offsets(lens)
+    n = int(off[-1])
+    k = workloads.make_keys("uniform", n, 32, 9)
+    v = workloads.index_payload(n)
+    say("segmented device offsets", n)
+    dk, dv = dev(torch, k), dev(torch, v)
+    doff = torch.from_numpy(off.astype(np.int64)).cuda()
+    ctx.sort_segmented_(dk, dv, doff)
+    torch.cuda.synchronize()
+    rk, rv = o.segmented_sort(k, v, off)
+    assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv)
