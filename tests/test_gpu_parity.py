@@ -391,3 +391,74 @@ def test_segmented_device_offsets(torch, ctx, o):
     torch.cuda.synchronize()
     rk, rv = o.segmented_sort(k, v, off)
     assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv)
+
+
+# --------------------------------------------------------------------------------------
+# Edge cases of the key range and of the local sort's capacity.
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("n", [3, 4097, (1 << 20) + 3])
+def test_keys_only_extremes(torch, ctx, o, bits, n):
+    dt = np.uint32 if bits == 32 else np.uint64
+    rng = np.random.default_rng(n)
+    k = np.where(rng.integers(0, 2, n) == 1, np.iinfo(dt).max, 0).astype(dt)
+    v = workloads.index_payload(n, bits)
+    say("extremes", bits, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_buckets_at_capacity(torch, ctx, o, kb):
+    """Top-digit buckets of exactly the local sort's capacity C, of C + 1 (then sorted by
+    the next level), of C - 1, and of one record."""
+    import paper_2207_14334_amd as dfr
+    cap = dfr.local_sort_capacity(kb, kb)
+    sizes = [cap, cap + 1, cap - 1, 1, cap, 2 * cap + 1]
+    bits = 8 * kb
+    dt = np.uint32 if kb == 4 else np.uint64
+    parts = []
+    for b, m in enumerate(sizes):
+        low = workloads.make_keys("uniform", m, bits, 100 + b) >> dt(8)
+        parts.append((dt(37 * b + 5) << dt(bits - 8)) | low)
+    k = np.concatenate(parts)
+    rng = np.random.default_rng(kb)
+    k = k[rng.permutation(k.size)]
+    v = workloads.index_payload(k.size, bits)
+    say("buckets at capacity", kb, k.size)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, force_top_digits=1, divert_records=cap)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+
+
+def test_size_limit(torch, ctx):
+    """More records than one segment may hold: refused before any work."""
+    import ctypes
+    import paper_2207_14334_amd as dfr
+    k = dev(torch, np.arange(16, dtype=np.uint32))
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    st = dfr.lib().dfr_sort_u32(ctx._h, k.data_ptr(), None, dfr.MAX_SEGMENT_RECORDS + 1, None, 0, s)
+    assert st == dfr.E_TOO_LARGE
+    # A misaligned key pointer.
+    assert dfr.lib().dfr_sort_u64(ctx._h, k.data_ptr() + 4, None, 2, None, 0, s) == dfr.E_INVALID_ARG
+    assert np.array_equal(host(k), np.arange(16, dtype=np.uint32))
+
+
+def test_lookback_determinism(torch, ctx, o):
+    """Decoupled look-back with half tiles (longer chains) over a grid far larger than
+    the resident blocks: repeats agree bit for bit and match the oracle."""
+    import paper_2207_14334_amd as dfr
+    n = (1 << 24) + 321
+    k = workloads.make_keys("uniform", n, 32, 44)
+    v = workloads.index_payload(n)
+    say("lookback determinism", n)
+    first = None
+    for _ in range(4):
+        sk, sv, _ = gpu_sort(torch, ctx, k, v, force_lookback=1,
+                             tile_records=dfr.deal_tile_records(4, 4) // 2)
+        if first is None:
+            first = (sk, sv)
+        assert np.array_equal(sk, first[0]) and np.array_equal(sv, first[1])
+    assert o.check_index_payload(k, first[0], first[1]) is None
