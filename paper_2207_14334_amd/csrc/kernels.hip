@@ -189,7 +189,10 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     constexpr int W = THREADS / 64;
     constexpr int SLICE = NDIG * RADIX;  // bins for up to NDIG digits
     constexpr int PER_VEC = 16 / KB;  // keys per 16-byte load
-    constexpr int VECS = 8;           // 16-byte loads in flight per thread
+#ifndef DFR_COUNT_VECS
+#define DFR_COUNT_VECS 8
+#endif
+    constexpr int VECS = DFR_COUNT_VECS;  // 16-byte loads in flight per thread
     __shared__ uint32_t s_h[W * SLICE];
     __shared__ uint32_t s_tot[SLICE];  // the block's counts for the current segment
     __shared__ K s_or[W];
@@ -353,7 +356,10 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     __shared__ K s_keys[T];
     __shared__ V s_vals[VB ? T : 1];
     __shared__ uint32_t s_wcnt[W * RADIX];
-    __shared__ uint64_t s_gdelta[RADIX];
+    // Per digit: the place of the tile's first record of that digit in the segment,
+    // minus that record's place in the staged tile (a record at staged index i of digit
+    // d goes to segment position s_delta[d] + i).
+    __shared__ int32_t s_delta[RADIX];
     __shared__ uint32_t s_local[RADIX];
     __shared__ uint32_t s_part[RADIX / 64];
     __shared__ uint32_t s_ticket;
@@ -445,7 +451,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
 
     if (!LOOKBACK && tid < RADIX) {
         s_local[tid] = loc_excl;
-        s_gdelta[tid] = seg_start + (uint64_t)a.off[(size_t)t * RADIX + tid] - (uint64_t)loc_excl;
+        s_delta[tid] = (int32_t)(a.off[(size_t)t * RADIX + tid] - loc_excl);
     }
     if (LOOKBACK && tid < RADIX) {
         s_local[tid] = loc_excl;
@@ -461,7 +467,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
             __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid], LB_PRE | (excl + tile_cnt),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_gdelta[tid] = seg_start + (uint64_t)seg_excl + (uint64_t)excl - (uint64_t)loc_excl;
+        s_delta[tid] = (int32_t)(seg_excl + excl - loc_excl);
     }
     __syncthreads();
 
@@ -480,19 +486,25 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     }
     __syncthreads();
 
-    // Runs of equal digits go to consecutive addresses of their bucket.
-    K* kout = (K*)a.kout;
-    V* vout = (V*)a.vout;
+    // Runs of equal digits go to consecutive addresses of their bucket.  Positions are
+    // 32-bit offsets into the segment (a segment holds fewer than 2^30 records).
+    K* kseg = (K*)a.kout + seg_start;
+    V* vseg = (V*)a.vout + seg_start;
+    const uint32_t seg_len = (uint32_t)(seg_end - seg_start);
     bool bad = false;
-    for (uint32_t i = tid; i < len; i += THREADS) {
-        const K kk = s_keys[i];
-        const uint32_t d = (uint32_t)(kk >> shift) & dmask;
-        const uint64_t p = s_gdelta[d] + i;
-        if (p >= seg_start && p < seg_end) {
-            kout[p] = kk;
-            if (VB) vout[p] = s_vals[i];
-        } else {
-            bad = true;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = (uint32_t)k * THREADS + tid;
+        if (i < len) {
+            const K kk = s_keys[i];
+            const uint32_t d = (uint32_t)(kk >> shift) & dmask;
+            const uint32_t p = (uint32_t)(s_delta[d] + (int32_t)i);
+            if (p < seg_len) {
+                kseg[p] = kk;
+                if (VB) vseg[p] = s_vals[i];
+            } else {
+                bad = true;
+            }
         }
     }
     if (bad) atomicOr(a.err, ERR_RANGE);
@@ -1472,7 +1484,10 @@ __global__ __launch_bounds__(256) void k_key_transform(void* keys, uint64_t n, i
 constexpr int DEAL_THREADS = DFR_DEAL_THREADS;
 constexpr int DEAL_TILE_SMALL = DFR_DEAL_TILE_SMALL;
 constexpr int DEAL_TILE_LARGE = DFR_DEAL_TILE_LARGE;
-constexpr int COUNT_THREADS = 256;
+#ifndef DFR_COUNT_THREADS
+#define DFR_COUNT_THREADS 256
+#endif
+constexpr int COUNT_THREADS = DFR_COUNT_THREADS;
 constexpr int LOCAL_THREADS = DFR_LOCAL_THREADS;
 constexpr int LOCAL_CAP_SMALL = DFR_LOCAL_CAP_SMALL;
 constexpr int LOCAL_CAP_LARGE = DFR_LOCAL_CAP_LARGE;
