@@ -11,9 +11,10 @@ Workloads (``--workload``):
 * ``serving`` -- a Poisson stream of sort requests (sizes log-uniform in
   [2^10, 2^24], 70% uint32 / 30% uint64 keys with a payload of the key's width,
   uniform or Zipf keys), offered at a load rho of the mean service time of one plain
-  call, served (a) by FIFO plain calls on one stream and (b) by the context's
-  request queue (dfr_submit / dfr_poll: continuous batching into segmented sorts)
-  under a 32 GiB HBM budget.  Latency is arrival to completion; p50/p99 for both.
+  call (0.3 to 0.9, and 1.2 and 1.5 beyond what plain calls can serve), served (a) by
+  FIFO plain calls on one stream and (b) by the context's request queue (dfr_submit /
+  dfr_poll: continuous batching into segmented sorts) under a 32 GiB HBM budget.
+  Latency is arrival to completion; p50/p99 and throughput for both.
 
 Plain workload: one step = one plain DFR sort (count, deals of the top digits, bucket finding, local
 sort of runs of small buckets, recursion if any) of 2^28 uint32 keys drawn i.i.d.
@@ -395,7 +396,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=("plain", "batched", "serving"), default="plain")
     ap.add_argument("--requests", type=int, default=2000)
-    ap.add_argument("--rho", type=float, nargs="+", default=[0.3, 0.5, 0.7, 0.9])
+    ap.add_argument("--rho", type=float, nargs="+", default=[0.3, 0.5, 0.7, 0.9, 1.2, 1.5])
     ap.add_argument("--budget-gib", type=int, default=32)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--dist", default="uniform")
