@@ -838,7 +838,7 @@ struct Words {
 template <typename WT, bool SEPPOS, int KB, int VB, int THREADS, int CAP, int IB, int DB, int MAXI>
 __device__ __forceinline__ bool bucket_sort_chunk(
     Words<MAXI> x, uint32_t len, uint32_t iu, uint32_t wbase, int lane, int w,
-    int tid, uint32_t nbk, int h, int B, typename uint_of<KB>::type key0,
+    int tid, uint32_t nbk, bool direct, int lo, int h, int B, typename uint_of<KB>::type key0,
     const typename uint_of<KB>::type* kin, const typename uint_of<VB>::type* vin,
     typename uint_of<KB>::type* kout, typename uint_of<VB>::type* vout, const uint32_t* s_rel,
     WT* s_w, uint16_t* s_pos, uint32_t* s_bin, uint32_t* s_part, uint32_t* s_max) {
@@ -856,7 +856,9 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     for (int k = 0; k < MAXI; ++k) {
         const uint32_t idx = wbase + k * 64 + lane;
         uint64_t bi = 0;
-        if (nbk > 1) {
+        if (direct) {
+            bi = (uint64_t)(((K)x.v[k] >> lo) - (key0 >> lo));
+        } else if (nbk > 1) {
             uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
             while (hi_i - lo_i > 1) {
                 const uint32_t mid = (lo_i + hi_i) >> 1;
@@ -871,7 +873,7 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     const uint32_t nbins = 1u << nbits;
     const int dshift = PB + B - nbits;
     const uint32_t nwords = nbins > 1 ? nbins / 2 : 1;
-    if (nbk > 1) __syncthreads();  // s_rel no longer needed
+    if (nbk > 1 && !direct) __syncthreads();  // s_rel no longer needed
     // Slots inside the bins.
     uint32_t slot[MAXI];
 #pragma unroll
@@ -944,7 +946,11 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     // that precedes the writes, since the output may be the input buffer itself.
     uint32_t pos[MAXI];  // destination in the low 16 bits, source above
     K ko[MAXI];
+    // Bits in [h, lo) are the chunk's constant ones; bits >= lo are the bucket's.
+    const uint64_t lowmask = lo >= 8 * KB ? ~0ull : (1ull << lo) - 1ull;
+    const uint64_t mid0 = (uint64_t)key0 & lowmask & ~mask_h;
     const uint64_t hi0 = (uint64_t)key0 & ~mask_h;
+    const uint64_t d0 = lo >= 8 * KB ? 0ull : (uint64_t)(key0 >> lo);
 #pragma unroll
     for (int k = 0; k < MAXI; ++k) {
         const uint32_t p = wbase + k * 64 + lane;
@@ -968,7 +974,9 @@ __device__ __forceinline__ bool bucket_sort_chunk(
                 src = (uint32_t)me & ((1u << IB) - 1u);
             }
             const uint32_t at = gs + r < len ? gs + r : len - 1;
-            const uint64_t hi = nbk > 1 ? ((uint64_t)kin[at] & ~mask_h) : hi0;
+            uint64_t hi = hi0;
+            if (direct) hi = mid0 | ((((uint64_t)me >> PB >> h) + d0) << lo);
+            else if (nbk > 1) hi = (uint64_t)kin[at] & ~mask_h;
             pos[k] = at | (src << 16);
             ko[k] = (K)((((uint64_t)me >> PB) & mask_h) | hi);
         }
@@ -1128,13 +1136,25 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOC
             __syncthreads();
             continue;
         }
-        if (nbk > 1) {
+        // Bucket index from the key itself: the buckets' bits >= lo, less the first
+        // bucket's.  Exact while the chunk's buckets span few more values than there
+        // are buckets (dense digits); otherwise it is found from the bucket starts.
+        bool direct = false;
+        int Bw = B;
+        if (nbk > 1 && lo < KBITS) {
+            const uint64_t span = (uint64_t)((kin[len - 1] >> lo) - (key0 >> lo));
+            const int sb = 64 - __clzll(span);
+            const int Bd = h + sb;
+            direct = sb <= bb + 1 && Bd + IB <= 64 && (FORM == 2 || Bd + (FORM == 0 ? IB : 0) <= 32);
+            if (direct) Bw = Bd;
+        }
+        if (nbk > 1 && !direct) {
             for (uint32_t i = tid; i < nbk; i += THREADS) s_rel[i] = (uint32_t)(a.bstart[ch.f + i] - start);
             __syncthreads();
         }
         using WT = typename uint_of<WB>::type;
         const bool ok = bucket_sort_chunk<WT, FORM == 1, KB, VB, THREADS, CAP, IB, DB, MAXI>(
-            xs, len, iu, wbase, lane, w, tid, nbk, h, B, key0, kin, vin, kout, vout, s_rel,
+            xs, len, iu, wbase, lane, w, tid, nbk, direct, lo, h, Bw, key0, kin, vin, kout, vout, s_rel,
             (WT*)s_w, s_pos, s_bin, s_part, s_max);
         if (!ok) spill(item);
     }

@@ -433,6 +433,28 @@ def test_buckets_at_capacity(torch, ctx, o, kb):
     assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
 
 
+@pytest.mark.parametrize("spacing", [1, 2, 3, 4, 16])
+@pytest.mark.parametrize("kb", [4, 8])
+def test_local_sort_bucket_spacing(torch, ctx, o, spacing, kb):
+    """Runs of small buckets whose top-16-bit values are spaced 1, 2, 3, 4 or 16 apart:
+    the local sort takes a bucket's index from the key itself while the chunk's buckets
+    span at most about twice as many values as there are buckets, and from the bucket
+    starts otherwise; both rebuild the bits above the sorted ones."""
+    bits = 8 * kb
+    dt = np.uint32 if kb == 4 else np.uint64
+    n = (1 << 20) + 7
+    rng = np.random.default_rng(1000 * kb + spacing)
+    top = (rng.integers(0, 4096, n) * spacing + 5).astype(dt)
+    low = workloads.make_keys("uniform", n, bits, spacing) >> dt(16)
+    k = (top << dt(bits - 16)) | low
+    v = workloads.index_payload(n, bits)
+    say("bucket spacing", spacing, kb, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, force_top_digits=2)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    assert st["levels"] == 1, st
+
+
 def test_size_limit(torch, ctx):
     """More records than one segment may hold: refused before any work."""
     import ctypes
