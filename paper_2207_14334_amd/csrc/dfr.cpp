@@ -91,6 +91,7 @@ struct dfr_ctx {
     int force_d = 0;
     int timing = 0;  // 1 every stage, 2 the deal launches only
     bool force_lookback = false;  // deal every level with decoupled look-back
+    bool force_key_heads = false;  // find bucket heads from the keys on every level
     int radix_bits = 0;           // 0 = tuned or default
     uint32_t tile_records = 0;
     size_t window = 0;
@@ -765,7 +766,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                           asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
                           2 * asize<Big>(bigcap) + 3 * asize<uint32_t>(nslots + medcap) +
-                          asize<uint32_t>(8);
+                          asize<uint32_t>(8) + asize<uint32_t>(1u << (2 * RADIX_BITS)) +
+                          asize<uint64_t>(RADIX);
     const uint32_t scan_tpb = 128;
     const uint32_t scan_nb = (uint32_t)((ntiles + scan_tpb - 1) / scan_tpb);
     const size_t need_nolb = nolb ? asize<uint32_t>(ntiles * RADIX) * 2 +
@@ -799,6 +801,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* wide = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work, wide
+    uint32_t* joint = aalloc<uint32_t>(c, 1u << (2 * RADIX_BITS));  // pair counts (heads from counts)
+    uint64_t* joint_rows = aalloc<uint64_t>(c, RADIX);
     st = same_tiles ? DFR_OK : upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
     if (!st && any_full) st = upload(j, dhtiles, htiles.data(), nht * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
@@ -917,20 +921,49 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
         HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
         HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
-        HeadArgs ha{};
-        ha.keys = j.k[cur];
-        ha.tiles = dhtiles;
-        ha.ntiles = (uint32_t)nht;
-        ha.segs = dsegs;
-        ha.tcount = htcount;
-        ha.tbase = htbase;
-        ha.tslot = htslot;
-        ha.bstart = dbstart;
-        ha.bseg = dbseg;
-        ha.bcap = bcap;
-        ha.nbuckets = counters;
-        ha.err = j.err_dev;
-        HIP_TRY(c, launch_heads(kb, ha, j.s));
+        // One segment dealt on two digits, bases scanned ahead: its buckets are the
+        // non-empty digit pairs, counted from the first digit's histogram and the second
+        // deal's per-tile counts, so the keys need not be read again.
+        const Seg& g0 = hs[active[0]];
+        const bool from_counts = single && !c->force_key_heads && d == 2 && g0.first_pass == 0 &&
+                                 g0.npass == 2 && g0.shift[0] != g0.shift[1] && !full[active[0]];
+        if (from_counts) {
+            JointArgs ja{};
+            ja.keys = j.k[1 - cur];  // the first deal's output, intact after the second
+            ja.seg_start = g0.start;
+            ja.seg_len = g0.len;
+            ja.h0 = dhist + ((size_t)active[0] * ndig + g0.hslot[0]) * RADIX;
+            ja.tcnt = tone;
+            ja.ntiles = (uint32_t)ntiles;
+            ja.tile = j.tile;
+            ja.shift1 = g0.shift[1];
+            ja.width0 = g0.width[0];
+            ja.width1 = g0.width[1];
+            ja.joint = joint;
+            ja.rows = joint_rows;
+            ja.bstart = dbstart;
+            ja.bseg = dbseg;
+            ja.seg = active[0];
+            ja.bcap = bcap;
+            ja.nbuckets = counters;
+            ja.err = j.err_dev;
+            HIP_TRY(c, launch_joint_heads(kb, ja, j.s));
+        } else {
+            HeadArgs ha{};
+            ha.keys = j.k[cur];
+            ha.tiles = dhtiles;
+            ha.ntiles = (uint32_t)nht;
+            ha.segs = dsegs;
+            ha.tcount = htcount;
+            ha.tbase = htbase;
+            ha.tslot = htslot;
+            ha.bstart = dbstart;
+            ha.bseg = dbseg;
+            ha.bcap = bcap;
+            ha.nbuckets = counters;
+            ha.err = j.err_dev;
+            HIP_TRY(c, launch_heads(kb, ha, j.s));
+        }
         ClassifyArgs ca{};
         ca.bstart = dbstart;
         ca.bseg = dbseg;
@@ -2153,6 +2186,10 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
     }
     if (!strcmp(name, "force_lookback")) {
         c->force_lookback = value != 0;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "force_key_heads")) {
+        c->force_key_heads = value != 0;
         return DFR_OK;
     }
     if (!strcmp(name, "serve_workers") || !strcmp(name, "serve_batch_records")) {

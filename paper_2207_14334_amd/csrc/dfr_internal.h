@@ -140,6 +140,29 @@ struct HeadArgs {
     uint32_t* err;
 };
 
+// Bucket heads of a one-segment level dealt on two digits, from counts rather than the
+// keys (see k_joint_counts).  u is the first deal's digit, v the second's.
+struct JointArgs {
+    const void* keys;       // the first deal's output (whole buffer)
+    uint64_t seg_start;
+    uint64_t seg_len;
+    const uint32_t* h0;     // the segment's histogram of u
+    const uint32_t* tcnt;   // the second deal's per-tile counts of v: tcnt[t * RADIX + v]
+    uint32_t ntiles;        // tiles of the second deal: [t * tile, min((t + 1) * tile, seg_len))
+    uint32_t tile;
+    int32_t shift1;         // v = (key >> shift1) mod 2^width1
+    int32_t width0;
+    int32_t width1;
+    uint32_t* joint;        // [2^width1][2^width0] record counts of each pair (v, u)
+    uint64_t* rows;         // [2^width1] records | non-empty pairs << 32, of each row v
+    uint64_t* bstart;
+    uint32_t* bseg;
+    uint32_t seg;           // the segment's index, written to bseg
+    uint64_t bcap;
+    uint32_t* nbuckets;
+    uint32_t* err;
+};
+
 struct ClassifyArgs {
     const uint64_t* bstart;
     const uint32_t* bseg;
@@ -227,6 +250,7 @@ hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, int
 hipError_t launch_key_transform(int kb, int mode, bool inverse, void* keys, size_t n,
                                 hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
+hipError_t launch_joint_heads(int kb, const JointArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 // Which form of the local sort runs first for chunks whose buckets agree on every bit
 // >= max_lo_bit: 0 and 1 use 32-bit words (with and without the position inside), 2

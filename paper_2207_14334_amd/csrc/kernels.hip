@@ -692,6 +692,150 @@ __global__ __launch_bounds__(256) void k_heads_emit(HeadArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
+// Bucket heads without reading the keys, for a one-segment level dealt on two digits
+// (the lower, u, then the upper, v).  The level's buckets are the non-empty pairs
+// (v, u), in that order, so their starts are an exclusive scan of the pair counts.
+// After the first deal the records of each u fill one known range (the u histogram's
+// prefix sum); the second deal's per-tile counts of v, summed over the tiles wholly
+// inside that range, plus a direct count of the records of the range in the (at most
+// two) tiles it shares with its neighbours, give the pair counts.
+//
+// k_joint_counts: one block per u; its four groups of RADIX threads sum a quarter of
+// the range's tiles each, eight tiles in flight, and share the key counting.
+// k_joint_rows: one block per v, the records and non-empty pairs of row v.
+// k_joint_emit: one block per v, the row's pairs scanned after the rows before it; the
+// non-empty ones are listed.
+// ---------------------------------------------------------------------------------
+constexpr int JOINT_GROUPS = 4;
+template <int KB>
+__global__ __launch_bounds__(JOINT_GROUPS * RADIX) void k_joint_counts(JointArgs a) {
+    using K = typename uint_of<KB>::type;
+    __shared__ uint32_t s_c[RADIX];
+    __shared__ uint32_t s_g[JOINT_GROUPS][RADIX];
+    __shared__ uint32_t s_sum[RADIX / 64];
+    const uint32_t u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t v = tid % RADIX, grp = tid / RADIX;
+    const uint32_t n0 = 1u << a.width0, n1 = 1u << a.width1;
+    // Start of u's range: the sum of the histogram below u.
+    if (tid < RADIX) {
+        uint32_t x = tid < u ? a.h0[tid] : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) s_sum[w] = x;
+        s_c[tid] = 0;
+    }
+    __syncthreads();
+    uint64_t lo = 0;
+#pragma unroll
+    for (int ww = 0; ww < RADIX / 64; ++ww) lo += s_sum[ww];
+    const uint64_t hi = lo + a.h0[u];
+    const uint64_t len = a.seg_len, T = a.tile;
+    uint32_t sum = 0;
+    if (hi > lo && hi <= len) {
+        // Tiles t with t*T >= lo and min((t+1)*T, len) <= hi.
+        const uint64_t t0 = (lo + T - 1) / T;
+        const uint64_t t1 = hi == len ? (uint64_t)a.ntiles : hi / T;
+        uint64_t p0 = lo, p1 = hi, q0 = hi, q1 = hi;  // ranges counted from the keys
+        if (t0 < t1) {
+            if (v < n1) {
+                constexpr int U = 8;
+                uint32_t acc[U] = {};
+                uint64_t t = t0 + grp;
+                for (; t + (U - 1) * JOINT_GROUPS < t1; t += U * JOINT_GROUPS) {
+#pragma unroll
+                    for (int r = 0; r < U; ++r) acc[r] += a.tcnt[(t + r * JOINT_GROUPS) * RADIX + v];
+                }
+                for (; t < t1; t += JOINT_GROUPS) acc[0] += a.tcnt[t * RADIX + v];
+#pragma unroll
+                for (int r = 0; r < U; ++r) sum += acc[r];
+            }
+            p1 = t0 * T;
+            q0 = t1 * T < len ? t1 * T : len;
+        }
+        const K* kp = (const K*)a.keys + a.seg_start;
+        const uint32_t m1 = n1 - 1;
+        for (uint64_t i = p0 + tid; i < p1; i += JOINT_GROUPS * RADIX)
+            atomicAdd(&s_c[(uint32_t)(kp[i] >> a.shift1) & m1], 1u);
+        for (uint64_t i = q0 + tid; i < q1; i += JOINT_GROUPS * RADIX)
+            atomicAdd(&s_c[(uint32_t)(kp[i] >> a.shift1) & m1], 1u);
+    } else if (hi > len) {
+        if (tid == 0) atomicOr(a.err, ERR_RANGE);
+    }
+    s_g[grp][v] = sum;
+    __syncthreads();
+    if (tid < n1) {
+        uint32_t c = s_c[tid];
+#pragma unroll
+        for (int g = 0; g < JOINT_GROUPS; ++g) c += s_g[g][tid];
+        a.joint[(size_t)tid * n0 + u] = c;
+    }
+}
+
+// Exclusive scan of 64-bit values over a block of RADIX threads; returns the exclusive
+// prefix and sets *total.
+__device__ __forceinline__ uint64_t scan256_excl64(uint64_t x, uint64_t* s_part, uint64_t* total) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint64_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(incl, o, 64);
+        if ((int)lane >= o) incl += y;
+    }
+    if (lane == 63) s_part[w] = incl;
+    __syncthreads();
+    uint64_t run = incl - x, tot = 0;
+#pragma unroll
+    for (uint32_t ww = 0; ww < RADIX / 64; ++ww) {
+        if (ww < w) run += s_part[ww];
+        tot += s_part[ww];
+    }
+    *total = tot;
+    return run;
+}
+
+// Records (low 32 bits) and non-empty pairs (high 32 bits) of one pair count.
+__device__ __forceinline__ uint64_t pair_word(uint32_t c) {
+    return (uint64_t)c | ((uint64_t)(c != 0) << 32);
+}
+
+__global__ __launch_bounds__(RADIX) void k_joint_rows(JointArgs a) {
+    __shared__ uint64_t s_part[RADIX / 64];
+    const uint32_t v = blockIdx.x, tid = threadIdx.x;
+    const uint32_t n0 = 1u << a.width0;
+    const uint64_t x = tid < n0 ? pair_word(a.joint[(size_t)v * n0 + tid]) : 0ull;
+    uint64_t total;
+    scan256_excl64(x, s_part, &total);
+    if (tid == 0) a.rows[v] = total;
+}
+
+__global__ __launch_bounds__(RADIX) void k_joint_emit(JointArgs a) {
+    __shared__ uint64_t s_part[RADIX / 64];
+    const uint32_t v = blockIdx.x, tid = threadIdx.x;
+    const uint32_t n0 = 1u << a.width0, n1 = 1u << a.width1;
+    uint64_t before;
+    scan256_excl64(tid < v ? a.rows[tid] : 0ull, s_part, &before);
+    __syncthreads();  // s_part is used again
+    const uint32_t c = tid < n0 ? a.joint[(size_t)v * n0 + tid] : 0u;
+    uint64_t total;
+    const uint64_t at = before + scan256_excl64(pair_word(c), s_part, &total);
+    if (c) {
+        const uint64_t idx = at >> 32;
+        if (idx < a.bcap) {
+            a.bstart[idx] = a.seg_start + (uint32_t)at;
+            a.bseg[idx] = a.seg;
+        } else {
+            atomicOr(a.err, ERR_BUCKET_CAP);
+        }
+    }
+    if (v == n1 - 1 && tid == 0) {
+        const uint64_t all = before + total;
+        *a.nbuckets = (uint32_t)(all >> 32);
+        // Every record of the segment is in exactly one pair.
+        if ((uint32_t)all != (uint32_t)a.seg_len) atomicOr(a.err, ERR_RANGE);
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // Classify buckets (Sec. 3: runs of small buckets are sorted in bulk, large buckets
 // recursively).  Window width = wsmall <= cap/2: the small buckets starting in one
 // window of a segment are contiguous (a bucket longer than wsmall is the last to start
@@ -1828,6 +1972,17 @@ hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, s, a);
         hipLaunchKernelGGL(k_heads_emit<8>, dim3(emit_blocks), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_joint_heads(int kb, const JointArgs& a, hipStream_t s) {
+    const uint32_t n0 = 1u << a.width0, n1 = 1u << a.width1;
+    if (kb == 4)
+        hipLaunchKernelGGL(k_joint_counts<4>, dim3(n0), dim3(JOINT_GROUPS * RADIX), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_joint_counts<8>, dim3(n0), dim3(JOINT_GROUPS * RADIX), 0, s, a);
+    hipLaunchKernelGGL(k_joint_rows, dim3(n1), dim3(RADIX), 0, s, a);
+    hipLaunchKernelGGL(k_joint_emit, dim3(n1), dim3(RADIX), 0, s, a);
     return hipGetLastError();
 }
 

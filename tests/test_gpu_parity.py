@@ -455,6 +455,45 @@ def test_local_sort_bucket_spacing(torch, ctx, o, spacing, kb):
     assert st["levels"] == 1, st
 
 
+HEADS_CASES = [
+    # (key bits, n, distribution, radix bits, forced top digits)
+    (32, 5, "uniform", 0, 2),
+    (32, 8191, "uniform", 0, 2),
+    (32, 8193, "uniform", 0, 2),
+    (32, (1 << 20) + 3, "uniform", 0, 2),
+    (32, (1 << 22) + 9, "uniform", 0, 0),
+    (32, (1 << 21) + 1, "normal", 0, 2),
+    (32, (1 << 21) + 1, "few", 0, 2),
+    (32, (1 << 21) + 1, "narrow", 0, 2),
+    (32, (1 << 20) + 11, "uniform", 6, 2),
+    (32, (1 << 20) + 11, "uniform", 7, 2),
+    (64, (1 << 20) + 5, "uniform", 0, 2),
+    (64, (1 << 20) + 5, "skewed", 0, 2),
+]
+
+
+@pytest.mark.parametrize("bits,n,dist,rb,d", HEADS_CASES,
+                         ids=[f"u{b}-{n}-{t}-rb{r}-d{d}" for b, n, t, r, d in HEADS_CASES])
+def test_heads_from_counts(torch, ctx, o, bits, n, dist, rb, d):
+    """A one-segment level dealt on two digits lists its buckets from the digit counts
+    (first digit's histogram, second deal's per-tile counts, and the keys of the tiles
+    that straddle a first-digit range); the same sort with the heads found from the keys
+    gives the same chunks and the same, stable result."""
+    k = workloads.make_keys(dist, n, bits, 77)
+    v = workloads.index_payload(n, bits)
+    opts = {"force_top_digits": d}
+    if rb:
+        opts["radix_bits"] = rb
+    say("heads from counts", bits, n, dist, rb, d)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, **opts)
+    say("heads from keys", bits, n, dist, rb, d)
+    fk, fv, ft = gpu_sort(torch, ctx, k, v, force_key_heads=1, **opts)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    assert np.array_equal(fk, rk) and np.array_equal(fv, rv), ft
+    assert st["chunks"] == ft["chunks"] and st["levels"] == ft["levels"], (st, ft)
+
+
 def test_size_limit(torch, ctx):
     """More records than one segment may hold: refused before any work."""
     import ctypes
