@@ -338,7 +338,11 @@ dfr_tune default_tune(int kb, int vb) {
     t.radix_bits = RADIX_BITS;
     t.tile_records = deal_tile_records(kb, vb);
     t.divert_records = default_divert(kb, vb);
-    t.window_records = local_cap(kb, vb) / 4;
+    // Windows of half the bucketed local sort's capacity (rounded down to a power of
+    // two): a window's chunk spans less than two windows, so it fits that kernel.
+    uint64_t w = 16;
+    while (2 * w <= local_bucket_capacity(kb, vb) / 2) w *= 2;
+    t.window_records = w;
     return t;
 }
 

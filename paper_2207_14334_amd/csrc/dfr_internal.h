@@ -231,7 +231,8 @@ struct CopyChunk {
 // Tile and capacity choices per (key bytes, value bytes).
 uint32_t deal_tile_records(int kb, int vb);  // the default tile
 bool deal_tile_supported(int kb, int vb, uint32_t tile);  // the default or half of it
-uint32_t local_sort_capacity(int kb, int vb);
+uint32_t local_sort_capacity(int kb, int vb);    // the general kernel's chunk capacity
+uint32_t local_bucket_capacity(int kb, int vb);  // the bucketed kernels' chunk capacity
 
 // Launchers (kernels.hip).  Each returns the launch's hipError_t.
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);

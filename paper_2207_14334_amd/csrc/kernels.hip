@@ -1677,6 +1677,9 @@ bool deal_tile_supported(int kb, int vb, uint32_t tile) {
 uint32_t local_sort_capacity(int kb, int vb) {
     return kb + vb <= 8 ? (uint32_t)LOCAL_CAP_SMALL : (uint32_t)LOCAL_CAP_LARGE;
 }
+uint32_t local_bucket_capacity(int kb, int vb) {
+    return kb + vb <= 8 ? (uint32_t)DFR_BUCKET_CAP_SMALL : (uint32_t)DFR_BUCKET_CAP_LARGE;
+}
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
@@ -2028,10 +2031,12 @@ static void local_kb_vb(const LocalArgs& a, uint32_t blocks, int first_form, hip
 int local_sort_first_form(int kb, int vb, int max_lo_bit) {
     // A chunk's sort bits are at most its lo_bit varying bits plus a few bits of bucket
     // index.  With room for the position as well, the 32-bit words carry it (form 0);
-    // else, up to 32 bits of lo_bit, the position goes beside them (form 1).
-    const int ib = (kb + vb <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE) <= 4096 ? 12 : 13;
+    // else, below 32 bits of lo_bit, the position goes beside them (form 1).  At 32 the
+    // bucket index of a run of buckets no longer fits, and every such chunk would be
+    // handed on to the 64-bit form after a wasted read.
+    const int ib = local_bucket_capacity(kb, vb) <= 4096 ? 12 : 13;
     if (max_lo_bit + ib <= 32) return 0;
-    return max_lo_bit <= 32 ? 1 : 2;
+    return max_lo_bit < 32 ? 1 : 2;
 }
 
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
