@@ -695,6 +695,7 @@ __global__ __launch_bounds__(256) void k_heads_emit(HeadArgs a) {
 // Bucket heads without reading the keys, for a one-segment level dealt on two digits
 // (the lower, u, then the upper, v).  The level's buckets are the non-empty pairs
 // (v, u), in that order, so their starts are an exclusive scan of the pair counts.
+// (A level dealt on one digit is the case of a single v: the counts are its histogram.)
 // After the first deal the records of each u fill one known range (the u histogram's
 // prefix sum); the second deal's per-tile counts of v, summed over the tiles wholly
 // inside that range, plus a direct count of the records of the range in the (at most
@@ -716,6 +717,10 @@ __global__ __launch_bounds__(JOINT_GROUPS * RADIX) void k_joint_counts(JointArgs
     const uint32_t u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t v = tid % RADIX, grp = tid / RADIX;
     const uint32_t n0 = 1u << a.width0, n1 = 1u << a.width1;
+    if (a.width1 == 0) {  // a level dealt on one digit: its buckets are the digit's values
+        if (tid == 0) a.joint[u] = a.h0[u];
+        return;
+    }
     // Start of u's range: the sum of the histogram below u.
     if (tid < RADIX) {
         uint32_t x = tid < u ? a.h0[tid] : 0u;

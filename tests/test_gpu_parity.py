@@ -469,6 +469,9 @@ HEADS_CASES = [
     (32, (1 << 20) + 11, "uniform", 7, 2),
     (64, (1 << 20) + 5, "uniform", 0, 2),
     (64, (1 << 20) + 5, "skewed", 0, 2),
+    (32, (1 << 21) + 1, "uniform", 0, 1),
+    (32, 70001, "uniform", 0, 1),
+    (64, (1 << 20) + 5, "skewed", 0, 0),
 ]
 
 
@@ -477,8 +480,9 @@ HEADS_CASES = [
 def test_heads_from_counts(torch, ctx, o, bits, n, dist, rb, d):
     """A one-segment level dealt on two digits lists its buckets from the digit counts
     (first digit's histogram, second deal's per-tile counts, and the keys of the tiles
-    that straddle a first-digit range); the same sort with the heads found from the keys
-    gives the same chunks and the same, stable result."""
+    that straddle a first-digit range), one dealt on one digit from its histogram; the
+    same sort with the heads found from the keys gives the same chunks and the same,
+    stable result."""
     k = workloads.make_keys(dist, n, bits, 77)
     v = workloads.index_payload(n, bits)
     opts = {"force_top_digits": d}
