@@ -105,6 +105,32 @@ def cpu_baseline(dist, log2n_sample=24, seeds=(0, 1, 2)):
     }
 
 
+def copy_ceiling(torch, gib=4, reps=5):
+    """The achievable HBM ceiling for comparison: a device-to-device copy of `gib` GiB
+    by the runtime (read + write bytes over the copy's time, median of `reps`)."""
+    import numpy as np
+    n = (gib << 30) // 4
+    src = torch.empty(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    t = float(np.median(ms))
+    gbs = 2 * (gib << 30) / (t * 1e-3) / 1e9
+    return {"bytes_copied": gib << 30, "ms": round(t, 4), "GB/s": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def check_segments(keys_in, keys_out, vals_out, off, segs):
     """check_result on the listed segments (payload = global index)."""
     for s in segs:
@@ -466,14 +492,17 @@ def run_plain(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = None
+    stamps = [t0]
     for i in range(args.warmup, copies):
-        ctx.sort_(ks[i], vs[i], temp)
+        ctx.sort_(ks[i], vs[i], temp)  # returns once the sort's last read-back is in
+        stamps.append(time.perf_counter())
         st = ctx.stats()
         for k in agg:
             agg[k] += st[k]
         plan = st
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = np.diff(np.array(stamps)) * 1e3
     ctx.set_option("timing", 0)
     # Per-stage kernel times from one more sort after the timed region (events around
     # every stage add gaps between kernels, so they stay out of the timed steps).
@@ -529,6 +558,7 @@ def run_plain(args):
     hbm_frac_sort = sort_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     cpu = None if args.no_cpu_baseline or kt != "u32" else cpu_baseline(args.dist)
+    ceiling = copy_ceiling(torch)
 
     out = {
         "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,
@@ -555,6 +585,10 @@ def run_plain(args):
                  "estimated_bucket_overflow": plan["estimated_overflow"] if plan else None},
         "stage_ms_one_sort": {k: round(v, 4) for k, v in stage.items() if k.startswith("ms_")},
         "cold_first_sort_ms": round(cold_ms, 3),
+        "step_ms": {"median": round(float(np.median(step_ms)), 4),
+                    "min": round(float(step_ms.min()), 4),
+                    "p90": round(float(np.percentile(step_ms, 90)), 4)},
+        "copy_ceiling": ceiling,
         "result_check": parity,
     }
     print(json.dumps(out), flush=True)
