@@ -433,6 +433,8 @@ def main():
     ap.add_argument("--set", action="append", default=[], metavar="OPTION=VALUE",
                     help="a library option (dfr_set_option) for the plain workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip the runtime copy timing (profiling runs calibrate on the input copies)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -558,7 +560,7 @@ def run_plain(args):
     hbm_frac_sort = sort_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     cpu = None if args.no_cpu_baseline or kt != "u32" else cpu_baseline(args.dist)
-    ceiling = copy_ceiling(torch)
+    ceiling = None if args.no_copy_ceiling else copy_ceiling(torch)
 
     out = {
         "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,

@@ -663,29 +663,47 @@ __global__ __launch_bounds__(256) void k_heads_emit(HeadArgs a) {
             }
             continue;
         }
+        // More heads than slots: find them again, U rows of 64 keys per step (the loads
+        // of a step issue together); a key's predecessor is the lane below, or the last
+        // key of the row before.
         const Seg* sg = a.segs + tl.seg;
         const int lo = sg->lo_bit;
         const K* kp = (const K*)a.keys + tl.start;
+        const bool seg_first = tl.start == sg->start;  // the tile opens its segment
+        K carry = seg_first ? K(0) : kp[-1];
         uint64_t run = base;
-        for (uint32_t i0 = 0; i0 < tl.len; i0 += 64) {
-            const uint32_t idx = i0 + lane;
-            const uint64_t gpos = tl.start + idx;
-            bool h = false;
-            if (idx < tl.len) {
-                if (gpos == sg->start) h = true;
-                else if (lo < KBITS) h = (kp[idx] >> lo) != (kp[(int64_t)idx - 1] >> lo);
+        constexpr int U = 8;
+        for (uint32_t i0 = 0; i0 < tl.len; i0 += 64 * U) {
+            K x[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint32_t idx = i0 + k * 64 + lane;
+                x[k] = idx < tl.len ? kp[idx] : K(0);
             }
-            const uint64_t hb = __ballot(h);
-            if (h) {
-                const uint64_t gi = run + lanes_below(hb);
-                if (gi < a.bcap) {
-                    a.bstart[gi] = gpos;
-                    a.bseg[gi] = tl.seg;
-                } else {
-                    over = true;
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint32_t idx = i0 + k * 64 + lane;
+                K prev = __shfl_up(x[k], 1, 64);
+                const K row_end = k > 0 ? __shfl(x[k > 0 ? k - 1 : 0], 63, 64) : carry;
+                if (lane == 0) prev = row_end;
+                bool h = false;
+                if (idx < tl.len) {
+                    if (idx == 0 && seg_first) h = true;
+                    else if (lo < KBITS) h = (x[k] >> lo) != (prev >> lo);
                 }
+                const uint64_t hb = __ballot(h);
+                if (h) {
+                    const uint64_t gi = run + lanes_below(hb);
+                    if (gi < a.bcap) {
+                        a.bstart[gi] = tl.start + idx;
+                        a.bseg[gi] = tl.seg;
+                    } else {
+                        over = true;
+                    }
+                }
+                run += (uint64_t)__popcll(hb);
             }
-            run += (uint64_t)__popcll(hb);
+            carry = __shfl(x[U - 1], 63, 64);
         }
     }
     if (over) atomicOr(a.err, ERR_BUCKET_CAP);
@@ -847,49 +865,93 @@ __global__ __launch_bounds__(RADIX) void k_joint_emit(JointArgs a) {
 // in its window) and span at most 2*wsmall records, so each window's run is one
 // local-sort chunk.
 // ---------------------------------------------------------------------------------
+// Appends one entry for every lane of the wave that wants to, with one atomic on the
+// list's counter; returns each such lane's index.  All lanes of the wave call it.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
+    const uint64_t m = __ballot(want);
+    uint32_t base = 0;
+    if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+        base = __shfl(base, leader, 64);
+    }
+    return base + lanes_below(m);
+}
+
+// Buckets of a segment are listed in position order, so a window's first and last small
+// bucket are found from the neighbours: a small bucket opens its window when the bucket
+// before lies in another segment or window, and closes it when the bucket after lies in
+// another segment or window or is not small.  (A bucket that is not small ends past its
+// own window, so every bucket before it in that window is small and none comes after.)
 __global__ void k_classify(ClassifyArgs a) {
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
     bool over = false;
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-         b += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t s = a.bseg[b];
-        const Seg* sg = a.segs + s;
-        const uint64_t start = a.bstart[b];
-        const uint64_t seg_end = sg->start + sg->len;
-        const uint64_t end = (b + 1 < nb && a.bseg[b + 1] == s) ? a.bstart[b + 1] : seg_end;
-        const uint64_t len = end - start;
-        if (len <= a.cap && (len > a.wsmall || sg->lo_bit >= a.kbits)) {
-            // Medium bucket, or a bucket with no prefix bits to tell it from its
-            // neighbours (a whole caller segment): a chunk of its own.
-            const uint32_t m = atomicAdd(a.nmed, 1u);
-            if (m < a.medcap) {
-                a.med[m] = (uint32_t)b;
-                const uint32_t wk = atomicAdd(a.nwork, 1u);
-                if (wk < a.workcap) a.work[wk] = a.nslots + m;
-                else over = true;
-            } else {
-                over = true;
-            }
-        } else if (len <= a.wsmall) {
-            const uint64_t slot = sg->window_base + (start - sg->start) / a.wsmall;
-            if (slot < a.nslots) {
-                // The first bucket to reach a window lists it as a work item.
-                if (atomicMin(&a.cfirst[slot], (uint32_t)b) == 0xffffffffu) {
-                    const uint32_t wk = atomicAdd(a.nwork, 1u);
-                    if (wk < a.workcap) a.work[wk] = (uint32_t)slot;
-                    else over = true;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < nb; b0 += stride) {
+        const uint64_t b = b0 + threadIdx.x;
+        int kind = 0;  // 1 medium, 2 small, 3 done, 4 large
+        uint64_t start = 0, len = 0, slot = 0;
+        bool first = false;
+        int lo_bit = 0;
+        if (b < nb) {
+            const uint32_t s = a.bseg[b];
+            const Seg* sg = a.segs + s;
+            start = a.bstart[b];
+            lo_bit = sg->lo_bit;
+            const uint64_t seg_end = sg->start + sg->len;
+            const bool next_same = b + 1 < nb && a.bseg[b + 1] == s;
+            const uint64_t end = next_same ? a.bstart[b + 1] : seg_end;
+            len = end - start;
+            if (len <= a.cap && (len > a.wsmall || lo_bit >= a.kbits)) {
+                // Medium bucket, or a bucket with no prefix bits to tell it from its
+                // neighbours (a whole caller segment): a chunk of its own.
+                kind = 1;
+            } else if (len <= a.wsmall) {
+                kind = 2;
+                slot = sg->window_base + (start - sg->start) / a.wsmall;
+                first = !(b > 0 && a.bseg[b - 1] == s &&
+                          sg->window_base + (a.bstart[b - 1] - sg->start) / a.wsmall == slot);
+                bool last = true;
+                if (next_same) {
+                    const uint64_t nend = (b + 2 < nb && a.bseg[b + 2] == s) ? a.bstart[b + 2] : seg_end;
+                    last = sg->window_base + (end - sg->start) / a.wsmall != slot || nend - end > a.wsmall;
                 }
-                atomicMax(&a.clast[slot], (uint32_t)b);
+                if (slot < a.nslots) {
+                    if (first) a.cfirst[slot] = (uint32_t)b;
+                    if (last) a.clast[slot] = (uint32_t)b;
+                } else {
+                    over = true;
+                    first = false;
+                }
+            } else {
+                kind = lo_bit == 0 ? 3 : 4;
+            }
+        }
+        const uint32_t mi = wave_append(a.nmed, kind == 1);
+        bool med = false;
+        if (kind == 1) {
+            if (mi < a.medcap) {
+                a.med[mi] = (uint32_t)b;
+                med = true;
             } else {
                 over = true;
             }
-        } else if (sg->lo_bit == 0) {
-            const uint32_t m = atomicAdd(a.ndone, 1u);
-            if (m < a.donecap) a.done[m] = Big{start, (uint32_t)len, 0u};
+        }
+        // Work items: each medium bucket, and each window once (from its first bucket).
+        const bool work = med || (kind == 2 && first);
+        const uint32_t wk = wave_append(a.nwork, work);
+        if (work) {
+            if (wk < a.workcap) a.work[wk] = med ? a.nslots + mi : (uint32_t)slot;
             else over = true;
-        } else {
-            const uint32_t m = atomicAdd(a.nbig, 1u);
-            if (m < a.bigcap) a.big[m] = Big{start, (uint32_t)len, (uint32_t)sg->lo_bit};
+        }
+        const uint32_t di = wave_append(a.ndone, kind == 3);
+        if (kind == 3) {
+            if (di < a.donecap) a.done[di] = Big{start, (uint32_t)len, 0u};
+            else over = true;
+        }
+        const uint32_t gi = wave_append(a.nbig, kind == 4);
+        if (kind == 4) {
+            if (gi < a.bigcap) a.big[gi] = Big{start, (uint32_t)len, (uint32_t)lo_bit};
             else over = true;
         }
     }
