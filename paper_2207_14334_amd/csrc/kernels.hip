@@ -883,11 +883,33 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
 // before lies in another segment or window, and closes it when the bucket after lies in
 // another segment or window or is not small.  (A bucket that is not small ends past its
 // own window, so every bucket before it in that window is small and none comes after.)
-__global__ void k_classify(ClassifyArgs a) {
+constexpr uint32_t CLASSIFY_THREADS = 256;
+constexpr uint32_t CLASSIFY_WBUF = 2048;  // work items a block gathers before listing them
+__global__ __launch_bounds__(CLASSIFY_THREADS) void k_classify(ClassifyArgs a) {
+    // Work items are gathered in LDS and listed with one atomic per CLASSIFY_WBUF of
+    // them: a level with many windows would otherwise queue on the list's one counter.
+    __shared__ uint32_t s_work[CLASSIFY_WBUF];
+    __shared__ uint32_t s_nw, s_base;
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
     bool over = false;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < nb; b0 += stride) {
+    if (threadIdx.x == 0) s_nw = 0;
+    __syncthreads();
+    auto flush = [&]() {  // every thread of the block
+        __syncthreads();
+        const uint32_t cnt = s_nw;
+        if (threadIdx.x == 0) s_base = cnt ? atomicAdd(a.nwork, cnt) : 0u;
+        __syncthreads();
+        const uint32_t base = s_base;
+        for (uint32_t i = threadIdx.x; i < cnt; i += CLASSIFY_THREADS) {
+            if ((uint64_t)base + i < a.workcap) a.work[base + i] = s_work[i];
+            else over = true;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_nw = 0;
+        __syncthreads();
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * CLASSIFY_THREADS;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * CLASSIFY_THREADS; b0 < nb; b0 += stride) {
         const uint64_t b = b0 + threadIdx.x;
         int kind = 0;  // 1 medium, 2 small, 3 done, 4 large
         uint64_t start = 0, len = 0, slot = 0;
@@ -939,11 +961,8 @@ __global__ void k_classify(ClassifyArgs a) {
         }
         // Work items: each medium bucket, and each window once (from its first bucket).
         const bool work = med || (kind == 2 && first);
-        const uint32_t wk = wave_append(a.nwork, work);
-        if (work) {
-            if (wk < a.workcap) a.work[wk] = med ? a.nslots + mi : (uint32_t)slot;
-            else over = true;
-        }
+        const uint32_t wp = wave_append(&s_nw, work);  // < CLASSIFY_WBUF: see the flush below
+        if (work) s_work[wp] = med ? a.nslots + mi : (uint32_t)slot;
         const uint32_t di = wave_append(a.ndone, kind == 3);
         if (kind == 3) {
             if (di < a.donecap) a.done[di] = Big{start, (uint32_t)len, 0u};
@@ -954,7 +973,13 @@ __global__ void k_classify(ClassifyArgs a) {
             if (gi < a.bigcap) a.big[gi] = Big{start, (uint32_t)len, (uint32_t)lo_bit};
             else over = true;
         }
+        // A step adds at most CLASSIFY_THREADS items: list them while that still fits.
+        __syncthreads();
+        const bool full = s_nw > CLASSIFY_WBUF - CLASSIFY_THREADS;
+        __syncthreads();  // every thread has read the count before the next step adds to it
+        if (full) flush();
     }
+    flush();
     if (over) atomicOr(a.err, ERR_LIST_CAP);
 }
 
@@ -2058,7 +2083,7 @@ hipError_t launch_joint_heads(int kb, const JointArgs& a, hipStream_t s) {
 
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s) {
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(CLASSIFY_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
