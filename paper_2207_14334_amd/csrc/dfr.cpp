@@ -620,20 +620,19 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         Timed tm(c, j.s, ST_COUNT);
         HIP_TRY(c, launch_collisions(dhist, (uint32_t)S, ndig, rb, dcoll, dnz, dovf, j.s));
     }
-    const size_t readback = S * 2 * sizeof(uint64_t) + S * ndig * (sizeof(double) + 8) + 512;
-    st = pin_reserve(c, readback, j.s);
+    // Collision estimates, non-empty bins, overflow, OR and AND lie next to each other in
+    // the arena: one copy brings them all back.
+    const size_t readback = off_and + asize<uint64_t>(S) - off_coll;
+    st = pin_reserve(c, readback + ALIGN, j.s);
     if (st) return st;
-    uint64_t* h_or = palloc<uint64_t>(c, S);
-    uint64_t* h_and = palloc<uint64_t>(c, S);
-    double* h_coll = palloc<double>(c, S * ndig);
-    uint32_t* h_nz = palloc<uint32_t>(c, S * ndig);
-    uint32_t* h_ovf = palloc<uint32_t>(c, S * ndig);
-    HIP_TRY(c, hipMemcpyAsync(h_or, dor, S * 8, hipMemcpyDeviceToHost, j.s));
-    HIP_TRY(c, hipMemcpyAsync(h_and, dand, S * 8, hipMemcpyDeviceToHost, j.s));
-    HIP_TRY(c, hipMemcpyAsync(h_coll, dcoll, S * ndig * sizeof(double), hipMemcpyDeviceToHost, j.s));
-    HIP_TRY(c, hipMemcpyAsync(h_nz, dnz, S * ndig * 4, hipMemcpyDeviceToHost, j.s));
-    HIP_TRY(c, hipMemcpyAsync(h_ovf, dovf, S * ndig * 4, hipMemcpyDeviceToHost, j.s));
+    char* h_rb = palloc<char>(c, readback);
+    HIP_TRY(c, hipMemcpyAsync(h_rb, c->arena + off_coll, readback, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipStreamSynchronize(j.s));
+    const double* h_coll = (const double*)h_rb;
+    const uint32_t* h_nz = (const uint32_t*)(h_rb + (off_nz - off_coll));
+    const uint32_t* h_ovf = (const uint32_t*)(h_rb + (off_ovf - off_coll));
+    const uint64_t* h_or = (const uint64_t*)(h_rb + (off_or - off_coll));
+    const uint64_t* h_and = (const uint64_t*)(h_rb + (off_and - off_coll));
     std::vector<uint64_t> vor(S), vand(S);
     for (size_t i = 0; i < S; ++i) {
         if (kb == 4) {
