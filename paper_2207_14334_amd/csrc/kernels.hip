@@ -340,11 +340,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
 // ---------------------------------------------------------------------------------
 // Per-tile counts of a deal's digit from the byte the previous deal wrote beside each
 // record (its digit for this pass), instead of from the keys: a quarter or an eighth of
-// the bytes.  One tile per step of a block; private LDS bins per wave.  Where more than
-// a quarter of a wave's lanes share lane 0's first byte (a skewed digit), each byte is
-// added per group of equal lanes, as in k_count: the lanes sharing the first active
-// lane's value, then those sharing the next remaining lane's, add their number in one
-// atomic; the rest one atomic each.
+// the bytes.  One tile per step of a block; private LDS bins per wave.
 // ---------------------------------------------------------------------------------
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_count_bytes(CountArgs a) {
@@ -368,37 +364,13 @@ __global__ __launch_bounds__(THREADS) void k_count_bytes(CountArgs a) {
         for (uint32_t i = tid; i < head; i += THREADS) atomicAdd(&hw[bp[i]], 1u);
         for (uint32_t i = tail + tid; i < tl.len; i += THREADS) atomicAdd(&hw[bp[i]], 1u);
         const uint4* vp = (const uint4*)(bp + head);
-        for (uint32_t v0 = 0; v0 < nvec; v0 += THREADS) {
-            const uint32_t v = v0 + tid;
-            const bool ok = v < nvec;
-            const uint4 q = ok ? vp[v] : make_uint4(0, 0, 0, 0);
-            const uint32_t first = __builtin_amdgcn_readfirstlane(q.x & 0xffu);
-            const bool skew = __popcll(__ballot(ok && (q.x & 0xffu) == first)) > 16;
+        for (uint32_t v = tid; v < nvec; v += THREADS) {
+            const uint4 q = vp[v];
             const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
-            if (!ok) continue;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const uint32_t d = (wd[c] >> (8 * b)) & 0xffu;
-                    if (!skew) {
-                        atomicAdd(&hw[d], 1u);
-                        continue;
-                    }
-                    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                    const uint64_t m0 = __ballot(d == d0);
-                    if (d == d0) {
-                        if (lanes_below(m0) == 0) atomicAdd(&hw[d0], (uint32_t)__popcll(m0));
-                    } else {
-                        const uint32_t d1 = __builtin_amdgcn_readfirstlane(d);
-                        const uint64_t m1 = __ballot(d == d1);
-                        if (d == d1) {
-                            if (lanes_below(m1) == 0) atomicAdd(&hw[d1], (uint32_t)__popcll(m1));
-                        } else {
-                            atomicAdd(&hw[d], 1u);
-                        }
-                    }
-                }
+                for (int b = 0; b < 4; ++b) atomicAdd(&hw[(wd[c] >> (8 * b)) & 0xffu], 1u);
         }
         __syncthreads();
         for (int idx = tid; idx < RADIX; idx += THREADS) {
