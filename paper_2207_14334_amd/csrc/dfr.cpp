@@ -776,13 +776,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     const size_t need_nolb = nolb ? asize<uint32_t>(ntiles * RADIX) * 2 +
                                         (single || perseg ? asize<uint32_t>((size_t)scan_nb * RADIX) : 0)
                                   : 0;
-    // One segment dealt three times or more: each deal also writes the next deal's
-    // digit of every record beside it, and the next deal's per-tile counts read those
-    // bytes instead of the keys.  (The bytes cost a deal about what they save the count;
-    // with two deals the gain is 1% of the sort, at 0.1 ms more on the first deal.)
-    const bool use_side = single && d >= 3;
-    const size_t need_side = use_side ? asize<uint8_t>(segs[active[0]].len) : 0;
-    st = arena_need(c, need_b + need_nolb + need_side, j.s);  // keeps region A
+    st = arena_need(c, need_b + need_nolb, j.s);  // keeps region A
     if (st) return st;
     dhist = (uint32_t*)(c->arena + off_hist);
     uint32_t* tcnt = (uint32_t*)(c->arena + off_tcnt);
@@ -812,7 +806,6 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work, wide
     uint32_t* joint = aalloc<uint32_t>(c, 1u << (2 * RADIX_BITS));  // pair counts (heads from counts)
     uint64_t* joint_rows = aalloc<uint64_t>(c, RADIX);
-    uint8_t* side = use_side ? aalloc<uint8_t>(c, segs[active[0]].len) : nullptr;
     st = same_tiles ? DFR_OK : upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
     if (!st && any_full) st = upload(j, dhtiles, htiles.data(), nht * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
@@ -838,13 +831,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ca.segs = single ? nullptr : dsegs;  // several segments: each its own digit
             ca.pass = p;
             const uint32_t grid = (ntp + ca.tiles_per_block - 1) / ca.tiles_per_block;
-            if (use_side) {
-                ca.keys = side;
-                ca.start_offset = hs[active[0]].start;
-                HIP_TRY(c, launch_count_bytes(ca, grid, j.s));
-            } else {
-                HIP_TRY(c, launch_count(kb, ca, grid, j.s));
-            }
+            HIP_TRY(c, launch_count(kb, ca, grid, j.s));
         }
         if (single) {
             const Seg& g = hs[active[0]];
@@ -915,7 +902,6 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         da.lookback = lb;
         da.ticket = lb + ntiles * RADIX;
         da.err = j.err_dev;
-        da.side = use_side && p + 1 < d ? side : nullptr;
         HIP_TRY(c, launch_deal(kb, j.vb, da, j.s));
         cur = 1 - cur;
         c->stats.deal_passes += 1;

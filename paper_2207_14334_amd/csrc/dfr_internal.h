@@ -74,7 +74,6 @@ struct CountArgs {
     uint32_t* tile_hist; // optional [tile][ndig][RADIX]: each tile's own counts
     const Seg* segs;     // optional: digit shift per tile from segs[seg].shift[pass]
     int32_t pass;
-    uint64_t start_offset;  // launch_count_bytes: record index of the byte at keys[0]
 };
 
 // Per-tile bucket bases for many segments: one block per segment walks its tiles.
@@ -120,8 +119,6 @@ struct DealArgs {
     const uint32_t* off; // when set: per-tile bucket bases, and no look-back
     uint32_t tile;       // records per tile (selects the kernel; see deal_tile_supported)
     uint32_t* err;
-    uint8_t* side;       // optional, one-segment levels: the next pass's digit of each
-                         // record, at its output place relative to the segment start
 };
 
 // Bucket heads per tile, at most HEAD_SLOTS of them kept per tile as tile-relative
@@ -241,9 +238,6 @@ uint32_t local_bucket_capacity(int kb, int vb);  // the bucketed kernels' chunk 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s);
-// Per-tile histograms of one byte per record (a.keys holds the bytes; a.tile_hist the
-// result, one digit per tile).
-hipError_t launch_count_bytes(const CountArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
 hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s);
 hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s);

@@ -338,55 +338,6 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
-// Per-tile counts of a deal's digit from the byte the previous deal wrote beside each
-// record (its digit for this pass), instead of from the keys: a quarter or an eighth of
-// the bytes.  One tile per step of a block; private LDS bins per wave.
-// ---------------------------------------------------------------------------------
-template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_count_bytes(CountArgs a) {
-    constexpr int W = THREADS / 64;
-    __shared__ uint32_t s_h[W * RADIX];
-    const int tid = threadIdx.x, w = tid >> 6;
-    uint32_t* hw = s_h + w * RADIX;
-    const uint32_t t0 = blockIdx.x * a.tiles_per_block;
-    if (t0 >= a.ntiles) return;
-    const uint32_t t1 = a.ntiles - t0 < a.tiles_per_block ? a.ntiles : t0 + a.tiles_per_block;
-    for (int i = tid; i < W * RADIX; i += THREADS) s_h[i] = 0;
-    __syncthreads();
-    for (uint32_t t = t0; t < t1; ++t) {
-        const Tile tl = a.tiles[t];
-        const uint8_t* bp = (const uint8_t*)a.keys + (tl.start - a.start_offset);
-        // Unaligned head, 16-byte body, tail.
-        uint32_t head = (uint32_t)((16u - ((uintptr_t)bp & 15u)) & 15u);
-        if (head > tl.len) head = tl.len;
-        const uint32_t nvec = (tl.len - head) / 16;
-        const uint32_t tail = head + nvec * 16;
-        for (uint32_t i = tid; i < head; i += THREADS) atomicAdd(&hw[bp[i]], 1u);
-        for (uint32_t i = tail + tid; i < tl.len; i += THREADS) atomicAdd(&hw[bp[i]], 1u);
-        const uint4* vp = (const uint4*)(bp + head);
-        for (uint32_t v = tid; v < nvec; v += THREADS) {
-            const uint4 q = vp[v];
-            const uint32_t wd[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) atomicAdd(&hw[(wd[c] >> (8 * b)) & 0xffu], 1u);
-        }
-        __syncthreads();
-        for (int idx = tid; idx < RADIX; idx += THREADS) {
-            uint32_t sum = 0;
-#pragma unroll
-            for (int ww = 0; ww < W; ++ww) {
-                sum += s_h[ww * RADIX + idx];
-                s_h[ww * RADIX + idx] = 0;
-            }
-            a.tile_hist[(size_t)t * RADIX + idx] = sum;
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------------
 // Deal (Sec. 2; one pass of the LSD phase of Sec. 3).  One tile per block, tiles in
 // ticket order so every tile it waits on is already running.
 //
@@ -540,10 +491,6 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     K* kseg = (K*)a.kout + seg_start;
     V* vseg = (V*)a.vout + seg_start;
     const uint32_t seg_len = (uint32_t)(seg_end - seg_start);
-    // The next pass's digit, when the caller keeps it beside the records.
-    uint8_t* side = a.side;
-    const int nshift = a.side ? sg->shift[a.pass + 1] : 0;
-    const uint32_t nmask = a.side ? (1u << sg->width[a.pass + 1]) - 1u : 0u;
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
@@ -555,7 +502,6 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
             if (p < seg_len) {
                 kseg[p] = kk;
                 if (VB) vseg[p] = s_vals[i];
-                if (side) side[p] = (uint8_t)((uint32_t)(kk >> nshift) & nmask);
             } else {
                 bad = true;
             }
@@ -1848,12 +1794,6 @@ static void count_kb(const CountArgs& a, uint32_t blocks, hipStream_t s) {
         hipLaunchKernelGGL((k_count<KB, COUNT_THREADS, 4>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL((k_count<KB, COUNT_THREADS, 8>), dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
-}
-
-hipError_t launch_count_bytes(const CountArgs& a, uint32_t blocks, hipStream_t s) {
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_bytes<COUNT_THREADS>, dim3(blocks), dim3(COUNT_THREADS), 0, s, a);
-    return hipGetLastError();
 }
 
 hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s) {
