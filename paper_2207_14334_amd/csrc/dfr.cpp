@@ -395,6 +395,7 @@ struct Job {
     int rb = RADIX_BITS;  // digit width of the deal passes
     size_t cap;     // local sort capacity
     size_t wsmall;  // small bucket limit = window width
+    bool window_default = false;  // wsmall is the default, not an option or a tuning
     size_t divert;
     bool first_level = true;
     int top_d_forced = 0;
@@ -715,6 +716,20 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     for (size_t i = 0; same_tiles && i < S; ++i) same_tiles = active[i] == i;
     if (!same_tiles) build_tiles(segs, active, j.tile, tiles, first_tile);
     std::vector<uint32_t> pass_tiles(d, 0);  // tiles dealt in pass p
+    // Window width of this level.  By default, where every dealt segment's buckets
+    // average 512 records or more, windows of half the bucketed local sort's capacity
+    // (a chunk spans less than two windows, so it still fits): fuller chunks, while a
+    // chunk's buckets stay few enough for their index to fit beside the sort bits.
+    size_t wsmall = j.wsmall;
+    if (j.window_default) {
+        const size_t half = local_bucket_capacity(kb, j.vb) / 2;
+        bool large = true;
+        for (uint32_t i : active) {
+            const int bits = rb * dsel[i];
+            large = large && bits < 64 && (segs[i].len >> bits) >= 512;
+        }
+        if (large && half > wsmall) wsmall = half;
+    }
     for (uint32_t i : active) {
         const uint64_t nt = (segs[i].len + j.tile - 1) / j.tile;
         for (int p = skip_of(i); p < d; ++p) pass_tiles[p] += (uint32_t)nt;
@@ -743,8 +758,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         if (!full[i]) {
             all_full = false;
             g.window_base = (uint32_t)nslots;
-            nslots += (segs[i].len + j.wsmall - 1) / j.wsmall;
-            medcap += segs[i].len / (j.wsmall + 1);
+            nslots += (segs[i].len + wsmall - 1) / wsmall;
+            medcap += segs[i].len / (wsmall + 1);
             bigcap += segs[i].len / (j.cap + 1);
             const uint64_t maxb = rb * di >= 64 ? ~0ull : (1ull << (rb * di));
             bcap += std::min<uint64_t>(segs[i].len, maxb);
@@ -976,7 +991,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ca.nbuckets = counters;
         ca.bcap = bcap;
         ca.segs = dsegs;
-        ca.wsmall = (uint32_t)j.wsmall;
+        ca.wsmall = (uint32_t)wsmall;
         ca.cap = (uint32_t)j.cap;
         ca.kbits = 8 * kb;
         ca.cfirst = cfirst;
@@ -1102,6 +1117,8 @@ dfr_status run_sort(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const st
     j.tile = t.tile_records;
     j.rb = t.radix_bits;
     j.wsmall = t.window_records;
+    j.window_default = !forced && !c->window &&
+                       c->tunes.find(tune_key(kb, vb, size_class(segs0))) == c->tunes.end();
     j.divert = t.divert_records;
     j.top_d_forced = c->force_d;
     uint64_t n = 0;

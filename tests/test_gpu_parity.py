@@ -498,6 +498,21 @@ def test_heads_from_counts(torch, ctx, o, bits, n, dist, rb, d):
     assert st["chunks"] == ft["chunks"] and st["levels"] == ft["levels"], (st, ft)
 
 
+@pytest.mark.parametrize("n,dist", [((1 << 25) + 77, "uniform"), ((1 << 26) + 3, "normal")])
+def test_wide_default_windows(torch, ctx, o, n, dist):
+    """Levels whose buckets average 512 records or more take windows of half the bucketed
+    local sort's capacity by default; checked by the properties that single out the
+    stable sort under the index payload, and the rank formula at sampled places."""
+    k = workloads.make_keys(dist, n, 32, 91)
+    v = workloads.index_payload(n)
+    say("wide default windows", n, dist)
+    sk, sv, st = gpu_sort(torch, ctx, k, v)
+    assert o.check_index_payload(k, sk, sv) is None, st
+    rng = np.random.default_rng(n)
+    for p in rng.integers(0, n, size=3):
+        assert o.rank_of(k, int(sv[p])) == int(p), (dist, int(p))
+
+
 def test_size_limit(torch, ctx):
     """More records than one segment may hold: refused before any work."""
     import ctypes
