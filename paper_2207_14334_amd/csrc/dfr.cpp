@@ -785,7 +785,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
                           2 * asize<Big>(bigcap) + 3 * asize<uint32_t>(nslots + medcap) +
                           asize<uint32_t>(8) + asize<uint32_t>(1u << (2 * RADIX_BITS)) +
-                          asize<uint64_t>(RADIX);
+                          asize<uint64_t>(RADIX) + 2 * asize<uint32_t>(S);
     const uint32_t scan_tpb = 128;
     const uint32_t scan_nb = (uint32_t)((ntiles + scan_tpb - 1) / scan_tpb);
     const size_t need_nolb = nolb ? asize<uint32_t>(ntiles * RADIX) * 2 +
@@ -821,6 +821,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work, wide
     uint32_t* joint = aalloc<uint32_t>(c, 1u << (2 * RADIX_BITS));  // pair counts (heads from counts)
     uint64_t* joint_rows = aalloc<uint64_t>(c, RADIX);
+    uint32_t* hh_ids = aalloc<uint32_t>(c, S);    // heads from histograms: segments,
+    uint32_t* hh_first = aalloc<uint32_t>(c, S);  // and each one's first list index
     st = same_tiles ? DFR_OK : upload(j, dtiles, tiles.data(), ntiles * sizeof(Tile));
     if (!st && any_full) st = upload(j, dhtiles, htiles.data(), nht * sizeof(Tile));
     if (!st) st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
@@ -969,6 +971,27 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ja.nbuckets = counters;
             ja.err = j.err_dev;
             HIP_TRY(c, launch_joint_heads(kb, ja, j.s));
+        } else if (!c->force_key_heads && d == 1) {
+            // Every segment dealt on one digit: its buckets are that digit's non-empty
+            // values, from its histogram.
+            std::vector<uint32_t> ids;
+            for (uint32_t i : active)
+                if (!full[i]) ids.push_back(i);
+            st = upload(j, hh_ids, ids.data(), ids.size() * sizeof(uint32_t));
+            if (st) return st;
+            HistHeadArgs ha{};
+            ha.segs = dsegs;
+            ha.ids = hh_ids;
+            ha.nids = (uint32_t)ids.size();
+            ha.hist = dhist;
+            ha.hist_digits = ndig;
+            ha.first = hh_first;
+            ha.bstart = dbstart;
+            ha.bseg = dbseg;
+            ha.bcap = bcap;
+            ha.nbuckets = counters;
+            ha.err = j.err_dev;
+            HIP_TRY(c, launch_hist_heads(ha, j.s));
         } else {
             HeadArgs ha{};
             ha.keys = j.k[cur];

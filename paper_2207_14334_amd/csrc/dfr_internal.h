@@ -163,6 +163,22 @@ struct JointArgs {
     uint32_t* err;
 };
 
+// Bucket heads of a level whose segments are all dealt on one digit: each segment's
+// buckets are the non-empty values of that digit, from its histogram.
+struct HistHeadArgs {
+    const Seg* segs;
+    const uint32_t* ids;    // the segments that need buckets, in list order
+    uint32_t nids;
+    const uint32_t* hist;   // per-segment digit histograms [seg][hist_digits][RADIX]
+    int32_t hist_digits;
+    uint32_t* first;        // [nids]: non-empty values, then each segment's first list index
+    uint64_t* bstart;
+    uint32_t* bseg;
+    uint64_t bcap;
+    uint32_t* nbuckets;
+    uint32_t* err;
+};
+
 struct ClassifyArgs {
     const uint64_t* bstart;
     const uint32_t* bseg;
@@ -252,6 +268,7 @@ hipError_t launch_key_transform(int kb, int mode, bool inverse, void* keys, size
                                 hipStream_t s);
 hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s);
 hipError_t launch_joint_heads(int kb, const JointArgs& a, hipStream_t s);
+hipError_t launch_hist_heads(const HistHeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 // Which form of the local sort runs first for chunks whose buckets agree on every bit
 // >= max_lo_bit: 0 and 1 use 32-bit words (with and without the position inside), 2

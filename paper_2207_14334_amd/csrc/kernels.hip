@@ -859,6 +859,84 @@ __global__ __launch_bounds__(RADIX) void k_joint_emit(JointArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
+// Bucket heads of a level whose segments are all dealt on one digit, from the digit's
+// histogram of each segment (no read of the keys): one block per segment counts its
+// non-empty values, one block scans those counts into each segment's first list index,
+// and one block per segment lists its buckets (exclusive scan of the histogram).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t hist_value(const HistHeadArgs& a, uint32_t s, const Seg& sg,
+                                               uint32_t v) {
+    const uint32_t n0 = 1u << sg.width[0];
+    return v < n0 ? a.hist[((size_t)s * a.hist_digits + sg.hslot[0]) * RADIX + v] : 0u;
+}
+
+__global__ __launch_bounds__(RADIX) void k_hist_heads_count(HistHeadArgs a) {
+    __shared__ uint32_t s_n[RADIX / 64];
+    const uint32_t i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t s = a.ids[i];
+    const Seg sg = a.segs[s];
+    const uint64_t m = __ballot(hist_value(a, s, sg, tid) != 0);
+    if (lane == 0) s_n[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t n = 0;
+        for (int ww = 0; ww < RADIX / 64; ++ww) n += s_n[ww];
+        a.first[i] = n;
+    }
+}
+
+constexpr int HIST_SCAN_THREADS = 1024;
+__global__ __launch_bounds__(HIST_SCAN_THREADS) void k_hist_heads_scan(HistHeadArgs a) {
+    __shared__ uint32_t s_part[HIST_SCAN_THREADS / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t per = (a.nids + HIST_SCAN_THREADS - 1) / HIST_SCAN_THREADS;
+    const uint32_t i0 = tid * per < a.nids ? tid * per : a.nids;
+    const uint32_t i1 = i0 + per < a.nids ? i0 + per : a.nids;
+    uint32_t mine = 0;
+    for (uint32_t i = i0; i < i1; ++i) mine += a.first[i];
+    uint32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if ((int)lane >= o) incl += y;
+    }
+    if (lane == 63) s_part[w] = incl;
+    __syncthreads();
+    uint32_t run = incl - mine, total = 0;
+    for (uint32_t ww = 0; ww < HIST_SCAN_THREADS / 64; ++ww) {
+        if (ww < w) run += s_part[ww];
+        total += s_part[ww];
+    }
+    for (uint32_t i = i0; i < i1; ++i) {
+        const uint32_t c = a.first[i];
+        a.first[i] = run;
+        run += c;
+    }
+    if (tid == 0) *a.nbuckets = total;
+}
+
+__global__ __launch_bounds__(RADIX) void k_hist_heads_emit(HistHeadArgs a) {
+    __shared__ uint64_t s_part[RADIX / 64];
+    const uint32_t i = blockIdx.x, tid = threadIdx.x;
+    const uint32_t s = a.ids[i];
+    const Seg sg = a.segs[s];
+    const uint32_t c = hist_value(a, s, sg, tid);
+    uint64_t total;
+    const uint64_t at = scan256_excl64(pair_word(c), s_part, &total);
+    if (c) {
+        const uint64_t idx = (uint64_t)a.first[i] + (at >> 32);
+        if (idx < a.bcap) {
+            a.bstart[idx] = sg.start + (uint32_t)at;
+            a.bseg[idx] = s;
+        } else {
+            atomicOr(a.err, ERR_BUCKET_CAP);
+        }
+    }
+    // Every record of the segment has one value of the digit.
+    if (tid == 0 && (uint32_t)total != (uint32_t)sg.len) atomicOr(a.err, ERR_RANGE);
+}
+
+// ---------------------------------------------------------------------------------
 // Classify buckets (Sec. 3: runs of small buckets are sorted in bulk, large buckets
 // recursively).  Window width = wsmall <= cap/2: the small buckets starting in one
 // window of a segment are contiguous (a bucket longer than wsmall is the last to start
@@ -2067,6 +2145,14 @@ hipError_t launch_heads(int kb, const HeadArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_heads_scan, dim3(1), dim3(1024), 0, s, a);
         hipLaunchKernelGGL(k_heads_emit<8>, dim3(emit_blocks), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_heads(const HistHeadArgs& a, hipStream_t s) {
+    if (a.nids == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist_heads_count, dim3(a.nids), dim3(RADIX), 0, s, a);
+    hipLaunchKernelGGL(k_hist_heads_scan, dim3(1), dim3(HIST_SCAN_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_hist_heads_emit, dim3(a.nids), dim3(RADIX), 0, s, a);
     return hipGetLastError();
 }
 

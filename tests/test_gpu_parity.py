@@ -513,6 +513,35 @@ def test_wide_default_windows(torch, ctx, o, n, dist):
         assert o.rank_of(k, int(sv[p])) == int(p), (dist, int(p))
 
 
+@pytest.mark.parametrize("kb,dist", [(4, "uniform"), (4, "normal"), (8, "uniform"), (4, "few")])
+def test_segmented_heads_from_histograms(torch, ctx, o, kb, dist):
+    """A segmented level dealt on one digit lists each segment's buckets from its digit
+    histogram; the same sort with the heads found from the keys gives the same chunks
+    and the same, stable result, per segment."""
+    lens = workloads.batch_lengths(300, 16, 1 << 18, 11)
+    lens[5] = 0
+    lens[6] = 8193
+    off = workloads.segment_offsets(lens)
+    n = int(off[-1])
+    k = workloads.make_keys(dist, n, 8 * kb, 12)
+    v = workloads.index_payload(n, 8 * kb)
+    out = []
+    for force in (0, 1):
+        say("segmented heads", kb, dist, n, "from keys" if force else "from histograms")
+        ctx.set_option("force_key_heads", force)
+        try:
+            dk, dv = dev(torch, k), dev(torch, v)
+            ctx.sort_segmented_(dk, dv, off)
+            torch.cuda.synchronize()
+            out.append((host(dk), host(dv), ctx.stats()))
+        finally:
+            ctx.set_option("force_key_heads", 0)
+    rk, rv = o.segmented_sort(k, v, off)
+    for sk, sv, st in out:
+        assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    assert out[0][2]["chunks"] == out[1][2]["chunks"], (out[0][2], out[1][2])
+
+
 def test_size_limit(torch, ctx):
     """More records than one segment may hold: refused before any work."""
     import ctypes
