@@ -943,13 +943,10 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
         // One segment dealt on two digits, bases scanned ahead: its buckets are the
         // non-empty digit pairs, counted from the first digit's histogram and the second
-        // deal's per-tile counts, so the keys need not be read again.  Dealt on one
-        // digit: its buckets are that digit's non-empty values.
+        // deal's per-tile counts, so the keys need not be read again.
         const Seg& g0 = hs[active[0]];
-        const bool from_counts = single && !c->force_key_heads && g0.first_pass == 0 &&
-                                 !full[active[0]] &&
-                                 ((d == 2 && g0.npass == 2 && g0.shift[0] != g0.shift[1]) ||
-                                  (d == 1 && g0.npass == 1));
+        const bool from_counts = single && !c->force_key_heads && d == 2 && g0.first_pass == 0 &&
+                                 g0.npass == 2 && g0.shift[0] != g0.shift[1] && !full[active[0]];
         if (from_counts) {
             JointArgs ja{};
             ja.keys = j.k[1 - cur];  // the first deal's output, intact after the second
@@ -959,9 +956,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ja.tcnt = tone;
             ja.ntiles = (uint32_t)ntiles;
             ja.tile = j.tile;
-            ja.shift1 = d == 2 ? g0.shift[1] : 0;
+            ja.shift1 = g0.shift[1];
             ja.width0 = g0.width[0];
-            ja.width1 = d == 2 ? g0.width[1] : 0;
+            ja.width1 = g0.width[1];
             ja.joint = joint;
             ja.rows = joint_rows;
             ja.bstart = dbstart;

@@ -7,19 +7,31 @@
 // buckets to a simple stable sort and recurses on large buckets.
 //
 //   k_count        count: digit histograms of every digit in one read, plus the OR and
-//                  AND of each segment's keys (digits that never vary are skipped).
-//   k_deal         deal: one stable scatter pass.  Tiles take tickets in order; each
-//                  tile ranks its records by digit with wave ballots, publishes its
-//                  digit counts, and finds its offsets by decoupled look-back over the
-//                  tiles before it; records are staged in LDS so each bucket's run is
-//                  written contiguously.
-//   k_heads        bucket boundaries after the deals: positions where the leading
-//                  bits change, compacted in order (look-back over one counter).
+//                  AND of each segment's keys (digits that never vary are skipped); also
+//                  each tile's own counts, for the deals' bucket bases.
+//   k_tile_scan_*  per-tile bucket bases of one segment (reduce, then scan);
+//   k_seg_scan     the same for many short segments, one block per segment.
+//   k_deal         deal: one stable scatter pass.  Each tile ranks its records by digit
+//                  with wave ballots and stages them in LDS in digit order, so each
+//                  bucket's run is written contiguously; its bases come from the scans,
+//                  or from decoupled look-back over the tiles before it.
+//   k_heads*       bucket boundaries after the deals, from the keys: positions where
+//                  the leading bits change, listed in order.
+//   k_joint_*      the same without the keys, for one segment dealt on two digits:
+//                  pair counts from the first digit's histogram and the second deal's
+//                  per-tile counts.
+//   k_hist_heads_* the same for segments dealt on one digit, from their histograms.
 //   k_classify     buckets -> runs of small buckets packed per window, medium buckets,
 //                  large buckets (recursion) and finished large buckets.
-//   k_local_sort   the diversion: a stable LSD radix sort inside LDS of one run of
-//                  small buckets (or one medium bucket), over only the bits that vary.
-//   k_copy_tiles   copy of finished ranges back into the caller's buffers.
+//   k_local_sort_bucket, k_local_sort
+//                  the diversion: each run of small buckets (or medium bucket) sorted
+//                  in LDS by bucketing words and ranking them inside their bins, or by
+//                  a stable LSD radix sort over only the bits that vary.
+//   k_copy_tiles, k_copy_chunks
+//                  copies of finished ranges, and the serving gather/scatter.
+//   k_key_transform, k_collisions
+//                  order-preserving maps of signed/float keys; the plan's collision
+//                  estimates and overflow counts from the histograms.
 #include "dfr_internal.h"
 
 #include <algorithm>
@@ -713,7 +725,6 @@ __global__ __launch_bounds__(256) void k_heads_emit(HeadArgs a) {
 // Bucket heads without reading the keys, for a one-segment level dealt on two digits
 // (the lower, u, then the upper, v).  The level's buckets are the non-empty pairs
 // (v, u), in that order, so their starts are an exclusive scan of the pair counts.
-// (A level dealt on one digit is the case of a single v: the counts are its histogram.)
 // After the first deal the records of each u fill one known range (the u histogram's
 // prefix sum); the second deal's per-tile counts of v, summed over the tiles wholly
 // inside that range, plus a direct count of the records of the range in the (at most
@@ -735,10 +746,6 @@ __global__ __launch_bounds__(JOINT_GROUPS * RADIX) void k_joint_counts(JointArgs
     const uint32_t u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t v = tid % RADIX, grp = tid / RADIX;
     const uint32_t n0 = 1u << a.width0, n1 = 1u << a.width1;
-    if (a.width1 == 0) {  // a level dealt on one digit: its buckets are the digit's values
-        if (tid == 0) a.joint[u] = a.h0[u];
-        return;
-    }
     // Start of u's range: the sum of the histogram below u.
     if (tid < RADIX) {
         uint32_t x = tid < u ? a.h0[tid] : 0u;
