@@ -233,8 +233,9 @@ dfr_status dfr_get_serve_stats(dfr_ctx* ctx, dfr_serve_stats* out);
  *                     instead of scanning the tiles' bucket bases ahead of the deal
  *                     (same result; for testing and measurement), 0 to restore.
  *   "force_key_heads" 1 to find every level's bucket heads by reading the keys, also
- *                     where a one-segment level dealt on two digits can take them from
- *                     the digit counts (same result; for testing), 0 to restore.
+ *                     where a level could take them from its digit counts (one segment
+ *                     dealt on two digits) or histograms (dealt on one digit); same
+ *                     result, for testing.  0 to restore.
  *   "radix_bits"      digit width b of the deal passes, 4..8 with at most 8 digits
  *                     per key (so 8 for 64-bit keys); the paper's digits are 8 bits
  *                     (Sec. 4).  0 = tuned or default.

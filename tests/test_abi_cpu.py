@@ -40,6 +40,16 @@ def test_every_declared_symbol_is_exported(L):
         assert hasattr(L, name), name
 
 
+def test_every_option_is_documented():
+    """The option names dfr_set_option accepts are exactly those include/dfr.h lists."""
+    src = open(os.path.join(ROOT, "paper_2207_14334_amd", "csrc", "dfr.cpp")).read()
+    a = src.index("dfr_status dfr_set_option(")
+    body = src[a:src.index("\n}\n", a)]
+    accepted = set(re.findall(r'strcmp\(name, "([a-z_]+)"\)', body))
+    documented = set(re.findall(r'^ \*   "([a-z_]+)"', open(HEADER).read(), flags=re.M))
+    assert accepted and accepted == documented, (accepted ^ documented)
+
+
 def test_temp_bytes(L):
     assert dfr.temp_bytes(0, 4, 0) == 0
     assert dfr.temp_bytes(1, 4, 0) == 256
