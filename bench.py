@@ -439,7 +439,8 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the sort's "
-                                   "multi-GPU path is not built (see DESIGN.md)"}), flush=True)
+                                   "multi-GPU path (histogram all-reduce, splitters, "
+                                   "all-to-all exchange) is not built"}), flush=True)
         sys.exit(2)
     if args.workload == "batched":
         return run_batched(args)
