@@ -45,7 +45,7 @@ typedef int32_t dfr_status;
 #define DFR_OK 0
 #define DFR_E_INVALID_ARG (-1) /* NULL with n > 0, misaligned, overlapping, bad width,  */
                                /* temp too small, malformed segment offsets           */
-#define DFR_E_TOO_LARGE (-2)   /* a segment of 2^30 records or more                    */
+#define DFR_E_TOO_LARGE (-2)   /* a segment of 2^32 records or more                    */
 #define DFR_E_NO_MEMORY (-3)   /* device scratch could not be allocated               */
 #define DFR_E_HIP (-4)         /* HIP runtime error; detail in dfr_last_error          */
 #define DFR_E_PENDING (-5)     /* request not finished yet                             */
@@ -54,9 +54,10 @@ typedef int32_t dfr_status;
 #define DFR_E_UNSUPPORTED (-8) /* entry point or option not available                  */
 #define DFR_E_INTERNAL (-9)    /* a kernel's bounded wait expired; results invalid     */
 
-/* Largest number of records in one sort, or in one segment of a segmented sort.
- * The per-tile digit counts that the look-back scan publishes are 30-bit fields. */
-#define DFR_MAX_SEGMENT_RECORDS ((size_t)1 << 30) - 1
+/* Largest number of records in one sort, or in one segment of a segmented sort,
+ * 2^32 - 1: digit counts, bucket positions inside a segment and the deal's scatter
+ * offsets are 32-bit. */
+#define DFR_MAX_SEGMENT_RECORDS ((size_t)0xffffffffu)
 
 typedef struct dfr_ctx dfr_ctx;
 
@@ -271,6 +272,18 @@ typedef struct {
                                   estimated buckets (ceil(n / 2^b) slots each, Sec.
                                   3.1) would have overflowed when dealing the first
                                   level's top varying digit; measured from the counts */
+    /* Which kernel forms ran, over all levels (for tests and profiling). */
+    uint64_t chunks_form0;       /* local-sort chunks sorted on 32-bit words holding
+                                    their position                                   */
+    uint64_t chunks_form1;       /* ... on 32-bit words with the position beside them */
+    uint64_t chunks_form2;       /* ... on 64-bit words                               */
+    uint64_t chunks_general;     /* ... by the general stable radix kernel in LDS     */
+    int32_t deal_passes_scanned;  /* deal launches whose bucket bases were scanned    */
+    int32_t deal_passes_lookback; /* deal launches with decoupled look-back          */
+    int32_t levels_heads_keys;    /* levels whose bucket heads came from the keys    */
+    int32_t levels_heads_counts;  /* ... from the two dealt digits' counts           */
+    int32_t levels_heads_hist;    /* ... from the dealt digit's histograms           */
+    int32_t deal_passes_estimated; /* deal launches into estimated buckets (Sec. 3) */
 } dfr_stats;
 
 dfr_status dfr_get_stats(const dfr_ctx* ctx, dfr_stats* out);

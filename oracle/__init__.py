@@ -10,6 +10,8 @@ of the paper it follows, is stated in ``oracle.c``:
 
 * ``stable_sort`` -- the definition of the result: record i goes to
   rank(i) = #{j: k_j < k_i} + #{j < i: k_j == k_i}  (Sec. 2.1 stability, Sec. 3).
+* ``stable_sort_parallel`` -- the same result on several host threads (chunks sorted
+  by that definition, then merged pairwise with equal keys left first), for timing.
 * ``rank`` -- that formula evaluated directly, O(n^2).
 * ``count`` / ``deal`` -- one counting-sort pass (Sec. 2, counting sort paragraph).
 * ``lsd_sort`` -- LSD radix sort from the deals (Sec. 2.1).
@@ -43,7 +45,7 @@ def build(out_path: str = _LIB, defines: tuple[str, ...] = ()) -> str:
     the oracle with a planted mistake and check that the pins catch it.
     """
     cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", _SRC, "-o",
-           out_path + ".tmp", "-lm"]
+           out_path + ".tmp", "-lm", "-lpthread"]
     cmd[1:1] = [f"-D{d}" for d in defines]
     subprocess.run(cmd, check=True)
     os.replace(out_path + ".tmp", out_path)
@@ -60,6 +62,7 @@ class Oracle:
         lib = ctypes.CDLL(path)
         P, Z, I = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
         lib.oracle_stable_sort.argtypes = [P, P, Z, I, I, P, P]
+        lib.oracle_stable_sort_parallel.argtypes = [P, P, Z, I, I, I, P, P]
         lib.oracle_segmented_sort.argtypes = [P, P, Z, I, I, P, Z, P, P]
         lib.oracle_rank.argtypes = [P, Z, I, P]
         lib.oracle_rank_of.argtypes = [P, Z, I, Z]
@@ -107,6 +110,15 @@ class Oracle:
         ov = np.empty_like(vals) if vals is not None else None
         self._rc(self.lib.oracle_stable_sort(self._p(keys), self._p(vals), keys.size, kb, vb,
                                              self._p(ok), self._p(ov)))
+        return ok, ov
+
+    def stable_sort_parallel(self, keys, vals=None, threads: int = 1):
+        keys, vals, kb, vb = self._prep(keys, vals)
+        ok = np.empty_like(keys)
+        ov = np.empty_like(vals) if vals is not None else None
+        self._rc(self.lib.oracle_stable_sort_parallel(self._p(keys), self._p(vals), keys.size,
+                                                      kb, vb, int(threads), self._p(ok),
+                                                      self._p(ov)))
         return ok, ov
 
     def overflow_fraction(self, N: int, M: int) -> float:

@@ -32,6 +32,7 @@
  * success, -1 on a bad argument, -2 when host memory runs out.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -109,6 +110,111 @@ int oracle_stable_sort(const void* keys, const void* vals, size_t n, int kb, int
         if (vb) st(out_vals, vb, i, ld(vals, vb, r[i].idx));
     }
     free(r);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* The same definition on several host threads, for timing the CPU baseline: each    */
+/* thread sorts one contiguous chunk of the records by (key, index) as above, then    */
+/* neighbouring sorted runs are merged pairwise, level by level, into one run.  A     */
+/* merge that takes the left run's record while its key is not greater than the       */
+/* right run's keeps equal keys in input order (every left record precedes every      */
+/* right one in the input), so the result is the same stable sort.                    */
+/* ------------------------------------------------------------------------------ */
+
+typedef struct {
+    keyed_index* r;
+    size_t lo, hi;
+} sort_job;
+
+static void* sort_chunk(void* arg) {
+    sort_job* j = (sort_job*)arg;
+    qsort(j->r + j->lo, j->hi - j->lo, sizeof(keyed_index), cmp_key_then_index);
+    return NULL;
+}
+
+typedef struct {
+    const keyed_index* src;
+    keyed_index* dst;
+    size_t lo, mid, hi;  /* merges src[lo, mid) and src[mid, hi) into dst[lo, hi) */
+} merge_job;
+
+static void* merge_runs(void* arg) {
+    merge_job* m = (merge_job*)arg;
+    size_t a = m->lo, b = m->mid, o = m->lo;
+    while (a < m->mid && b < m->hi) {
+#ifdef ORACLE_PLANT_MERGE_RIGHT_FIRST
+        /* Planted mistake for the pin tests: equal keys take the right run first. */
+        if (m->src[a].key < m->src[b].key)
+#else
+        if (m->src[a].key <= m->src[b].key)
+#endif
+            m->dst[o++] = m->src[a++];
+        else
+            m->dst[o++] = m->src[b++];
+    }
+    while (a < m->mid) m->dst[o++] = m->src[a++];
+    while (b < m->hi) m->dst[o++] = m->src[b++];
+    return NULL;
+}
+
+int oracle_stable_sort_parallel(const void* keys, const void* vals, size_t n, int kb, int vb,
+                                int threads, void* out_keys, void* out_vals) {
+    if (!widths_ok(kb, vb) || threads < 1) return OR_EARG;
+    if (n == 0) return OR_OK;
+    if (!keys || !out_keys || (vb && (!vals || !out_vals))) return OR_EARG;
+    size_t p = (size_t)threads < n ? (size_t)threads : n;
+    keyed_index* r = (keyed_index*)malloc(n * sizeof(keyed_index));
+    keyed_index* t = (keyed_index*)malloc(n * sizeof(keyed_index));
+    size_t* bound = (size_t*)malloc((p + 1) * sizeof(size_t));
+    pthread_t* th = (pthread_t*)malloc(p * sizeof(pthread_t));
+    sort_job* sj = (sort_job*)malloc(p * sizeof(sort_job));
+    merge_job* mj = (merge_job*)malloc(p * sizeof(merge_job));
+    if (!r || !t || !bound || !th || !sj || !mj) {
+        free(r); free(t); free(bound); free(th); free(sj); free(mj);
+        return OR_ENOMEM;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        r[i].key = ld(keys, kb, i);
+        r[i].idx = i;
+    }
+    for (size_t c = 0; c <= p; ++c) bound[c] = n / p * c + (c < n % p ? c : n % p);
+    for (size_t c = 0; c < p; ++c) {
+        sj[c].r = r;
+        sj[c].lo = bound[c];
+        sj[c].hi = bound[c + 1];
+        if (pthread_create(&th[c], NULL, sort_chunk, &sj[c]) != 0) sort_chunk(&sj[c]), th[c] = 0;
+    }
+    for (size_t c = 0; c < p; ++c)
+        if (th[c]) pthread_join(th[c], NULL);
+    /* Runs are [bound[c], bound[c + 1]); each level merges runs 2i and 2i + 1. */
+    size_t runs = p;
+    keyed_index *src = r, *dst = t;
+    while (runs > 1) {
+        size_t m = 0;
+        for (size_t c = 0; c < runs; c += 2) {
+            mj[m].src = src;
+            mj[m].dst = dst;
+            mj[m].lo = bound[c];
+            mj[m].mid = bound[c + 1];  /* a last unpaired run is copied as it is */
+            mj[m].hi = c + 1 < runs ? bound[c + 2] : bound[c + 1];
+            if (pthread_create(&th[m], NULL, merge_runs, &mj[m]) != 0) merge_runs(&mj[m]), th[m] = 0;
+            ++m;
+        }
+        for (size_t c = 0; c < m; ++c)
+            if (th[c]) pthread_join(th[c], NULL);
+        for (size_t c = 0; c < m; ++c) bound[c] = mj[c].lo;
+        bound[m] = n;
+        runs = m;
+        keyed_index* x = src;
+        src = dst;
+        dst = x;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        st(out_keys, kb, i, src[i].key);
+        if (vb) st(out_vals, vb, i, ld(vals, vb, src[i].idx));
+    }
+    free(r); free(t); free(bound); free(th); free(sj); free(mj);
     return OR_OK;
 }
 

@@ -28,7 +28,7 @@ E_BUDGET = -7
 E_UNSUPPORTED = -8
 E_INTERNAL = -9
 
-MAX_SEGMENT_RECORDS = (1 << 30) - 1
+MAX_SEGMENT_RECORDS = (1 << 32) - 1
 
 EXPORTED = [
     "dfr_create", "dfr_destroy", "dfr_status_string", "dfr_last_error", "dfr_temp_bytes",
@@ -60,6 +60,11 @@ class Stats(ctypes.Structure):
         ("ms_buckets", ctypes.c_double), ("ms_local_sort", ctypes.c_double),
         ("ms_other", ctypes.c_double), ("deal_launches_timed", ctypes.c_int32),
         ("estimated_overflow", ctypes.c_double),
+        ("chunks_form0", ctypes.c_uint64), ("chunks_form1", ctypes.c_uint64),
+        ("chunks_form2", ctypes.c_uint64), ("chunks_general", ctypes.c_uint64),
+        ("deal_passes_scanned", ctypes.c_int32), ("deal_passes_lookback", ctypes.c_int32),
+        ("levels_heads_keys", ctypes.c_int32), ("levels_heads_counts", ctypes.c_int32),
+        ("levels_heads_hist", ctypes.c_int32), ("deal_passes_estimated", ctypes.c_int32),
     ]
 
     def as_dict(self):

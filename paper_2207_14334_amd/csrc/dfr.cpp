@@ -98,6 +98,12 @@ struct dfr_ctx {
     std::map<uint32_t, dfr_tune> tunes;  // tuned settings per (kb, vb, size class)
 
     dfr_stats stats{};
+    // Order between calls on different streams: every call records `done` on its
+    // stream when it returns, and a call on another stream first makes its stream wait
+    // for it, because calls share the arena, the temp cache and the pinned staging.
+    hipEvent_t done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool have_last = false;
     struct Ev {
         int stage;
         bool deal;
@@ -401,6 +407,7 @@ struct Job {
     int top_d_forced = 0;
     uint32_t err_word_host = 0;
     bool err_known = false;  // err_word_host holds the word after the last error-setting kernel
+    uint32_t stat_host[STAT_WORDS] = {};  // the status block as last read back
     uint32_t* err_dev = nullptr;
 };
 
@@ -520,6 +527,7 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         la.nwide = dcounts + 4;
         la.widecap = (uint32_t)nb;
         la.err = j.err_dev;
+        la.stat = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nb, 8192);
         int max_lo = 0;
         for (const Seg& g : hs) max_lo = std::max(max_lo, (int)g.lo_bit);
@@ -779,7 +787,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // --- 3. deal ------------------------------------------------------------------
     const uint64_t ntiles = tiles.size();
     const size_t need_b = asize<Tile>(ntiles) + asize<Tile>(nht) + asize<Seg>(S) +
-                          asize<uint32_t>(ntiles * RADIX + 1) +
+                          asize<uint64_t>(ntiles * RADIX + 1) +
                           asize<uint32_t>(nht) + asize<uint64_t>(nht) + asize<uint16_t>(nht * HEAD_SLOTS) +
                           asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
@@ -804,7 +812,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     dtiles = same_tiles ? (Tile*)(c->arena + off_ctiles) : aalloc<Tile>(c, ntiles);
     Tile* dhtiles = any_full ? aalloc<Tile>(c, nht) : dtiles;
     Seg* dsegs = aalloc<Seg>(c, S);
-    uint32_t* lb = aalloc<uint32_t>(c, ntiles * RADIX + 1);
+    uint64_t* lb = aalloc<uint64_t>(c, ntiles * RADIX + 1);  // look-back words, then the ticket
     uint32_t* htcount = aalloc<uint32_t>(c, nht);
     uint64_t* htbase = aalloc<uint64_t>(c, nht);
     uint16_t* htslot = aalloc<uint16_t>(c, nht * HEAD_SLOTS);
@@ -863,7 +871,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ta.off = toff;
             Timed ts(c, j.s, ST_OTHER);
             HIP_TRY(c, launch_tile_scan(ta, j.s));
-            HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
+            HIP_TRY(c, launch_fill_u64(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
         } else if (perseg) {
             // A few long segments: the one-segment scan over each segment's tiles.
             Timed ts(c, j.s, ST_OTHER);
@@ -883,7 +891,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                 ta.off = toff + (size_t)g.first_tile * RADIX;
                 HIP_TRY(c, launch_tile_scan(ta, j.s));
             }
-            HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
+            HIP_TRY(c, launch_fill_u64(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
         } else if (segscan) {
             SegScanArgs sa{};
             sa.segs = dsegs;
@@ -898,9 +906,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             sa.off = toff;
             Timed ts(c, j.s, ST_OTHER);
             HIP_TRY(c, launch_seg_scan(sa, j.s));
-            HIP_TRY(c, launch_fill_u32(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
+            HIP_TRY(c, launch_fill_u64(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
         } else {
-            HIP_TRY(c, launch_fill_u32(lb, 0, ntiles * RADIX + 1, j.s));
+            HIP_TRY(c, launch_fill_u64(lb, 0, ntiles * RADIX + 1, j.s));
         }
         Timed tm(c, j.s, ST_DEAL, true);
         DealArgs da{};
@@ -917,11 +925,13 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         da.hist_digits = ndig;
         da.pass = p;
         da.lookback = lb;
-        da.ticket = lb + ntiles * RADIX;
+        da.ticket = (uint32_t*)(lb + ntiles * RADIX);
         da.err = j.err_dev;
         HIP_TRY(c, launch_deal(kb, j.vb, da, j.s));
         cur = 1 - cur;
         c->stats.deal_passes += 1;
+        if (nolb) c->stats.deal_passes_scanned += 1;
+        else c->stats.deal_passes_lookback += 1;
     }
     *next_in = cur;
 
@@ -968,6 +978,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ja.nbuckets = counters;
             ja.err = j.err_dev;
             HIP_TRY(c, launch_joint_heads(kb, ja, j.s));
+            c->stats.levels_heads_counts += 1;
         } else if (!c->force_key_heads && d == 1) {
             // Every segment dealt on one digit: its buckets are that digit's non-empty
             // values, from its histogram.
@@ -989,6 +1000,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ha.nbuckets = counters;
             ha.err = j.err_dev;
             HIP_TRY(c, launch_hist_heads(ha, j.s));
+            c->stats.levels_heads_hist += 1;
         } else {
             HeadArgs ha{};
             ha.keys = j.k[cur];
@@ -1004,6 +1016,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ha.nbuckets = counters;
             ha.err = j.err_dev;
             HIP_TRY(c, launch_heads(kb, ha, j.s));
+            c->stats.levels_heads_keys += 1;
         }
         ClassifyArgs ca{};
         ca.bstart = dbstart;
@@ -1061,6 +1074,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         la.nwide = counters + 6;
         la.widecap = (uint32_t)(nslots + medcap);
         la.err = j.err_dev;
+        la.stat = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 8192);
         int max_lo = 0;
         for (uint32_t i : active)
@@ -1074,17 +1088,18 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     st = pin_reserve(c, 8 * 4 + 2 * bigcap * sizeof(Big) + 256, j.s);
     if (st) return st;
     uint32_t* hc = palloc<uint32_t>(c, 8);
-    uint32_t* he = palloc<uint32_t>(c, 1);
+    uint32_t* he = palloc<uint32_t>(c, STAT_WORDS);
     HIP_TRY(c, hipMemcpyAsync(hc, counters, 8 * 4, hipMemcpyDeviceToHost, j.s));
-    // The error word comes back with the counters: no kernel after this point can set
-    // it unless another level runs (which clears err_known).
-    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, 4, hipMemcpyDeviceToHost, j.s));
+    // The status block comes back with the counters: no kernel after this point can
+    // change it unless another level runs (which clears err_known).
+    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, STAT_WORDS * 4, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipStreamSynchronize(j.s));
-    j.err_word_host = *he;
+    memcpy(j.stat_host, he, sizeof j.stat_host);
+    j.err_word_host = he[STAT_ERR];
     j.err_known = true;
     const uint32_t nbig = std::min<uint32_t>(hc[2], (uint32_t)bigcap);
     const uint32_t ndone = std::min<uint32_t>(hc[3], (uint32_t)bigcap);
-    c->stats.chunks += hc[0];
+    c->stats.chunks += hc[5];  // work items listed by classify
     Big* hb = palloc<Big>(c, std::max<uint32_t>(nbig, 1));
     Big* hd = palloc<Big>(c, std::max<uint32_t>(ndone, 1));
     if (nbig) HIP_TRY(c, hipMemcpyAsync(hb, big, nbig * sizeof(Big), hipMemcpyDeviceToHost, j.s));
@@ -1108,14 +1123,19 @@ dfr_status check_err(Job& j) {
     dfr_ctx* c = j.c;
     uint32_t e = j.err_word_host;
     if (!j.err_known) {
-        dfr_status st = pin_reserve(c, 64, j.s);
+        dfr_status st = pin_reserve(c, 64 + STAT_WORDS * 4, j.s);
         if (st) return st;
-        uint32_t* h = palloc<uint32_t>(c, 1);
-        HIP_TRY(c, hipMemcpyAsync(h, j.err_dev, 4, hipMemcpyDeviceToHost, j.s));
+        uint32_t* h = palloc<uint32_t>(c, STAT_WORDS);
+        HIP_TRY(c, hipMemcpyAsync(h, j.err_dev, STAT_WORDS * 4, hipMemcpyDeviceToHost, j.s));
         HIP_TRY(c, hipStreamSynchronize(j.s));
-        e = *h;
+        memcpy(j.stat_host, h, sizeof j.stat_host);
+        e = h[STAT_ERR];
         synced(c);
     }
+    c->stats.chunks_form0 = j.stat_host[STAT_FORM0];
+    c->stats.chunks_form1 = j.stat_host[STAT_FORM0 + 1];
+    c->stats.chunks_form2 = j.stat_host[STAT_FORM0 + 2];
+    c->stats.chunks_general = j.stat_host[STAT_GENERAL];
     if (e) {
         char buf[128];
         snprintf(buf, sizeof buf, "device error word 0x%x", e);
@@ -1153,7 +1173,7 @@ dfr_status run_sort(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const st
     dfr_status st = DFR_OK;
     if (!c->err_dev) HIP_TRY(c, hipMalloc((void**)&c->err_dev, ALIGN));
     j.err_dev = c->err_dev;
-    HIP_TRY(c, launch_fill_u32(j.err_dev, 0, 1, s));
+    HIP_TRY(c, launch_fill_u32(j.err_dev, 0, STAT_WORDS, s));
 
     std::vector<LSeg> small, large;
     for (auto& g : segs0) {
@@ -1240,6 +1260,28 @@ dfr_status set_device(dfr_ctx* c) {
     return DFR_OK;
 }
 
+// Stream order of one call against the context's previous call (see dfr_ctx::done).
+struct CallOrder {
+    dfr_ctx* c;
+    hipStream_t s;
+    dfr_status st = DFR_OK;
+    CallOrder(dfr_ctx* c_, hipStream_t s_) : c(c_), s(s_) {
+        if (c->have_last && c->last_stream != s) {
+            const hipError_t e = hipStreamWaitEvent(s, c->done, 0);
+            if (e != hipSuccess) st = fail_hip(c, e, "hipStreamWaitEvent");
+        }
+    }
+    ~CallOrder() {
+        if (hipEventRecord(c->done, s) == hipSuccess) {
+            c->last_stream = s;
+            c->have_last = true;
+        } else {
+            (void)hipGetLastError();
+            c->have_last = false;
+        }
+    }
+};
+
 // run_sort between the in-place map of signed or float keys to unsigned ones and its
 // inverse (mode 0: unsigned keys, no map).
 dfr_status run_sort_mapped(dfr_ctx* c, int kb, int vb, int mode, void* keys, void* vals, size_t n,
@@ -1270,6 +1312,8 @@ dfr_status sort_plain(dfr_ctx* c, int kb, int vb, void* keys, void* vals, size_t
     st = set_device(c);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    if (order.st) return order.st;
     st = get_temp(c, n, kb, vb, &temp, s);
     if (st) return st;
     std::vector<LSeg> segs{LSeg{0, n, 8 * kb}};
@@ -1333,6 +1377,8 @@ dfr_status sort_segmented(dfr_ctx* c, int kb, int vb, void* keys, void* vals, co
     st = set_device(c);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    if (order.st) return order.st;
     st = get_temp(c, n, kb, vb, &temp, s);
     if (st) return st;
     return run_sort_mapped(c, kb, vb, mode, keys, vb ? vals : nullptr, n, segs, temp, s);
@@ -1639,7 +1685,11 @@ dfr_status run_batch(Server::Worker& wk, const std::vector<Server::Req>& b, doub
         if (!st) st = copy_batch(j, b, wk.sk, wk.sv, false);
         if (!st) HIP_TRY(w, hipEventRecord(wk.ev[3], wk.s));
     }
-    if (!st) HIP_TRY(w, hipStreamSynchronize(wk.s));
+    // Wait for the batch's device work whatever its status: the requests' buffers are
+    // handed back to their callers once their tickets are done.
+    const hipError_t sync_err = hipStreamSynchronize(wk.s);
+    if (!st && sync_err != hipSuccess) st = fail_hip(w, sync_err, "hipStreamSynchronize");
+    (void)hipGetLastError();
     synced(w);
     if (!st) {
         float f = 0;
@@ -1738,8 +1788,9 @@ void worker_loop(Server* sv, int wi) {
                 st, std::chrono::duration<double>(t_end - q.t_submit).count()};
         }
         if (st) {
-            // Record the failure on the owner for dfr_last_error; the worker's context
-            // is rebuilt so later batches start clean.
+            // Record the failure on the owner for dfr_last_error.  The batch's device
+            // work has finished (run_batch waits for it whatever its status); the
+            // worker's context is cleared of its failed mark so later batches run.
             sv->owner->err = "serving batch: " + wk.w->err;
             wk.w->failed = false;
         }
@@ -1766,6 +1817,7 @@ dfr_status start_server(dfr_ctx* c) {
         wk.w->tunes = c->tunes;
         wk.w->temp_slack = 4;  // batches vary in size: grow the temp cache by half again
         bool ok = hipStreamCreateWithFlags(&wk.s, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&wk.w->done, hipEventDisableTiming) == hipSuccess;
         for (int e = 0; ok && e < 4; ++e) ok = hipEventCreate(&wk.ev[e]) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
@@ -1773,6 +1825,7 @@ dfr_status start_server(dfr_ctx* c) {
                 if (sv->workers[k].s) (void)hipStreamDestroy(sv->workers[k].s);
                 for (auto e : sv->workers[k].ev)
                     if (e) (void)hipEventDestroy(e);
+                if (sv->workers[k].w->done) (void)hipEventDestroy(sv->workers[k].w->done);
                 delete sv->workers[k].w;
             }
             delete sv;
@@ -1799,6 +1852,7 @@ void stop_server(dfr_ctx* c) {
         if (wk.w->pin) (void)hipHostFree(wk.w->pin);
         for (auto e : wk.w->event_pool) (void)hipEventDestroy(e);
         for (auto e : wk.ev) (void)hipEventDestroy(e);
+        if (wk.w->done) (void)hipEventDestroy(wk.w->done);
         (void)hipStreamDestroy(wk.s);
         delete wk.w;
     }
@@ -1835,6 +1889,11 @@ dfr_status dfr_create(int hip_device, size_t hbm_budget_bytes, dfr_ctx** out) {
         total_b = 0;
     }
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : total_b / 4;
+    if (hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return DFR_E_HIP;
+    }
     *out = c;
     return DFR_OK;
 }
@@ -1856,6 +1915,7 @@ void dfr_destroy(dfr_ctx* c) {
         (void)hipEventDestroy(e.b);
     }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->done) (void)hipEventDestroy(c->done);
     delete c;
 }
 
@@ -1917,6 +1977,8 @@ dfr_status dfr_autotune(dfr_ctx* c, int key_bytes, int val_bytes, const void* ke
     }
     st = set_device(c);
     if (st) return st;
+    CallOrder order(c, (hipStream_t)stream);
+    if (order.st) return order.st;
     return autotune(c, key_bytes, val_bytes, keys, val_bytes ? vals : nullptr, segs, n,
                     reps > 0 ? reps : 2, (hipStream_t)stream, out);
 }
@@ -2001,6 +2063,8 @@ dfr_status dfr_count(dfr_ctx* c, const void* keys, int key_bytes, size_t n, int 
     dfr_status st = set_device(c);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    if (order.st) return order.st;
     HIP_TRY(c, launch_fill_u32(hist, 0, (size_t)num_digits * RADIX, s));
     if (n == 0) return DFR_OK;
     std::vector<LSeg> segs{LSeg{0, n, 8 * key_bytes}};
@@ -2062,6 +2126,8 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
     dfr_status st = set_device(c);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    if (order.st) return order.st;
     Job j;
     j.c = c;
     j.s = s;
@@ -2072,7 +2138,7 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
     build_tiles(segs, ids, deal_tile_records(key_bytes, val_bytes), tiles, ft);
     const size_t nt = tiles.size();
     st = arena_reserve(c, asize<Tile>(nt) + asize<Seg>(1) + asize<uint32_t>(RADIX) +
-                              2 * asize<uint64_t>(1) + asize<uint32_t>(nt * RADIX + 1) +
+                              2 * asize<uint64_t>(1) + asize<uint64_t>(nt * RADIX + 1) +
                               asize<uint32_t>(1),
                        s);
     if (st) return st;
@@ -2081,7 +2147,7 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
     uint32_t* dh = aalloc<uint32_t>(c, RADIX);
     uint64_t* dor = aalloc<uint64_t>(c, 1);
     uint64_t* dand = aalloc<uint64_t>(c, 1);
-    uint32_t* lb = aalloc<uint32_t>(c, nt * RADIX + 1);
+    uint64_t* lb = aalloc<uint64_t>(c, nt * RADIX + 1);
     uint32_t* derr = aalloc<uint32_t>(c, 1);
     Seg g{};
     g.start = 0;
@@ -2096,7 +2162,7 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
     if (!st) st = upload(j, ds, &g, sizeof g);
     if (st) return st;
     HIP_TRY(c, launch_fill_u32(dh, 0, RADIX, s));
-    HIP_TRY(c, launch_fill_u32(lb, 0, nt * RADIX + 1, s));
+    HIP_TRY(c, launch_fill_u64(lb, 0, nt * RADIX + 1, s));
     HIP_TRY(c, launch_fill_u32(derr, 0, 1, s));
     CountArgs ca{};
     ca.keys = keys_in;
@@ -2123,7 +2189,7 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
     da.hist_digits = 1;
     da.pass = 0;
     da.lookback = lb;
-    da.ticket = lb + nt * RADIX;
+    da.ticket = (uint32_t*)(lb + nt * RADIX);
     da.err = derr;
     da.tile = deal_tile_records(key_bytes, val_bytes);
     {

@@ -12,14 +12,11 @@ namespace dfr {
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 
-// Look-back words of the deal pass: 2-bit status over a 30-bit count.
-constexpr uint32_t LB_AGG = 1u << 30;   // tile's own count published
-constexpr uint32_t LB_PRE = 2u << 30;   // inclusive prefix through this tile published
-constexpr uint32_t LB_COUNT = (1u << 30) - 1;
-// 64-bit look-back words (bucket-head compaction): same layout in the top bits.
-constexpr uint64_t LB64_AGG = 1ull << 62;
-constexpr uint64_t LB64_PRE = 2ull << 62;
-constexpr uint64_t LB64_COUNT = (1ull << 62) - 1;
+// Look-back words of the deal pass: a 2-bit status above a count of up to 62 bits (a
+// segment holds fewer than 2^32 records, so every count fits).
+constexpr uint64_t LB_AGG = 1ull << 62;  // tile's own count published
+constexpr uint64_t LB_PRE = 2ull << 62;  // inclusive prefix through this tile published
+constexpr uint64_t LB_COUNT = (1ull << 62) - 1;
 
 // Bits of the device error word.
 constexpr uint32_t ERR_SPIN = 1;        // a bounded look-back wait expired
@@ -114,7 +111,7 @@ struct DealArgs {
     const uint32_t* hist;
     int32_t hist_digits;
     int32_t pass;
-    uint32_t* lookback;  // [ntiles][RADIX]
+    uint64_t* lookback;  // [ntiles][RADIX]
     uint32_t* ticket;
     const uint32_t* off; // when set: per-tile bucket bases, and no look-back
     uint32_t tile;       // records per tile (selects the kernel; see deal_tile_supported)
@@ -233,7 +230,14 @@ struct LocalArgs {
     uint32_t widecap;
     int32_t spill_only; // set by the launcher
     uint32_t* err;
+    uint32_t* stat;     // chunks sorted by forms 0, 1, 2 and by the general kernel
 };
+
+// Words of the per-call device status block: the error word, then kernel counters.
+constexpr int STAT_ERR = 0;
+constexpr int STAT_FORM0 = 1;  // + form: chunks of the bucketed local sort, forms 0..2
+constexpr int STAT_GENERAL = 4;  // chunks of the general local sort
+constexpr int STAT_WORDS = 8;
 
 // A run of at most 2^32 - 1 records copied between two places.
 struct CopyChunk {

@@ -50,23 +50,24 @@ struct uint_of<8> {
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
 
-// Tile order of the look-back-free deal: 0 block index, 1 ticket, 2 one contiguous
-// range of tiles per XCD.
-#ifndef DFR_DEAL_ORDER
-#define DFR_DEAL_ORDER 2
-#endif
-constexpr int DEAL_ORDER = DFR_DEAL_ORDER;
-
-// Shapes of the bucketed local sort (overridable at build time for tuning sweeps).
-#ifndef DFR_LOCAL_MIN_WAVES  // waves per SIMD the bucketed local sort must fit
-#define DFR_LOCAL_MIN_WAVES 6
-#endif
-#ifndef DFR_LOCAL_MIN_WAVES32  // the same for its 32-bit-word form
-#define DFR_LOCAL_MIN_WAVES32 8
-#endif
-#ifndef DFR_LOCAL_DB_LESS  // bin bits below the most the position width allows
-#define DFR_LOCAL_DB_LESS 0
-#endif
+// Launch shapes.
+constexpr int DEAL_THREADS = 512;
+constexpr int DEAL_TILE_SMALL = 8192;  // records per deal tile when key + value <= 8 bytes
+constexpr int DEAL_TILE_LARGE = 4096;  // records per deal tile for 12- and 16-byte records
+constexpr int COUNT_THREADS = 256;
+constexpr int COUNT_VECS = 8;          // 16-byte loads in flight per counting thread
+constexpr int LOCAL_THREADS = 512;
+constexpr int LOCAL_CAP_SMALL = 8192;  // general local sort: records per chunk (<= 8-byte records)
+constexpr int LOCAL_CAP_LARGE = 4096;  // the same for 12- and 16-byte records
+constexpr int BUCKET_CAP_SMALL = 5120; // bucketed local sort: records per chunk (<= 8-byte records)
+constexpr int BUCKET_CAP_LARGE = 4096;
+constexpr int LOCAL_MIN_WAVES = 6;     // waves per SIMD the 64-bit-word local sort must fit
+constexpr int LOCAL_MIN_WAVES32 = 8;   // the same for its 32-bit-word forms
+constexpr int COPY_THREADS = 256;
+constexpr int HEAD_THREADS = 512;
+constexpr int GENERAL_THREADS = 256;
+// Largest chunk any local-sort kernel accepts (the general kernel's capacity).
+constexpr uint32_t LOCAL_CAP_ANY = LOCAL_CAP_SMALL;
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
@@ -107,27 +108,13 @@ __device__ __forceinline__ uint64_t same_digit_lanes_rt(uint32_t d, uint64_t act
 }
 
 // Spin (bounded) until a look-back word carries a status.
-__device__ __forceinline__ uint32_t wait_published(uint32_t* p, uint32_t* err) {
-    uint32_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t wait_published(uint64_t* p, uint32_t* err) {
+    uint64_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t spins = 0;
     while ((x & (LB_AGG | LB_PRE)) == 0) {
         if (++spins > SPIN_LIMIT) {
             atomicOr(err, ERR_SPIN);
             return LB_PRE;
-        }
-        __builtin_amdgcn_s_sleep(2);
-        x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint64_t wait_published64(uint64_t* p, uint32_t* err) {
-    uint64_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t spins = 0;
-    while ((x & (LB64_AGG | LB64_PRE)) == 0) {
-        if (++spins > SPIN_LIMIT) {
-            atomicOr(err, ERR_SPIN);
-            return LB64_PRE;
         }
         __builtin_amdgcn_s_sleep(2);
         x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -201,10 +188,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     constexpr int W = THREADS / 64;
     constexpr int SLICE = NDIG * RADIX;  // bins for up to NDIG digits
     constexpr int PER_VEC = 16 / KB;  // keys per 16-byte load
-#ifndef DFR_COUNT_VECS
-#define DFR_COUNT_VECS 8
-#endif
-    constexpr int VECS = DFR_COUNT_VECS;  // 16-byte loads in flight per thread
+    constexpr int VECS = COUNT_VECS;  // 16-byte loads in flight per thread
     __shared__ uint32_t s_h[W * SLICE];
     __shared__ uint32_t s_tot[SLICE];  // the block's counts for the current segment
     __shared__ K s_or[W];
@@ -369,21 +353,22 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     __shared__ V s_vals[VB ? T : 1];
     __shared__ uint32_t s_wcnt[W * RADIX];
     // Per digit: the place of the tile's first record of that digit in the segment,
-    // minus that record's place in the staged tile (a record at staged index i of digit
-    // d goes to segment position s_delta[d] + i).
-    __shared__ int32_t s_delta[RADIX];
+    // minus that record's place in the staged tile, modulo 2^32 (a record at staged
+    // index i of digit d goes to segment position s_delta[d] + i; a segment holds fewer
+    // than 2^32 records, so the position is exact in 32-bit arithmetic).
+    __shared__ uint32_t s_delta[RADIX];
     __shared__ uint32_t s_local[RADIX];
     __shared__ uint32_t s_part[RADIX / 64];
     __shared__ uint32_t s_ticket;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if ((LOOKBACK || DEAL_ORDER == 1) && tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
+    if (LOOKBACK && tid == 0) s_ticket = atomicAdd(a.ticket, 1u);
     for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[i] = 0;
     __syncthreads();
     uint32_t t;
-    if (LOOKBACK || DEAL_ORDER == 1) {
+    if (LOOKBACK) {
         t = s_ticket;
-    } else if (DEAL_ORDER == 2) {
+    } else {
         // Blocks are dealt to the 8 XCDs round-robin; give each XCD one contiguous
         // range of tiles, so the lines a bucket receives from neighbouring tiles are
         // written through one L2.
@@ -392,8 +377,6 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
         const uint32_t x = b % nx, i = b / nx;
         t = x < full ? x * per + i : full * per + (x - full) * (per - 1) + i;
         if (i >= (x < full ? per : per - 1)) t = a.ntiles;
-    } else {
-        t = blockIdx.x;
     }
     if (t >= a.ntiles) return;
 
@@ -449,7 +432,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
         tile_cnt = run;
         if (LOOKBACK)
             __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid],
-                               (t == first_tile ? LB_PRE : LB_AGG) | run, __ATOMIC_RELAXED,
+                               (t == first_tile ? LB_PRE : LB_AGG) | (uint64_t)run, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
     uint32_t total;
@@ -463,15 +446,15 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
 
     if (!LOOKBACK && tid < RADIX) {
         s_local[tid] = loc_excl;
-        s_delta[tid] = (int32_t)(a.off[(size_t)t * RADIX + tid] - loc_excl);
+        s_delta[tid] = a.off[(size_t)t * RADIX + tid] - loc_excl;
     }
     if (LOOKBACK && tid < RADIX) {
         s_local[tid] = loc_excl;
-        uint32_t excl = 0;
+        uint64_t excl = 0;
         if (t != first_tile) {
             uint32_t j = t - 1;
             for (;;) {
-                const uint32_t x = wait_published(&a.lookback[(size_t)j * RADIX + tid], a.err);
+                const uint64_t x = wait_published(&a.lookback[(size_t)j * RADIX + tid], a.err);
                 excl += x & LB_COUNT;
                 if ((x & LB_PRE) || j <= first_tile) break;
                 --j;
@@ -479,7 +462,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
             __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid], LB_PRE | (excl + tile_cnt),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_delta[tid] = (int32_t)(seg_excl + excl - loc_excl);
+        s_delta[tid] = seg_excl + (uint32_t)excl - loc_excl;
     }
     __syncthreads();
 
@@ -499,7 +482,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     __syncthreads();
 
     // Runs of equal digits go to consecutive addresses of their bucket.  Positions are
-    // 32-bit offsets into the segment (a segment holds fewer than 2^30 records).
+    // 32-bit offsets into the segment (a segment holds fewer than 2^32 records).
     K* kseg = (K*)a.kout + seg_start;
     V* vseg = (V*)a.vout + seg_start;
     const uint32_t seg_len = (uint32_t)(seg_end - seg_start);
@@ -510,7 +493,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
         if (i < len) {
             const K kk = s_keys[i];
             const uint32_t d = (uint32_t)(kk >> shift) & dmask;
-            const uint32_t p = (uint32_t)(s_delta[d] + (int32_t)i);
+            const uint32_t p = s_delta[d] + i;
             if (p < seg_len) {
                 kseg[p] = kk;
                 if (VB) vseg[p] = s_vals[i];
@@ -523,7 +506,8 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
-// Bucket heads (Sec. 2.2 buckets; Sec. 3 "determine if any large buckets remain").
+// Bucket heads (Sec. 2.2 buckets; Sec. 3: after the deals, the buckets are found so that
+// those still too large for the diversion can be recursed on).
 // After the deals, records of a segment are ordered by their bits >= lo_bit; a
 // bucket starts where those bits change (or at the segment start).  Heads are
 // written in position order: wave ballots inside the tile, look-back across tiles.
@@ -1068,11 +1052,6 @@ __global__ __launch_bounds__(CLASSIFY_THREADS) void k_classify(ClassifyArgs a) {
     if (over) atomicOr(a.err, ERR_LIST_CAP);
 }
 
-// Largest chunk any local-sort kernel accepts (the general kernel's capacity).
-#ifndef DFR_LOCAL_CAP_SMALL
-#define DFR_LOCAL_CAP_SMALL 8192
-#endif
-constexpr uint32_t LOCAL_CAP_ANY = DFR_LOCAL_CAP_SMALL;
 
 // A local-sort work item: either a window slot (a run of small buckets) or a medium
 // bucket (item >= nslots).  Returns false (uniformly across the block) for an empty slot or a bad one.
@@ -1352,14 +1331,14 @@ __device__ __forceinline__ bool bucket_sort_chunk(
 // 2: 64-bit words with the position inside.  Forms 0 and 1 hand chunks that do not fit
 // to the 64-bit form's list.
 template <int KB, int VB, int THREADS, int CAP, int FORM>
-__global__ __launch_bounds__(THREADS, FORM < 2 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
+__global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
     constexpr int MAXI = CAP / THREADS;
     constexpr int KBITS = 8 * KB;
     constexpr int IB = CAP <= 4096 ? 12 : CAP <= 8192 ? 13 : 16;  // bits of a position
-    constexpr int DB = IB - 1 - DFR_LOCAL_DB_LESS;                                     // most bin bits
+    constexpr int DB = IB - 1;  // most bin bits
     constexpr int NWORDS = (1 << DB) / 2;  // two 16-bit bin counters per LDS word
     static_assert(CAP % THREADS == 0 && CAP <= (1 << IB), "chunk layout");
     static_assert(CAP < (1 << 16), "a destination and a source share one 32-bit word");
@@ -1378,6 +1357,7 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOC
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
     const uint32_t nwork = *a.nwork < a.workcap ? *a.nwork : a.workcap;
     uint32_t* s_rel = (uint32_t*)s_w;
+    uint32_t sorted = 0;  // chunks this block finished (counted by thread 0)
 
     auto spill = [&](uint32_t item) {
         if (tid == 0) {
@@ -1455,6 +1435,7 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOC
                 }
             }
             __syncthreads();
+            ++sorted;
             continue;
         }
         // Bucket index from the key itself: the buckets' bits >= lo, less the first
@@ -1478,7 +1459,9 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? DFR_LOCAL_MIN_WAVES32 : DFR_LOC
             xs, len, iu, wbase, lane, w, tid, nbk, direct, lo, h, Bw, key0, kin, vin, kout, vout, s_rel,
             (WT*)s_w, s_pos, s_bin, s_part, s_max);
         if (!ok) spill(item);
+        else ++sorted;
     }
+    if (tid == 0 && sorted && a.stat) atomicAdd(&a.stat[STAT_FORM0 + FORM], sorted);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1518,10 +1501,12 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
     (void)nmed;
     uint32_t* s_rel = (uint32_t*)s_c;  // bucket starts, before records are staged
 
+    uint32_t sorted = 0;  // chunks this block sorted (counted by thread 0)
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const uint32_t item = a.spill[it];
         Chunk ch;
         if (!decode_chunk(a, item, nb, CAP, ch)) continue;
+        ++sorted;
         const uint64_t start = ch.start;
         const uint32_t len = ch.len;
         const uint32_t nbk = ch.nbk;
@@ -1697,6 +1682,7 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
         }
         __syncthreads();
     }
+    if (tid == 0 && sorted && a.stat) atomicAdd(&a.stat[STAT_GENERAL], sorted);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1803,44 +1789,6 @@ __global__ __launch_bounds__(256) void k_key_transform(void* keys, uint64_t n, i
 // ---------------------------------------------------------------------------------
 // Tile shapes and launchers.
 // ---------------------------------------------------------------------------------
-// Shapes (overridable at build time for tuning sweeps).
-#ifndef DFR_DEAL_THREADS
-#define DFR_DEAL_THREADS 512
-#endif
-#ifndef DFR_DEAL_TILE_SMALL  // records per deal tile when key + value <= 8 bytes
-#define DFR_DEAL_TILE_SMALL 8192
-#endif
-#ifndef DFR_DEAL_TILE_LARGE  // records per deal tile for 12- and 16-byte records
-#define DFR_DEAL_TILE_LARGE 4096
-#endif
-#ifndef DFR_LOCAL_THREADS
-#define DFR_LOCAL_THREADS 512
-#endif
-#ifndef DFR_LOCAL_CAP_SMALL
-#define DFR_LOCAL_CAP_SMALL 8192
-#endif
-#ifndef DFR_LOCAL_CAP_LARGE
-#define DFR_LOCAL_CAP_LARGE 4096
-#endif
-constexpr int DEAL_THREADS = DFR_DEAL_THREADS;
-constexpr int DEAL_TILE_SMALL = DFR_DEAL_TILE_SMALL;
-constexpr int DEAL_TILE_LARGE = DFR_DEAL_TILE_LARGE;
-#ifndef DFR_COUNT_THREADS
-#define DFR_COUNT_THREADS 256
-#endif
-constexpr int COUNT_THREADS = DFR_COUNT_THREADS;
-constexpr int LOCAL_THREADS = DFR_LOCAL_THREADS;
-constexpr int LOCAL_CAP_SMALL = DFR_LOCAL_CAP_SMALL;
-constexpr int LOCAL_CAP_LARGE = DFR_LOCAL_CAP_LARGE;
-constexpr int COPY_THREADS = 256;
-constexpr int HEAD_THREADS = 512;
-constexpr int GENERAL_THREADS = 256;
-#ifndef DFR_BUCKET_CAP_SMALL  // records per bucketed local-sort chunk (8-byte records)
-#define DFR_BUCKET_CAP_SMALL 5120
-#endif
-#ifndef DFR_BUCKET_CAP_LARGE
-#define DFR_BUCKET_CAP_LARGE 4096
-#endif
 static_assert(DEAL_TILE_SMALL % DEAL_THREADS == 0 && DEAL_TILE_LARGE % DEAL_THREADS == 0, "tile");
 static_assert(DEAL_TILE_SMALL >= DEAL_TILE_LARGE, "head kernel covers the larger tile");
 
@@ -1855,7 +1803,7 @@ uint32_t local_sort_capacity(int kb, int vb) {
     return kb + vb <= 8 ? (uint32_t)LOCAL_CAP_SMALL : (uint32_t)LOCAL_CAP_LARGE;
 }
 uint32_t local_bucket_capacity(int kb, int vb) {
-    return kb + vb <= 8 ? (uint32_t)DFR_BUCKET_CAP_SMALL : (uint32_t)DFR_BUCKET_CAP_LARGE;
+    return kb + vb <= 8 ? (uint32_t)BUCKET_CAP_SMALL : (uint32_t)BUCKET_CAP_LARGE;
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
@@ -2054,7 +2002,7 @@ __global__ __launch_bounds__(RADIX) void k_collisions(const uint32_t* hist, int 
         __syncthreads();
         // Records that estimated buckets of ceil(len / 2^bits) slots would not hold
         // (Fast Radix, Sec. 3.1): the measured counterpart of Eq. 2.
-        const uint32_t m = 1u << bits, cap = (s_len + m - 1) / m;
+        const uint32_t m = 1u << bits, cap = s_len / m + (s_len % m != 0);
         uint32_t ov = v < m && hv > cap ? hv - cap : 0u;
         for (int o = 32; o > 0; o >>= 1) ov += __shfl_xor(ov, o);
         if (lane == 0) s_ov[w] = ov;
@@ -2183,7 +2131,7 @@ hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s
 template <int KB, int VB>
 static void local_kb_vb(const LocalArgs& a, uint32_t blocks, int first_form, hipStream_t s) {
     constexpr int CAP = KB + VB <= 8 ? LOCAL_CAP_SMALL : LOCAL_CAP_LARGE;
-    constexpr int BCAP = KB + VB <= 8 ? DFR_BUCKET_CAP_SMALL : DFR_BUCKET_CAP_LARGE;
+    constexpr int BCAP = KB + VB <= 8 ? BUCKET_CAP_SMALL : BUCKET_CAP_LARGE;
     // A 32-bit form first (first_form 0 or 1), handing chunks that need more to the
     // 64-bit form; or the 64-bit form for every chunk (first_form 2).  Chunks none of
     // them can take go to the general kernel.

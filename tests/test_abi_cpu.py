@@ -183,3 +183,24 @@ def test_size_class_is_log2_of_size_biased_mean():
         dfr.size_class([5, 10])
     with pytest.raises(dfr.DfrError):
         dfr.size_class([0, 10, 5])
+
+
+def test_size_limit_macro_in_expressions(tmp_path):
+    """DFR_MAX_SEGMENT_RECORDS is one parenthesised value (2^32 - 1): it can be used in
+    any C expression."""
+    import subprocess
+    src = tmp_path / "limit.c"
+    src.write_text(
+        '#include <stdio.h>\n#include "dfr.h"\n'
+        "int main(void) {\n"
+        "    size_t x = (size_t)1 << 33;\n"
+        '    printf("%zu %zu %zu\\n", (size_t)(2 * DFR_MAX_SEGMENT_RECORDS),\n'
+        "           (size_t)(x % DFR_MAX_SEGMENT_RECORDS), (size_t)(~DFR_MAX_SEGMENT_RECORDS >> 32));\n"
+        "    return 0;\n}\n")
+    exe = tmp_path / "limit"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    m = (1 << 32) - 1
+    assert [int(v) for v in out] == [2 * m, (1 << 33) % m, ((~m) & ((1 << 64) - 1)) >> 32]
+    assert dfr.MAX_SEGMENT_RECORDS == m

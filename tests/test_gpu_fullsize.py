@@ -89,3 +89,71 @@ def test_batched_full_size(env, dist):
         p = int(rng.integers(a, b))
         assert o.rank_of(keys[a:b], int(ov[p]) - a) == p - a, (s, p)
     print(f"[done] batched {dist}: levels={st['levels']} deal_passes={st['deal_passes']}", flush=True)
+
+
+# The size limit of the boundary.  The paper's largest input, 256^3.75 = 2^30 records
+# (Fig. 1 and Fig. 2): uniform 32-bit keys with the uint32 index payload, checked by the
+# same properties and sampled ranks as above.
+@pytest.mark.timeout(900)
+def test_paper_largest_size(env):
+    torch, dfr, ctx = env
+    o = oracle.get()
+    n = 1 << 30
+    print(f"[case] paper's largest size u32 uniform n={n}: generating", flush=True)
+    keys = workloads.make_keys("uniform", n, 32, 5)
+    vals = workloads.index_payload(n)
+    dk = torch.from_numpy(keys).cuda()
+    dv = torch.from_numpy(vals).cuda()
+    del vals
+    print(f"[case] n={n}: sorting", flush=True)
+    ctx.sort_(dk, dv)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ok, ov = dk.cpu().numpy(), dv.cpu().numpy()
+    del dk, dv
+    torch.cuda.empty_cache()
+    print(f"[case] n={n}: checking", flush=True)
+    assert o.check_index_payload(keys, ok, ov) is None, st
+    rng = np.random.default_rng(n)
+    for p in rng.integers(0, n, size=2):
+        assert o.rank_of(keys, int(ov[p])) == int(p), int(p)
+    print(f"[done] n={n}: levels={st['levels']} deal_passes={st['deal_passes']}", flush=True)
+
+
+# The most records one call accepts, 2^32 - 1: distinct keys k_i = (a i + b) mod 2^32
+# (a odd), so the stable sort is the increasing order of the keys, which is every 32-bit
+# value but the one that index n would have taken; the record holding value x came from
+# index (x - b) / a mod 2^32.  The whole output is checked against that, chunk by chunk,
+# and the rank formula at sampled places.
+@pytest.mark.timeout(900)
+def test_size_limit_records(env):
+    torch, dfr, ctx = env
+    o = oracle.get()
+    n = dfr.MAX_SEGMENT_RECORDS
+    assert n == (1 << 32) - 1
+    print(f"[case] size limit n={n}: generating", flush=True)
+    keys, a, b = workloads.permutation_keys(n, 9)
+    dk = torch.from_numpy(keys).cuda()
+    dv = torch.from_numpy(workloads.index_payload(n)).cuda()
+    print(f"[case] n={n}: sorting", flush=True)
+    ctx.sort_(dk, dv)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ok, ov = dk.cpu().numpy(), dv.cpu().numpy()
+    del dk, dv
+    torch.cuda.empty_cache()
+    print(f"[case] n={n}: checking {st}", flush=True)
+    mask = (1 << 32) - 1
+    missing = (a * n + b) & mask
+    a_inv = pow(a, -1, 1 << 32)
+    step = 1 << 26
+    for lo in range(0, n, step):
+        p = np.arange(lo, min(n, lo + step), dtype=np.uint64)
+        x = p + (p >= np.uint64(missing)).astype(np.uint64)
+        src = ((x - np.uint64(b)) * np.uint64(a_inv)) & np.uint64(mask)
+        assert np.array_equal(ok[lo:lo + p.size], x.astype(np.uint32)), lo
+        assert np.array_equal(ov[lo:lo + p.size], src.astype(np.uint32)), lo
+    rng = np.random.default_rng(3)
+    for q in rng.integers(0, n, size=2):
+        assert o.rank_of(keys, int(ov[q])) == int(q), int(q)
+    print(f"[done] n={n}: levels={st['levels']} deal_passes={st['deal_passes']}", flush=True)

@@ -285,9 +285,11 @@ def test_deal_modes(torch, ctx, o, case, lookback):
         off = workloads.segment_offsets(lens)
         n = int(off[-1])
     else:
-        # One segment over more tiles than a single block scans ahead: the level falls
-        # back to look-back between tiles even with the option off.
-        lens = np.array([5, (1 << 23) + 8192 * 3 + 11, 70000, 0, 9000], dtype=np.int64)
+        # One segment over more tiles than a single block scans ahead, among more
+        # segments than are scanned one by one: the level falls back to look-back
+        # between tiles even with the option off.
+        lens = np.array([5, (1 << 23) + 8192 * 3 + 11, 70000, 0, 9000] + [12000] * 20,
+                        dtype=np.int64)
         off = workloads.segment_offsets(lens)
         n = int(off[-1])
     k = workloads.make_keys("uniform", n, 8 * kb, 31)
@@ -311,6 +313,12 @@ def test_deal_modes(torch, ctx, o, case, lookback):
     else:
         rk, rv = o.segmented_sort(k, v, off)
     assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), st
+    # The intended deal form ran.
+    assert st["deal_passes"] == st["deal_passes_scanned"] + st["deal_passes_lookback"], st
+    if lookback or case == "long_segment":
+        assert st["deal_passes_lookback"] > 0, st
+    else:
+        assert st["deal_passes_lookback"] == 0 and st["deal_passes_scanned"] > 0, st
 
 
 @pytest.mark.parametrize("bits", [32, 64])
@@ -431,6 +439,57 @@ def test_buckets_at_capacity(torch, ctx, o, kb):
     sk, sv, st = gpu_sort(torch, ctx, k, v, force_top_digits=1, divert_records=cap)
     rk, rv = o.stable_sort(k, v)
     assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    # Buckets of C records exceed the bucketed kernels' chunk: the general kernel sorts
+    # them; C + 1 and 2C + 1 recurse.
+    assert st["chunks_general"] >= 2 and st["levels"] >= 2, st
+
+
+FORM_CASES = [
+    # (key bits, payload bits, n, segmented, form expected): the headline shape (two
+    # digits of 32-bit keys dealt: 32-bit words with the position inside); one digit of
+    # 32-bit keys dealt (position beside the words); 64-bit keys (64-bit words).
+    (32, 32, (1 << 22) + 7, False, 0),
+    (32, 32, (1 << 20) + 3, False, 1),
+    (32, 32, None, True, 1),
+    (64, 64, (1 << 21) + 5, False, 2),
+    (32, 0, (1 << 22) + 1, False, 0),
+]
+
+
+@pytest.mark.parametrize("bits,vbits,n,segmented,form", FORM_CASES,
+                         ids=[f"u{b}v{vb}-{n}-{'seg' if g else 'plain'}-form{f}"
+                              for b, vb, n, g, f in FORM_CASES])
+def test_local_sort_forms(torch, ctx, o, bits, vbits, n, segmented, form):
+    """Each form of the bucketed local sort is the one that runs for its shape, and
+    the result matches the oracle."""
+    if segmented:
+        lens = workloads.batch_lengths(200, 16, 1 << 17, 21)
+        off = workloads.segment_offsets(lens)
+        n = int(off[-1])
+    k = workloads.make_keys("uniform", n, bits, 61)
+    v = workloads.index_payload(n, vbits) if vbits else None
+    say("local sort forms", bits, vbits, n, segmented, form)
+    dk = dev(torch, k)
+    dv = dev(torch, v) if v is not None else None
+    if segmented:
+        ctx.sort_segmented_(dk, dv, off)
+    else:
+        ctx.sort_(dk, dv)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    if segmented:
+        rk, rv = o.segmented_sort(k, v, off)
+    else:
+        rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(host(dk), rk), st
+    if v is not None:
+        assert np.array_equal(host(dv), rv), st
+    forms = [st["chunks_form0"], st["chunks_form1"], st["chunks_form2"]]
+    assert forms[form] > 0, st
+    if form < 2:  # the other 32-bit form is never chosen for the same level
+        assert forms[1 - form] == 0, st
+    # Every work item is sorted by exactly one kernel (hand-offs count where they end).
+    assert sum(forms) + st["chunks_general"] == st["chunks"], st
 
 
 @pytest.mark.parametrize("spacing", [1, 2, 3, 4, 16])
@@ -496,6 +555,16 @@ def test_heads_from_counts(torch, ctx, o, bits, n, dist, rb, d):
     assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
     assert np.array_equal(fk, rk) and np.array_equal(fv, rv), ft
     assert st["chunks"] == ft["chunks"] and st["levels"] == ft["levels"], (st, ft)
+    # The forced run found every level's heads from the keys.
+    assert ft["levels_heads_counts"] == 0 and ft["levels_heads_hist"] == 0, ft
+    if st["used_diversion"] and n > 8192:
+        assert ft["levels_heads_keys"] >= 1, ft
+    # The unforced run took the counts (two digits dealt) or histograms (one digit) on
+    # its first level when the plan allowed it.
+    if st["top_digits"] == 2 and st["used_diversion"] and n > 8192 and not rb:
+        assert st["levels_heads_counts"] >= 1, st
+    if st["top_digits"] == 1 and st["used_diversion"] and n > 8192:
+        assert st["levels_heads_hist"] >= 1, st
 
 
 @pytest.mark.parametrize("n,dist", [((1 << 25) + 77, "uniform"), ((1 << 26) + 3, "normal")])
@@ -548,8 +617,18 @@ def test_size_limit(torch, ctx):
     import paper_2207_14334_amd as dfr
     k = dev(torch, np.arange(16, dtype=np.uint32))
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert dfr.MAX_SEGMENT_RECORDS == (1 << 32) - 1
     st = dfr.lib().dfr_sort_u32(ctx._h, k.data_ptr(), None, dfr.MAX_SEGMENT_RECORDS + 1, None, 0, s)
     assert st == dfr.E_TOO_LARGE
+    # The same limit per segment of a segmented sort, and per serving request.
+    off = np.array([0, 3, 3 + (1 << 32)], dtype=np.uint64)
+    st = dfr.lib().dfr_sort_segmented_u32(ctx._h, k.data_ptr(), None, off.ctypes.data, 2, None, 0, s)
+    assert st == dfr.E_TOO_LARGE
+    with pytest.raises(dfr.DfrError) as e:
+        r = dfr.Request(4, 0, k.data_ptr(), None, 1 << 32)
+        t = ctypes.c_uint64(0)
+        ctx._raise(dfr.lib().dfr_submit(ctx._h, ctypes.byref(r), ctypes.byref(t)), "submit")
+    assert e.value.status == dfr.E_TOO_LARGE
     # A misaligned key pointer.
     assert dfr.lib().dfr_sort_u64(ctx._h, k.data_ptr() + 4, None, 2, None, 0, s) == dfr.E_INVALID_ARG
     assert np.array_equal(host(k), np.arange(16, dtype=np.uint32))

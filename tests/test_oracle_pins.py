@@ -248,10 +248,30 @@ def pin_overflow_monte_carlo(o):
     assert abs(o.overflow_fraction(N, 256) / math.sqrt(255 / (2 * math.pi * N)) - 1) < 1e-3
 
 
+def pin_parallel(o):
+    """The multi-threaded variant against numpy's stable argsort (an independent
+    library) on heavy duplicates, for thread counts below, at and above the record
+    count, and on the brute-force alphabet."""
+    rng = np.random.default_rng(17)
+    for n in (0, 1, 2, 5, 64, 1000, 65_537):
+        for threads in (1, 2, 3, 8, 16, 70):
+            k = rng.integers(0, 40, n, dtype=np.uint32)
+            v = workloads.index_payload(n)
+            ref = np.argsort(k, kind="stable")
+            pk, pv = o.stable_sort_parallel(k, v, threads)
+            assert np.array_equal(pv, ref) and np.array_equal(pk, k[ref]), (n, threads)
+    for keys in itertools.product(range(3), repeat=6):
+        k = np.array(keys, dtype=np.uint64)
+        v = workloads.index_payload(k.size, 64)
+        (perm,) = brute_stable_permutation(keys)
+        pk, pv = o.stable_sort_parallel(k, v, 3)
+        assert list(pv) == list(perm), keys
+
+
 ALL_PINS = [pin_bruteforce_small_alphabet, pin_bruteforce_extremes, pin_numpy,
             pin_special_cases, pin_golden, pin_properties, pin_rank_formula,
             pin_typed_golden, pin_typed_numpy, pin_overflow_enumeration,
-            pin_overflow_monte_carlo]
+            pin_overflow_monte_carlo, pin_parallel]
 
 
 # --------------------------------------------------------------------------------------
@@ -355,7 +375,8 @@ def test_checker_catches_each_broken_property(o):
 
 MUTANTS = ["ORACLE_PLANT_REVERSED_TIES", "ORACLE_PLANT_SIGNED_COMPARE",
            "ORACLE_PLANT_DROP_LAST", "ORACLE_PLANT_INCLUSIVE_SCAN",
-           "ORACLE_PLANT_FLOAT_NO_REVERSE", "ORACLE_PLANT_OVERFLOW_EXTRA_TERM"]
+           "ORACLE_PLANT_FLOAT_NO_REVERSE", "ORACLE_PLANT_OVERFLOW_EXTRA_TERM",
+           "ORACLE_PLANT_MERGE_RIGHT_FIRST"]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS)

@@ -53,3 +53,16 @@ def test_request_stream_mix():
     assert abs(wide - 0.3) < 0.04 and abs(zipf - 0.5) < 0.04
     arrive = np.array([r[0] for r in s])
     assert np.all(np.diff(arrive) >= 0) and arrive[0] == 0.0
+
+
+def test_permutation_keys_are_distinct_and_invertible():
+    """k_i = (a i + b) mod 2^32 with a odd: distinct keys, and the index of a key is
+    recovered as (k - b) a^-1 mod 2^32 (what the size-limit test relies on)."""
+    n = 1 << 18
+    k, a, b = workloads.permutation_keys(n, 9)
+    assert a % 2 == 1 and np.unique(k).size == n
+    a_inv = pow(a, -1, 1 << 32)
+    idx = ((k.astype(np.uint64) - np.uint64(b)) * np.uint64(a_inv)) & np.uint64(0xFFFFFFFF)
+    assert np.array_equal(idx, np.arange(n, dtype=np.uint64))
+    k2, a2, b2 = workloads.permutation_keys(n, 9)
+    assert np.array_equal(k, k2) and (a, b) == (a2, b2)

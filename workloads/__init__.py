@@ -112,6 +112,23 @@ def make_keys(dist: str, n: int, key_bits: int = 32, seed: int = 0, *,
     raise ValueError(f"unknown distribution {dist!r}")
 
 
+def permutation_keys(n: int, seed: int = 0) -> tuple[np.ndarray, int, int]:
+    """``n`` <= 2^32 distinct uint32 keys k_i = (a * i + b) mod 2^32 with a odd (a
+    bijection of the 32-bit values, so the keys are distinct), a and b drawn from the
+    seed; returns (keys, a, b).  Built in chunks, for inputs up to the 32-bit limit."""
+    if n > 1 << 32:
+        raise ValueError("at most 2^32 distinct 32-bit keys")
+    rng = _rng(seed, 3)
+    a = int(rng.integers(0, 1 << 31)) * 2 + 1
+    b = int(rng.integers(0, 1 << 32))
+    out = np.empty(n, dtype=np.uint32)
+    step = 1 << 26
+    for lo in range(0, n, step):
+        i = np.arange(lo, min(n, lo + step), dtype=np.uint64)
+        out[lo:lo + i.size] = ((i * np.uint64(a) + np.uint64(b)) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    return out, a, b
+
+
 def index_payload(n: int, val_bits: int = 32) -> np.ndarray:
     """The payload v_i = i, which makes the stable sort checkable by its properties."""
     return np.arange(n, dtype=np.uint32 if val_bits == 32 else np.uint64)
