@@ -650,3 +650,28 @@ def test_lookback_determinism(torch, ctx, o):
             first = (sk, sv)
         assert np.array_equal(sk, first[0]) and np.array_equal(sv, first[1])
     assert o.check_index_payload(k, first[0], first[1]) is None
+
+
+def test_calls_on_different_streams(torch, ctx, o):
+    """Consecutive calls on one context from different streams, with no host wait
+    between them: a 256-distinct-value sort (its last buckets copied back from the temp
+    buffer after the call's last read-back) on stream A, then sorts on stream B that
+    reuse the same scratch and temp buffer; every result matches the oracle."""
+    n = (1 << 22) + 17
+    ka = workloads.make_keys("few", n, 32, 71)
+    kb = workloads.make_keys("uniform", n, 32, 72)
+    v = workloads.index_payload(n)
+    ra, rb = o.stable_sort(ka, v), o.stable_sort(kb, v)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):
+        say("streams in turn", rep)
+        da, dva, db, dvb = dev(torch, ka), dev(torch, v), dev(torch, kb), dev(torch, v)
+        torch.cuda.synchronize()
+        ctx.sort_(da, dva, stream=sa)
+        ctx.sort_(db, dvb, stream=sb)
+        ctx.sort_(dva, None, stream=sa)  # a third call back on A, on A's first result
+        sa.synchronize()
+        sb.synchronize()
+        assert np.array_equal(host(da), ra[0]), rep
+        assert np.array_equal(host(dva), np.sort(ra[1])), rep
+        assert np.array_equal(host(db), rb[0]) and np.array_equal(host(dvb), rb[1]), rep

@@ -170,3 +170,30 @@ def test_plain_calls_beside_serving(torch, o):
             assert np.array_equal(dk.cpu().numpy(), rk)
             if v is not None:
                 assert np.array_equal(dv.cpu().numpy(), rv)
+
+
+def test_mix_at_full_request_sizes(torch, o):
+    """Requests of the serving workload's full size range, log-uniform in [2^10, 2^24],
+    with requests of exactly the default batch limit (2^25 records) and one past it (a
+    batch of its own, sorted in place), all queued at once; each result is the oracle's
+    (checked by the properties that single out the stable sort under the index payload,
+    and the rank formula at a sampled place)."""
+    import paper_2207_14334_amd as dfr
+    reqs = make_requests(24, 5, lo=1 << 10, hi=1 << 24, key_only_every=0)
+    for extra, bits in (((1 << 25), 32), ((1 << 25) + 1, 32), ((1 << 24), 64)):
+        reqs.append((workloads.make_keys("uniform", extra, bits, extra + bits),
+                     workloads.index_payload(extra, bits)))
+    say("serving full sizes", len(reqs), sum(k.size for k, _ in reqs))
+    with dfr.Context(0) as ctx:
+        dev = [(torch.from_numpy(k).cuda(), torch.from_numpy(v).cuda()) for k, v in reqs]
+        torch.cuda.synchronize()
+        tickets = [ctx.submit(k, v) for k, v in dev]
+        wait_all(ctx, tickets, timeout_s=120.0)
+        st = ctx.serve_stats()
+        assert st["requests"] == len(reqs), st
+        rng = np.random.default_rng(5)
+        for (k, v), (dk, dv) in zip(reqs, dev):
+            ok, ov = dk.cpu().numpy(), dv.cpu().numpy()
+            assert o.check_index_payload(k, ok, ov) is None, k.size
+            p = int(rng.integers(0, k.size))
+            assert o.rank_of(k, int(ov[p])) == p, (k.size, p)
