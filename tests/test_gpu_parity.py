@@ -446,13 +446,14 @@ def test_buckets_at_capacity(torch, ctx, o, kb):
 
 FORM_CASES = [
     # (key bits, payload bits, n, segmented, form expected): the headline shape (two
-    # digits of 32-bit keys dealt: 32-bit words with the position inside); one digit of
-    # 32-bit keys dealt (position beside the words); 64-bit keys (64-bit words).
-    (32, 32, (1 << 22) + 7, False, 0),
+    # digits of 32-bit keys dealt, buckets of ~1024 records or more: 32-bit words with
+    # the position inside); one digit of 32-bit keys dealt (position beside the words);
+    # 64-bit keys (64-bit words).
+    (32, 32, (1 << 26) + 7, False, 0),
     (32, 32, (1 << 20) + 3, False, 1),
     (32, 32, None, True, 1),
     (64, 64, (1 << 21) + 5, False, 2),
-    (32, 0, (1 << 22) + 1, False, 0),
+    (32, 0, (1 << 26) + 1, False, 0),
 ]
 
 
@@ -479,11 +480,19 @@ def test_local_sort_forms(torch, ctx, o, bits, vbits, n, segmented, form):
     st = ctx.stats()
     if segmented:
         rk, rv = o.segmented_sort(k, v, off)
+        assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), st
+    elif n > 1 << 24 and v is not None:  # the stable sort's properties, sampled ranks
+        sk, sv = host(dk), host(dv)
+        assert o.check_index_payload(k, sk, sv) is None, st
+        for p in np.random.default_rng(n).integers(0, n, size=2):
+            assert o.rank_of(k, int(sv[p])) == int(p), int(p)
+    elif n > 1 << 24:  # keys only: the sorted multiset (numpy, an independent library)
+        assert np.array_equal(host(dk), np.sort(k)), st
     else:
         rk, rv = o.stable_sort(k, v)
-    assert np.array_equal(host(dk), rk), st
-    if v is not None:
-        assert np.array_equal(host(dv), rv), st
+        assert np.array_equal(host(dk), rk), st
+        if v is not None:
+            assert np.array_equal(host(dv), rv), st
     forms = [st["chunks_form0"], st["chunks_form1"], st["chunks_form2"]]
     assert forms[form] > 0, st
     if form < 2:  # the other 32-bit form is never chosen for the same level
