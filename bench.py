@@ -1,30 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the DFR sort hot path on one MI355X.
 
-Workloads (``--workload``):
+Default run (``--workload all``): one JSON line whose headline is the plain sort below,
+with the rest of the metric beside it:
 
-* ``plain`` (default) -- the headline configuration, below.
-* ``batched`` -- 20,000 independent uint32 arrays with lengths log-uniform in
-  [16, --max-len] (default 2^20) and a uint32 index payload, sorted by one segmented
-  call after the autotuner has picked its launch settings on the same data; the same
-  arrays sorted by one plain call each are timed beside it.
-* ``serving`` -- a Poisson stream of sort requests (sizes log-uniform in
-  [2^10, 2^24], 70% uint32 / 30% uint64 keys with a payload of the key's width,
-  uniform or Zipf keys), offered at a load rho of the mean service time of one plain
-  call (0.3 to 0.9, and 1.2 and 1.5 beyond what plain calls can serve), served (a) by
-  FIFO plain calls on one stream and (b) by the context's request queue (dfr_submit /
-  dfr_poll: continuous batching into segmented sorts) under a 32 GiB HBM budget.
-  Latency is arrival to completion; p50/p99 and throughput for both.
+* ``value`` -- plain DFR sort of 2^28 uint32 keys, i.i.d. uniform over [0, 2^32), with a
+  uint32 index payload; every step sorts its own resident copy of one of three inputs
+  (seeds 0, 1, 2, in turn), and ``value`` is the keys sorted over the timed steps' time.
+  Per-seed rates are in ``value_by_seed``.
+* ``roofline`` -- the deal kernel (the dominant pass): algorithmic bytes per launch over
+  its mean launch time from HIP events on the sort's stream during the timed steps;
+  ``copy_ceiling`` -- the library's own streaming copy kernel on 4 GiB, the rate the
+  read-once/write-once passes can reach.
+* ``cpu_baseline`` -- the CPU oracle on the host: all cores on the full 2^28 input of
+  seed 0, and single-threaded on three 2^24 samples.
+* ``c1`` -- 2^20 uint32 keys, key-only: wall latency of one call.
+* ``normal`` -- the 2^28 sort on the normal distribution (mean 2^31, sd 2^28).
+* ``batched`` -- 20,000 uint32 arrays, lengths log-uniform in [16, 2^20] (1.9e9 keys),
+  uniform and Zipf(1.1) keys with the global index as payload: one tuned segmented call
+  against one plain call per array, with a per-segment check of sampled arrays.
+* ``serving`` -- 2,000 Poisson sort requests (sizes log-uniform in [2^10, 2^24], 70%
+  uint32 / 30% uint64 keys with a payload of the key's width, half uniform, half Zipf)
+  at offered loads 0.7 and 0.9 of one plain call's mean service time: FIFO plain calls
+  against the request queue's continuous batching, p50/p99 latency and throughput.
 
-Plain workload: one step = one plain DFR sort (count, deals of the top digits, bucket finding, local
-sort of runs of small buckets, recursion if any) of 2^28 uint32 keys drawn i.i.d.
-uniform over [0, 2^32) with a uint32 index payload, seed 0.  Every step sorts its own
-copy of that input, made resident in HBM before the timed region starts, so the timed
-region holds nothing but the sorts.
-
-Printed: ONE JSON line with the throughput (Gkeys/s), the roofline of the dominant
-kernel (the deal pass) from HIP events recorded around its launches during the timed
-region, and the CPU oracle timed on a bounded sample of the same workload.
+``--workload plain|batched|serving`` runs one part alone (the first with --log2n,
+--dist, --key-type and --set OPTION=VALUE for other shapes); batched and serving inputs
+are drawn on the GPU (seeded), the plain inputs with numpy.
 """
 from __future__ import annotations
 
@@ -84,11 +86,24 @@ def check_result(keys_in, keys_out, vals_out):
     return "pass"
 
 
-def cpu_baseline(dist, log2n_sample=24, seeds=(0, 1, 2)):
-    """The CPU oracle (single-threaded C stable sort) on a bounded sample."""
+def cpu_baseline(keys_full, dist="uniform", log2n_sample=24, seeds=(0, 1, 2)):
+    """The CPU oracle on the host: all cores (chunked stable sort, then a stable merge
+    tree) on the full input, and one thread on bounded samples of the same workload."""
+    import numpy as np
+
     import oracle
     import workloads
     o = oracle.get()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    threads = max(1, min(16, cores))
+    vals = workloads.index_payload(keys_full.size)
+    t0 = time.perf_counter()
+    o.stable_sort_parallel(keys_full, vals, threads)
+    par_s = time.perf_counter() - t0
+    del vals
     total_keys, total_s = 0, 0.0
     for seed in seeds:
         k = workloads.make_keys(dist, 1 << log2n_sample, 32, seed)
@@ -98,37 +113,46 @@ def cpu_baseline(dist, log2n_sample=24, seeds=(0, 1, 2)):
         total_s += time.perf_counter() - t0
         total_keys += k.size
     return {
-        "value": round(total_keys / total_s / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+        "value": round(keys_full.size / par_s / 1e9, 5), "unit": "Gkeys/s", "cores": threads,
         "kind": "oracle",
-        "sample": f"{len(seeds)} x 2^{log2n_sample} {dist} uint32 keys with uint32 index "
-                  f"payload (seeds {list(seeds)}), single-threaded, {total_s:.1f} s",
+        "sample": f"the full 2^{int(np.log2(keys_full.size))} {dist} uint32 input of seed 0 with "
+                  f"its uint32 index payload, {threads} threads (chunks sorted by (key, index), "
+                  f"then a stable pairwise merge tree), {par_s:.1f} s",
+        "hardware_concurrency": os.cpu_count(),
+        "single_thread": {
+            "value": round(total_keys / total_s / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+            "sample": f"{len(seeds)} x 2^{log2n_sample} {dist} uint32 keys with uint32 index "
+                      f"payload (seeds {list(seeds)}), {total_s:.1f} s"},
     }
 
 
-def copy_ceiling(torch, gib=4, reps=5):
-    """The achievable HBM ceiling for comparison: a device-to-device copy of `gib` GiB
-    by the runtime (read + write bytes over the copy's time, median of `reps`)."""
+def copy_ceiling(torch, ctx, gib=4, reps=5):
+    """The library's streaming copy kernel on `gib` GiB (read + write bytes over its time
+    from HIP events on its stream, median of `reps`): what a pass that reads and writes
+    every byte once can reach on this GPU."""
     import numpy as np
     n = (gib << 30) // 4
     src = torch.empty(n, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1)
-    dst.copy_(src)
+    ctx.stream_copy(src, dst)
     torch.cuda.synchronize()
     ms = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        dst.copy_(src)
+        ctx.stream_copy(src, dst)
         e1.record()
         e1.synchronize()
         ms.append(e0.elapsed_time(e1))
+    ok = bool(torch.equal(src, dst))
     del src, dst
     torch.cuda.empty_cache()
     t = float(np.median(ms))
     gbs = 2 * (gib << 30) / (t * 1e-3) / 1e9
-    return {"bytes_copied": gib << 30, "ms": round(t, 4), "GB/s": round(gbs, 1),
-            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    return {"kernel": "k_stream_copy", "bytes_copied": gib << 30, "ms": round(t, 4),
+            "GB/s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "copy_correct": ok}
 
 
 def check_segments(keys_in, keys_out, vals_out, off, segs):
@@ -141,24 +165,26 @@ def check_segments(keys_in, keys_out, vals_out, off, segs):
     return "pass"
 
 
-def run_batched(args):
-    """Batched segmented sort against one plain call per array."""
+def host_np(t):
+    """A uint32/uint64 GPU tensor as a numpy array of the same unsigned type."""
     import numpy as np
     import torch
+    if t.dtype == torch.uint32:
+        return t.view(torch.int32).cpu().numpy().view(np.uint32)
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)
 
-    import oracle
-    import paper_2207_14334_amd as dfr
+
+def batched_part(torch, dfr, dist, arrays, max_len, steps, plain_runs=1):
+    """One tuned segmented call over the batch against one plain call per array."""
+    import numpy as np
+
     import workloads
-
-    torch.cuda.set_device(0)
-    lens = workloads.batch_lengths(args.arrays, 16, args.max_len, 0)
+    lens = workloads.batch_lengths(arrays, 16, max_len, 0)
     off = workloads.segment_offsets(lens)
     n = int(off[-1])
-    log(f"generating {args.arrays} arrays, {n} {args.dist} keys")
-    keys_h = workloads.make_keys(args.dist, n, 32, 0)
-    vals_h = workloads.index_payload(n)
-    base_k = torch.from_numpy(keys_h).cuda()
-    base_v = torch.from_numpy(vals_h).cuda()
+    log(f"batched {dist}: drawing {n} keys on the GPU")
+    base_k = workloads.make_keys_device(dist, n, 32, 0)
+    base_v = workloads.index_payload_device(n, 32)
     k = torch.empty_like(base_k)
     v = torch.empty_like(base_v)
     temp = torch.empty(dfr.temp_bytes(n, 4, 4), dtype=torch.uint8, device="cuda")
@@ -176,28 +202,21 @@ def run_batched(args):
         return ev[0].elapsed_time(ev[1])
 
     tune = ctx.autotune(base_k, base_v, off, reps=1)
-    log(f"autotune: {tune}")
-    for _ in range(args.warmup):
-        timed_segmented()
-    times = [timed_segmented() for _ in range(args.steps)]
-    ctx.set_option("timing", 1)
+    log(f"batched {dist}: autotune {tune}")
     timed_segmented()
-    stages = ctx.stats()
-    ctx.set_option("timing", 0)
+    times = [timed_segmented() for _ in range(steps)]
+    st = ctx.stats()
     ms = float(np.median(times))
     gkeys = n / (ms * 1e-3) / 1e9
-    log(f"segmented: median {ms:.2f} ms over {args.steps}, {gkeys:.2f} Gkeys/s")
-    k_out, v_out = k.cpu().numpy(), v.cpu().numpy()
+    log(f"batched {dist}: segmented median {ms:.2f} ms, {gkeys:.2f} Gkeys/s")
     rng = np.random.default_rng(1)
     sample = sorted(set(rng.integers(0, lens.size, 200).tolist()) | {int(np.argmax(lens))})
-    parity = check_segments(keys_h, k_out, v_out, off, sample)
-    log(f"result check on {len(sample)} segments: {parity}")
-    del k_out, v_out
-
-    # One plain call per array, on the same stream, the host waiting on nothing but
-    # what each call itself waits for.
+    kin_h, kout_h, vout_h = host_np(base_k), host_np(k), host_np(v)
+    parity = check_segments(kin_h, kout_h, vout_h, off, sample)
+    del kin_h, kout_h, vout_h
+    log(f"batched {dist}: check of {len(sample)} segments: {parity}")
     plain = []
-    for _ in range(args.plain_runs):
+    for _ in range(plain_runs):
         k.copy_(base_k)
         v.copy_(base_v)
         torch.cuda.synchronize()
@@ -208,72 +227,41 @@ def run_batched(args):
         torch.cuda.synchronize()
         plain.append((time.perf_counter() - t0) * 1e3)
     plain_ms = min(plain)
-    log(f"plain calls: {plain_ms:.1f} ms, {n / plain_ms / 1e6:.3f} Gkeys/s")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        o = oracle.get()
-        m = int(np.searchsorted(off, 1 << 24))  # first arrays, about 2^24 keys
-        t0 = time.perf_counter()
-        o.segmented_sort(keys_h[: off[m]], vals_h[: off[m]], off[: m + 1])
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(int(off[m]) / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"the first {m} arrays ({int(off[m])} keys) of the same batch, "
-                         f"single-threaded, {dt:.1f} s"}
-
-    out = {
-        "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"batched segmented sort of {args.arrays} uint32 arrays, "
-                               f"lengths log-uniform in [16, {args.max_len}], {args.dist} "
-                               f"keys, uint32 index payload, seed 0",
-                   "n": n, "arrays": int(lens.size), "max_len": args.max_len,
-                   "distribution": args.dist, "parallelism": "single GPU"},
-        "plain_calls": {"ms": round(plain_ms, 2), "gkeys_per_s": round(n / plain_ms / 1e6, 4),
-                        "speedup_of_batched": round(plain_ms / ms, 2)},
-        "tune": tune, "untuned_ms": round(tune["ms_default"], 4),
-        "stage_ms": {kk: round(vv, 4) for kk, vv in stages.items() if kk.startswith("ms_")},
-        "plan": {kk: stages[kk] for kk in ("levels", "top_digits", "deal_passes", "large_buckets")},
-        "cpu_baseline": cpu,
-        "result_check": parity,
-    }
-    print(json.dumps(out), flush=True)
+    log(f"batched {dist}: plain calls {plain_ms:.1f} ms")
     ctx.close()
-    if parity != "pass":
-        sys.exit(1)
+    del base_k, base_v, k, v, temp
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{arrays} uint32 arrays, lengths log-uniform in [16, {max_len}], {dist} keys, "
+                    f"uint32 global-index payload, seed 0",
+        "n": n, "segmented_ms": round(ms, 3), "gkeys_per_s": round(gkeys, 3),
+        "untuned_ms": round(tune["ms_default"], 3),
+        "tune": {kk: tune[kk] for kk in ("radix_bits", "tile_records", "divert_records", "window_records")},
+        "plain_calls_ms": round(plain_ms, 1),
+        "plain_calls_gkeys_per_s": round(n / plain_ms / 1e6, 4),
+        "speedup_over_plain_calls": round(plain_ms / ms, 1),
+        "plan": {kk: st[kk] for kk in ("levels", "top_digits", "deal_passes", "large_buckets")},
+        "result_check": parity, "segments_checked": len(sample),
+    }
 
 
-def run_serving(args):
+def serving_part(torch, dfr, requests, rhos, budget_gib):
     """Poisson request stream: FIFO plain calls against the batching request queue."""
     import threading
 
     import numpy as np
-    import torch
 
-    import paper_2207_14334_amd as dfr
     import workloads
-
-    torch.cuda.set_device(0)
-    stream = workloads.request_stream(args.requests, 1.0, 1 << 10, 1 << 24, 0.3, 0.5, 0)
-    unit_arrivals = np.array([a for a, _, _, _ in stream])  # at rate 1 per second
-    log(f"generating {len(stream)} requests, {sum(r[1] for r in stream)} keys")
-    from concurrent.futures import ThreadPoolExecutor
-
-    def gen(i):
-        _, n, bits, dist = stream[i]
-        return workloads.make_keys(dist, n, bits, 1000 + i), workloads.index_payload(n, bits)
-
+    stream_def = workloads.request_stream(requests, 1.0, 1 << 10, 1 << 24, 0.3, 0.5, 0)
+    unit_arrivals = np.array([a for a, _, _, _ in stream_def])  # at rate 1 per second
+    total_keys = sum(r[1] for r in stream_def)
+    log(f"serving: drawing {len(stream_def)} requests, {total_keys} keys on the GPU")
     base, work = [], []
-    with ThreadPoolExecutor(8) as ex:  # numpy draws release the GIL
-        for kh, vh in ex.map(gen, range(len(stream))):
-            k = torch.from_numpy(kh).cuda()
-            v = torch.from_numpy(vh).cuda()
-            base.append((k, v))
-            work.append((torch.empty_like(k), torch.empty_like(v)))
-    total_keys = sum(r[1] for r in stream)
+    for i, (_, n, bits, dist) in enumerate(stream_def):
+        k = workloads.make_keys_device(dist, n, bits, 1000 + i)
+        v = workloads.index_payload_device(n, bits)
+        base.append((k, v))
+        work.append((torch.empty_like(k), torch.empty_like(v)))
     torch.cuda.synchronize()
 
     def reset():
@@ -282,8 +270,7 @@ def run_serving(args):
             wv.copy_(bv)
         torch.cuda.synchronize()
 
-    ctx = dfr.Context(0, hbm_budget_bytes=args.budget_gib << 30)
-    # Mean service time of one plain call: the whole stream back to back.
+    ctx = dfr.Context(0, hbm_budget_bytes=budget_gib << 30)
     sys.setswitchinterval(2e-4)  # the submitting thread must not wait long for the GIL
     reset()
     for i in range(min(len(work), 30)):
@@ -294,7 +281,7 @@ def run_serving(args):
         ctx.sort_(k, v)
     torch.cuda.synchronize()
     svc_mean = (time.perf_counter() - t0) / len(work)
-    log(f"plain call: {svc_mean * 1e3:.3f} ms mean over the stream")
+    log(f"serving: plain call {svc_mean * 1e3:.3f} ms mean over the stream")
 
     def spin_until(t):
         while True:
@@ -322,7 +309,6 @@ def run_serving(args):
         tickets = [None] * n
         sub_delay = np.zeros(n)
         lat = np.full(n, np.nan)
-        submitted = threading.Event()
         t0 = time.perf_counter() + 0.01
 
         def submitter():
@@ -330,7 +316,6 @@ def run_serving(args):
                 spin_until(t0 + arrive[i])
                 sub_delay[i] = time.perf_counter() - (t0 + arrive[i])
                 tickets[i] = ctx.submit(k, v)
-            submitted.set()
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -350,20 +335,20 @@ def run_serving(args):
         end = max(arrive[i] + lat[i] for i in range(n))
         return lat, end
 
-    # Warm the serving workers up as the plain calls were warmed up: the largest
-    # requests of each width once, so that their buffers exist before the timed runs.
+    # Warm the workers up as the plain calls were: the largest requests of each width
+    # once, so that their buffers exist before the timed runs.
     reset()
     warm = []
     for bits in (32, 64):
-        idx = [i for i, r in enumerate(stream) if r[2] == bits]
-        for i in sorted(idx, key=lambda i: -stream[i][1])[:4]:
+        idx = [i for i, r in enumerate(stream_def) if r[2] == bits]
+        for i in sorted(idx, key=lambda i: -stream_def[i][1])[:4]:
             warm.append(ctx.submit(*work[i]))
     for t in warm:
         while not ctx.poll(t)[0]:
             time.sleep(1e-4)
-    out_rho = {}
+    by_rho = {}
     st0 = ctx.serve_stats()
-    for rho in args.rho:
+    for rho in rhos:
         arrive = unit_arrivals * svc_mean / rho
         lat_p, span_p = fifo(arrive)
         lat_s, span_s = served(arrive)
@@ -381,60 +366,123 @@ def run_serving(args):
         }
         r["p99_ratio_plain_over_served"] = round(r["fifo_plain"]["p99_ms"] / r["served"]["p99_ms"], 3)
         st0 = st
-        out_rho[str(rho)] = r
-        log(f"rho {rho}: {json.dumps(r)}")
-
-    # Results of the last served run: each request sorted (properties of the stable
-    # sort under the index payload) on a sample.
+        by_rho[str(rho)] = r
+        log(f"serving rho {rho}: {json.dumps(r)}")
+    # The last served run's results: each sampled request sorted (the stable sort's
+    # properties under the index payload).
     rng = np.random.default_rng(3)
     parity = "pass"
     for i in sorted(set(rng.integers(0, len(work), 40).tolist())):
-        kin = base[i][0].cpu().numpy()
-        r = check_result(kin, work[i][0].cpu().numpy(), work[i][1].cpu().numpy())
+        r = check_result(host_np(base[i][0]), host_np(work[i][0]), host_np(work[i][1]))
         if r != "pass":
             parity = f"request {i}: {r}"
             break
-    head = out_rho[str(args.rho[-1] if 0.7 not in args.rho else 0.7)]
     out = {
-        "metric": METRIC, "value": head["served"]["gkeys_per_s"], "unit": "Gkeys/s",
-        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
-        "config": {"workload": f"serving: {len(stream)} Poisson sort requests, sizes log-uniform "
-                               f"in [2^10, 2^24], 70% uint32 / 30% uint64 keys with payload, "
-                               f"50% uniform / 50% Zipf, HBM budget {args.budget_gib} GiB",
-                   "requests": len(stream), "keys": total_keys,
-                   "plain_call_ms_mean": round(svc_mean * 1e3, 4), "headline_rho": 0.7,
-                   "parallelism": "single GPU"},
-        "p50_ms": head["served"]["p50_ms"], "p99_ms": head["served"]["p99_ms"],
-        "p99_plain_fifo_ms": head["fifo_plain"]["p99_ms"],
-        "by_rho": out_rho, "serve_stats": ctx.serve_stats(), "result_check": parity,
+        "workload": f"{len(stream_def)} Poisson sort requests, sizes log-uniform in [2^10, 2^24], "
+                    f"70% uint32 / 30% uint64 keys with a payload of the key's width, 50% uniform / "
+                    f"50% Zipf(1.1), HBM budget {budget_gib} GiB",
+        "requests": len(stream_def), "keys": total_keys,
+        "plain_call_ms_mean": round(svc_mean * 1e3, 4), "by_rho": by_rho,
+        "serve_stats": {kk: vv for kk, vv in ctx.serve_stats().items()
+                        if kk in ("batches", "requests", "max_batch_requests", "peak_held_bytes",
+                                  "allocs")},
+        "result_check": parity, "requests_checked": 40,
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
-    if parity != "pass":
-        sys.exit(1)
+    del base, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def c1_part(torch, dfr, calls=50):
+    """2^20 uint32 keys, key-only (small enough to stay in the caches): wall time of one
+    call, from its start to the end of its work on the stream."""
+    import numpy as np
+
+    import workloads
+    n = 1 << 20
+    keys_h = workloads.make_keys("uniform", n, 32, 0)
+    base = torch.from_numpy(keys_h).cuda()
+    copies = [base.clone() for _ in range(calls + 5)]
+    ctx = dfr.Context(0)
+    torch.cuda.synchronize()
+    for i in range(5):
+        ctx.sort_(copies[i])
+    torch.cuda.synchronize()
+    wall = []
+    for i in range(5, calls + 5):
+        t0 = time.perf_counter()
+        ctx.sort_(copies[i])
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e3)
+    st = ctx.stats()
+    ok = np.array_equal(host_np(copies[-1]), np.sort(keys_h))
+    ctx.close()
+    w = np.array(wall)
+    return {"workload": "2^20 uint32 keys, uniform, key-only, seed 0", "n": n,
+            "latency_ms": {"median": round(float(np.median(w)), 4), "min": round(float(w.min()), 4),
+                           "p90": round(float(np.percentile(w, 90)), 4)},
+            "gkeys_per_s": round(n / np.median(w) / 1e6, 3), "calls": calls,
+            "plan": {kk: st[kk] for kk in ("levels", "top_digits", "deal_passes")},
+            "result_check": "pass" if ok else "keys differ from numpy's sort"}
+
+
+def dist_part(torch, dfr, dist, log2n=28, steps=3):
+    """The plain 2^log2n uint32 + index payload sort on another distribution."""
+    import numpy as np
+
+    import workloads
+    n = 1 << log2n
+    keys_h = workloads.make_keys(dist, n, 32, 0)
+    base_k = torch.from_numpy(keys_h).cuda()
+    base_v = torch.from_numpy(workloads.index_payload(n)).cuda()
+    k, v = torch.empty_like(base_k), torch.empty_like(base_v)
+    temp = torch.empty(dfr.temp_bytes(n, 4, 4), dtype=torch.uint8, device="cuda")
+    ctx = dfr.Context(0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for i in range(steps + 1):
+        k.copy_(base_k)
+        v.copy_(base_v)
+        ev[0].record()
+        ctx.sort_(k, v, temp)
+        ev[1].record()
+        torch.cuda.synchronize()
+        if i:
+            times.append(ev[0].elapsed_time(ev[1]))
+    st = ctx.stats()
+    parity = check_result(keys_h, host_np(k), host_np(v))
+    ctx.close()
+    del base_k, base_v, k, v, temp
+    torch.cuda.empty_cache()
+    ms = float(np.median(times))
+    return {"workload": f"2^{log2n} uint32 keys, {dist}, uint32 index payload, seed 0", "n": n,
+            "ms": round(ms, 4), "gkeys_per_s": round(n / ms / 1e6, 3),
+            "plan": {kk: st[kk] for kk in ("levels", "top_digits", "deal_passes", "large_buckets")},
+            "result_check": parity}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("plain", "batched", "serving"), default="plain")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=("all", "plain", "batched", "serving"), default="all")
     ap.add_argument("--requests", type=int, default=2000)
-    ap.add_argument("--rho", type=float, nargs="+", default=[0.3, 0.5, 0.7, 0.9, 1.2, 1.5])
+    ap.add_argument("--rho", type=float, nargs="+", default=None,
+                    help="offered loads of the serving part (default 0.7 0.9; alone 0.3 .. 1.5)")
     ap.add_argument("--budget-gib", type=int, default=32)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--dist", default="uniform")
     ap.add_argument("--arrays", type=int, default=20000)
     ap.add_argument("--max-len", type=int, default=1 << 20)
-    ap.add_argument("--plain-runs", type=int, default=2)
     ap.add_argument("--key-type", default="u32", choices=("u32", "u64", "i32", "i64", "f32", "f64"))
     ap.add_argument("--set", action="append", default=[], metavar="OPTION=VALUE",
                     help="a library option (dfr_set_option) for the plain workload")
+    ap.add_argument("--seeds", type=int, default=3, help="inputs the plain steps cycle through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true",
-                    help="skip the runtime copy timing (profiling runs calibrate on the input copies)")
+                    help="skip the copy-kernel timing (profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -442,39 +490,62 @@ def main():
                                    "multi-GPU path (histogram all-reduce, splitters, "
                                    "all-to-all exchange) is not built"}), flush=True)
         sys.exit(2)
-    if args.workload == "batched":
-        return run_batched(args)
-    if args.workload == "serving":
-        return run_serving(args)
-    return run_plain(args)
-
-
-def run_plain(args):
-    import numpy as np
     import torch
 
     import paper_2207_14334_amd as dfr
+    torch.cuda.set_device(0)
+    wall0 = time.perf_counter()
+    if args.workload == "batched":
+        out = {"batched": [batched_part(torch, dfr, d, args.arrays, args.max_len, args.steps, 2)
+                           for d in (("uniform", "zipf") if args.dist == "uniform" else (args.dist,))]}
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "serving":
+        rhos = args.rho or [0.3, 0.5, 0.7, 0.9, 1.2, 1.5]
+        print(json.dumps({"serving": serving_part(torch, dfr, args.requests, rhos, args.budget_gib)}),
+              flush=True)
+        return
+    out = run_plain(args, torch, dfr)
+    ok = out["result_check"] == "pass"
+    if args.workload == "all":
+        out["c1"] = c1_part(torch, dfr)
+        log(f"c1: {out['c1']}")
+        out["normal"] = dist_part(torch, dfr, "normal")
+        log(f"normal: {out['normal']}")
+        out["batched"] = [batched_part(torch, dfr, d, args.arrays, args.max_len, 3)
+                          for d in ("uniform", "zipf")]
+        out["serving"] = serving_part(torch, dfr, args.requests, args.rho or [0.7, 0.9],
+                                      args.budget_gib)
+        ok = ok and all(p["result_check"] == "pass" for p in
+                        [out["c1"], out["normal"], out["serving"], *out["batched"]])
+    out["wall_s"] = round(time.perf_counter() - wall0, 1)
+    print(json.dumps(out), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
+def run_plain(args, torch, dfr):
+    import numpy as np
+
     import workloads
 
-    torch.cuda.set_device(0)
     n = 1 << args.log2n
     kt = args.key_type
     kbits = 32 if kt.endswith("32") else 64
     kb = vb = kbits // 8
-    log(f"generating {n} {args.dist} {kt} keys")
+    seeds = list(range(max(1, args.seeds)))
+    log(f"generating {len(seeds)} x {n} {args.dist} {kt} keys")
     # Signed and float keys are the same seeded bit patterns viewed as that type.
-    bits_h = workloads.make_keys(args.dist, n, kbits, 0)
-    keys_h = bits_h.view({"u32": np.uint32, "u64": np.uint64, "i32": np.int32, "i64": np.int64,
-                          "f32": np.float32, "f64": np.float64}[kt])
+    view = {"u32": np.uint32, "u64": np.uint64, "i32": np.int32, "i64": np.int64,
+            "f32": np.float32, "f64": np.float64}[kt]
+    keys_h = [workloads.make_keys(args.dist, n, kbits, sd).view(view) for sd in seeds]
     vals_h = workloads.index_payload(n, kbits)
-    base_k = torch.from_numpy(keys_h).cuda()
+    base_k = [torch.from_numpy(kh).cuda() for kh in keys_h]
     base_v = torch.from_numpy(vals_h).cuda()
     copies = args.warmup + args.steps
-    ks = [torch.empty_like(base_k) for _ in range(copies)]
-    vs = [torch.empty_like(base_v) for _ in range(copies)]
-    for i in range(copies):
-        ks[i].copy_(base_k)
-        vs[i].copy_(base_v)
+    seed_of = [i % len(seeds) for i in range(copies)]
+    ks = [base_k[seed_of[i]].clone() for i in range(copies)]
+    vs = [base_v.clone() for _ in range(copies)]
     temp = torch.empty(dfr.temp_bytes(n, kb, vb), dtype=torch.uint8, device="cuda")
     ctx = dfr.Context(0)
     for opt in args.set:
@@ -509,16 +580,16 @@ def run_plain(args):
     ctx.set_option("timing", 0)
     # Per-stage kernel times from one more sort after the timed region (events around
     # every stage add gaps between kernels, so they stay out of the timed steps).
-    ks[0].copy_(base_k)
+    ks[0].copy_(base_k[0])
     vs[0].copy_(base_v)
     ctx.set_option("timing", 1)
     ctx.sort_(ks[0], vs[0], temp)
     torch.cuda.synchronize()
     stage = ctx.stats()
     ctx.set_option("timing", 0)
-    # Cold variant: the first sort on a fresh context, its scratch (temp buffer, arena,
-    # pinned staging) allocated inside the call, as a one-off caller would see it.
-    ks[0].copy_(base_k)
+    # Cold variant: the first sort on a fresh context, its scratch (temp buffer, arena)
+    # allocated inside the call, as a one-off caller would see it.
+    ks[0].copy_(base_k[0])
     vs[0].copy_(base_v)
     torch.cuda.synchronize()
     cold_ctx = dfr.Context(0)
@@ -530,7 +601,12 @@ def run_plain(args):
     elapsed = t1 - t0
     ms_step = elapsed / args.steps * 1e3
     gkeys = n * args.steps / elapsed / 1e9
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {gkeys:.2f} Gkeys/s")
+    by_seed = {}
+    for sd in seeds:
+        mine = [step_ms[j] for j in range(args.steps) if seed_of[args.warmup + j] == sd]
+        if mine:
+            by_seed[str(sd)] = round(n / (np.mean(mine) * 1e-3) / 1e9, 4)
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {gkeys:.2f} Gkeys/s, by seed {by_seed}")
 
     # The check compares the keys as unsigned integers of the same order: the encodings
     # themselves for unsigned keys, the sign bit flipped for signed ones, and for floats
@@ -545,8 +621,16 @@ def run_plain(args):
             return np.where(neg, ~raw, raw ^ sign)
         return raw
 
-    parity = check_result(as_ordered(keys_h), as_ordered(ks[-1].cpu().numpy()), vs[-1].cpu().numpy())
+    parity = "pass"
+    for i in range(copies - len(seeds), copies):  # the last step of every seed
+        r = check_result(as_ordered(keys_h[seed_of[i]]), as_ordered(ks[i].cpu().numpy()),
+                         vs[i].cpu().numpy())
+        if r != "pass":
+            parity = f"seed {seed_of[i]}: {r}"
+            break
     log(f"result check: {parity}")
+    del ks, vs
+    torch.cuda.empty_cache()
 
     rec_bytes = kb + vb
     deal_bytes = 2 * rec_bytes * n  # read + write of key and payload, one pass
@@ -560,19 +644,25 @@ def run_plain(args):
     sort_bytes = n * (kb + d * 2 * rec_bytes + (kb + 2 * rec_bytes if plan and plan["used_diversion"] else 0))
     hbm_frac_sort = sort_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
-    cpu = None if args.no_cpu_baseline or kt != "u32" else cpu_baseline(args.dist)
-    ceiling = None if args.no_copy_ceiling else copy_ceiling(torch)
-
+    cpu = None if args.no_cpu_baseline or kt != "u32" else cpu_baseline(keys_h[0], args.dist)
+    if cpu:
+        log(f"cpu baseline: {cpu}")
+    del base_k, base_v, temp
+    torch.cuda.empty_cache()
+    ceiling = None if args.no_copy_ceiling else copy_ceiling(torch, ctx)
+    stage_ms = {k: round(v, 4) for k, v in stage.items() if k.startswith("ms_")}
     out = {
         "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": kt,
         "data": "synthetic",
         "config": {"workload": f"plain DFR sort of 2^{args.log2n} {kt} keys, i.i.d. "
-                               f"{args.dist} bit patterns, uint{kbits} index payload, seed 0",
+                               f"{args.dist} bit patterns, uint{kbits} index payload, seeds "
+                               f"{seeds} in turn",
                    "n": n, "key_type": kt, "key_bits": kbits, "payload_bits": kbits,
-                   "distribution": args.dist, "options": args.set,
+                   "distribution": args.dist, "seeds": seeds, "options": args.set,
                    "parallelism": "single GPU"},
+        "value_by_seed": by_seed,
         "roofline": {"bound": "hbm",
                      "kernel": f"k_deal<{kb},{vb},512,{dfr.deal_tile_records(kb, vb) // 512}>",
                      "achieved": round(deal_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -586,7 +676,13 @@ def run_plain(args):
                  "deal_passes": plan["deal_passes"] if plan else 0,
                  "large_buckets": plan["large_buckets"] if plan else 0,
                  "estimated_bucket_overflow": plan["estimated_overflow"] if plan else None},
-        "stage_ms_one_sort": {k: round(v, 4) for k, v in stage.items() if k.startswith("ms_")},
+        "stage_ms_one_sort": stage_ms,
+        "stage_frac_of_peak": {
+            k: round(b / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            for k, b in (("ms_deal", d * 2 * rec_bytes * n),
+                         ("ms_local_sort", 2 * rec_bytes * n if plan and plan["used_diversion"] else 0),
+                         ("ms_count", kb * n * (1 + max(d - 1, 0))))
+            if b and stage_ms.get(k)},
         "cold_first_sort_ms": round(cold_ms, 3),
         "step_ms": {"median": round(float(np.median(step_ms)), 4),
                     "min": round(float(step_ms.min()), 4),
@@ -594,10 +690,8 @@ def run_plain(args):
         "copy_ceiling": ceiling,
         "result_check": parity,
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
-    if parity != "pass":
-        sys.exit(1)
+    return out
 
 
 if __name__ == "__main__":

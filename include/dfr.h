@@ -158,6 +158,13 @@ dfr_status dfr_deal(dfr_ctx* ctx, const void* keys_in, const void* vals_in, void
                     void* vals_out, int key_bytes, int val_bytes, size_t n, int shift,
                     int bits, void* stream);
 
+/* Bandwidth reference: copy `bytes` (a multiple of 16; both pointers 16-byte aligned,
+ * not overlapping) from src to dst on the device with a plain streaming kernel of this
+ * library, enqueued on `stream`.  Every pass of the sort reads and writes each record
+ * once, as this copy does, so its rate is the ceiling those passes are measured
+ * against beside the HBM peak.  DFR_E_INVALID_ARG for bad pointers or sizes. */
+dfr_status dfr_stream_copy(dfr_ctx* ctx, const void* src, void* dst, size_t bytes, void* stream);
+
 /* ---------------------------------------------------------------------------------
  * Serving: submit sort requests of any size and width, poll for completion.
  *

@@ -36,8 +36,9 @@ EXPORTED = [
     "dfr_count", "dfr_deal", "dfr_submit", "dfr_poll", "dfr_set_option", "dfr_get_stats",
     "dfr_plan_top_digits", "dfr_local_sort_capacity", "dfr_deal_tile_records",
     "dfr_size_class", "dfr_autotune", "dfr_get_tune", "dfr_set_tune", "dfr_get_serve_stats",
-    "dfr_sort_keys", "dfr_sort_segmented_keys",
+    "dfr_sort_keys", "dfr_sort_segmented_keys", "dfr_stream_copy",
 ]
+
 
 # Key types of dfr_sort_keys.
 KEY_U32, KEY_U64, KEY_I32, KEY_I64, KEY_F32, KEY_F64 = range(6)
@@ -166,6 +167,8 @@ def lib():
     L.dfr_sort_keys.restype = S
     L.dfr_sort_segmented_keys.argtypes = [P, S, P, P, I, P, Z, P, Z, P]
     L.dfr_sort_segmented_keys.restype = S
+    L.dfr_stream_copy.argtypes = [P, P, P, Z, P]
+    L.dfr_stream_copy.restype = S
     _lib = L
     return L
 
@@ -356,6 +359,17 @@ class Context:
                                                       off.ctypes.data, off.size - 1, tp, tb,
                                                       self._stream(stream)), "sort_segmented")
         return keys, vals
+
+    def stream_copy(self, src, dst, stream=None):
+        """Copy GPU tensor ``src`` into ``dst`` (same byte size, a multiple of 16) with
+        the library's streaming copy kernel, the bandwidth reference of the passes."""
+        _check_tensor(src, "src")
+        _check_tensor(dst, "dst")
+        nb = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nb:
+            raise ValueError("src and dst must have the same byte size")
+        self._raise(lib().dfr_stream_copy(self._h, src.data_ptr(), dst.data_ptr(), nb,
+                                          self._stream(stream)), "stream_copy")
 
     # -- tuning --------------------------------------------------------------------
     def autotune(self, keys, vals=None, offsets=None, reps: int = 2, stream=None) -> dict:

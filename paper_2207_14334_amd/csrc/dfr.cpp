@@ -2211,6 +2211,22 @@ dfr_status dfr_deal(dfr_ctx* c, const void* keys_in, const void* vals_in, void* 
     return DFR_OK;
 }
 
+dfr_status dfr_stream_copy(dfr_ctx* c, const void* src, void* dst, size_t bytes, void* stream) {
+    if (!c) return DFR_E_INVALID_ARG;
+    if (c->failed) return DFR_E_HIP;
+    if (bytes == 0) return DFR_OK;
+    if (!src || !dst || bytes % 16 || (uintptr_t)src % 16 || (uintptr_t)dst % 16 ||
+        overlap(src, bytes, dst, bytes))
+        return DFR_E_INVALID_ARG;
+    dfr_status st = set_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    if (order.st) return order.st;
+    HIP_TRY(c, launch_stream_copy(src, dst, bytes, s));
+    return DFR_OK;
+}
+
 dfr_status dfr_submit(dfr_ctx* c, const dfr_request* req, uint64_t* ticket) {
     if (!c || !req || !ticket) return DFR_E_INVALID_ARG;
     const int kb = req->key_bytes, vb = req->val_bytes;

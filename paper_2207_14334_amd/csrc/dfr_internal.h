@@ -282,6 +282,8 @@ hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks
                              int first_form, hipStream_t s);
 hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t nchunks,
                               hipStream_t s);
+// Streaming copy of bytes / 16 vectors (both pointers 16-byte aligned).
+hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, void* kout,
                              void* vout, const Tile* tiles, uint32_t ntiles, hipStream_t s);
 

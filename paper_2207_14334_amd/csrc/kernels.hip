@@ -1756,6 +1756,35 @@ __global__ __launch_bounds__(THREADS) void k_copy_chunks(const CopyChunk* chunks
     }
 }
 
+// Streaming copy of 16-byte vectors, the bandwidth reference for the passes above (each
+// of which reads and writes every record once): every thread keeps STREAM_U loads in
+// flight, and consecutive threads touch consecutive vectors.
+constexpr int STREAM_THREADS = 256, STREAM_U = 8;
+__global__ __launch_bounds__(STREAM_THREADS) void k_stream_copy(const uint4* src, uint4* dst, uint64_t nvec) {
+    const uint64_t stride = (uint64_t)gridDim.x * STREAM_THREADS * STREAM_U;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * STREAM_THREADS * STREAM_U + threadIdx.x; i0 < nvec;
+         i0 += stride) {
+        uint4 r[STREAM_U];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u)
+            if (i0 + (uint64_t)u * STREAM_THREADS < nvec) r[u] = src[i0 + (uint64_t)u * STREAM_THREADS];
+#pragma unroll
+        for (int u = 0; u < STREAM_U; ++u)
+            if (i0 + (uint64_t)u * STREAM_THREADS < nvec) dst[i0 + (uint64_t)u * STREAM_THREADS] = r[u];
+    }
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s) {
+    const uint64_t nvec = bytes / 16;
+    if (nvec == 0) return hipSuccess;
+    const uint64_t per_block = (uint64_t)STREAM_THREADS * STREAM_U;
+    // Enough blocks to fill the 256 CUs several times over, each looping if needed.
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((nvec + per_block - 1) / per_block, 256u * 32u);
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(STREAM_THREADS), 0, s, (const uint4*)src,
+                       (uint4*)dst, nvec);
+    return hipGetLastError();
+}
+
 // Order-preserving maps from signed and floating-point encodings to unsigned integers
 // (the paper sorts unsigned keys only).  Signed: flip the sign bit, so that negative
 // values come first in two's-complement order.  Float: flip every bit of a negative

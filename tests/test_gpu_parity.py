@@ -448,11 +448,11 @@ FORM_CASES = [
     # (key bits, payload bits, n, segmented, form expected): the headline shape (two
     # digits of 32-bit keys dealt, buckets of ~1024 records or more: 32-bit words with
     # the position inside); one digit of 32-bit keys dealt (position beside the words);
-    # 64-bit keys (64-bit words).
+    # 64-bit keys with buckets of ~256 records or more (64-bit words).
     (32, 32, (1 << 26) + 7, False, 0),
     (32, 32, (1 << 20) + 3, False, 1),
     (32, 32, None, True, 1),
-    (64, 64, (1 << 21) + 5, False, 2),
+    (64, 64, (1 << 24) + 5, False, 2),
     (32, 0, (1 << 26) + 1, False, 0),
 ]
 

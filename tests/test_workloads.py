@@ -66,3 +66,26 @@ def test_permutation_keys_are_distinct_and_invertible():
     assert np.array_equal(idx, np.arange(n, dtype=np.uint64))
     k2, a2, b2 = workloads.permutation_keys(n, 9)
     assert np.array_equal(k, k2) and (a, b) == (a2, b2)
+
+
+def test_device_generators_shapes():
+    """The torch-drawn benchmark inputs have the shapes of make_keys' (run here on the
+    CPU device): Zipf(1.1) mass at 0 and below 2^16, normal moments, the uniform range,
+    determinism per seed, and the index payload."""
+    import torch
+    n = 1 << 21
+    z = workloads.make_keys_device("zipf", n, 32, 0, device="cpu")
+    zi = z.view(torch.int32).numpy().view(np.uint32)
+    assert abs(np.mean(zi == 0) - 0.105) < 0.01 and abs(np.mean(zi < (1 << 16)) - 0.77) < 0.02
+    g = workloads.make_keys_device("normal", n, 32, 0, device="cpu").view(torch.int32).numpy()
+    g = g.view(np.uint32).astype(np.float64)
+    assert abs(g.mean() / 2**31 - 1) < 1e-3 and abs(g.std() / 2**28 - 1) < 1e-2
+    u = workloads.make_keys_device("uniform", n, 32, 0, device="cpu").view(torch.int32).numpy()
+    u = u.view(np.uint32).astype(np.float64)
+    assert abs(u.mean() / 2**31 - 1) < 5e-3 and u.max() > 2**32 * 0.999
+    u2 = workloads.make_keys_device("uniform", n, 32, 0, device="cpu")
+    assert torch.equal(u2, workloads.make_keys_device("uniform", n, 32, 0, device="cpu"))
+    w = workloads.make_keys_device("uniform", 1000, 64, 1, device="cpu").view(torch.int64).numpy()
+    assert w.view(np.uint64).max() > (1 << 63)
+    v = workloads.index_payload_device(10, 32, 5, device="cpu").view(torch.int32).numpy()
+    assert list(v) == list(range(5, 15))

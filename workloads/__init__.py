@@ -129,6 +129,91 @@ def permutation_keys(n: int, seed: int = 0) -> tuple[np.ndarray, int, int]:
     return out, a, b
 
 
+# --------------------------------------------------------------------------------------
+# The same shapes drawn on the GPU (torch's Philox generator, seeded), for benchmark
+# inputs of billions of keys that numpy would take minutes to draw.  Tests use the numpy
+# generators above.
+# --------------------------------------------------------------------------------------
+
+def _torch_gen(seed: int, stream: int, device):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed((seed * 1_000_003 + stream) & ((1 << 63) - 1))
+    return g
+
+
+def _as_unsigned(x, key_bits):
+    """int64 tensor of values in [0, 2^key_bits) -> uint32/uint64 tensor of those values."""
+    import torch
+    if key_bits == 64:
+        return x.view(torch.uint64)
+    x = torch.where(x >= (1 << 31), x - (1 << 32), x).to(torch.int32)
+    return x.view(torch.uint32)
+
+
+def make_keys_device(dist: str, n: int, key_bits: int = 32, seed: int = 0, device="cuda"):
+    """``n`` keys of distribution ``dist`` ("uniform", "normal" or "zipf", with the
+    parameters of make_keys) drawn on the GPU; a uint32/uint64 tensor."""
+    import torch
+    if key_bits not in (32, 64):
+        raise ValueError("key_bits must be 32 or 64")
+    out = torch.empty(n, dtype=torch.uint32 if key_bits == 32 else torch.uint64, device=device)
+    g = _torch_gen(seed, 7, device)
+    step = 1 << 26
+    if dist == "zipf":
+        # Zipf(s) by Devroye's rejection method (Non-Uniform Random Variate Generation,
+        # 1986, ch. X.6): X = floor(U^(-1/(s-1))), accepted when
+        # V X (T - 1) / (b - 1) <= T / b with T = (1 + 1/X)^(s-1), b = 2^(s-1);
+        # ranks above the key range are redrawn, as make_keys does; key = rank - 1.
+        s_, limit = 1.1, float(1 << 32) if key_bits == 32 else float(1 << 63)
+        am1 = s_ - 1.0
+        b = 2.0 ** am1
+        filled = 0
+        while filled < n:
+            m = min(step, int((n - filled) * 1.4) + 4096)
+            u = 1.0 - torch.rand(m, dtype=torch.float64, generator=g, device=device)
+            v = torch.rand(m, dtype=torch.float64, generator=g, device=device)
+            x = torch.floor(u.pow(-1.0 / am1))
+            t = (1.0 + 1.0 / x).pow(am1)
+            ok = (x >= 1.0) & (x <= limit) & (v * x * (t - 1.0) / (b - 1.0) <= t / b)
+            r = x[ok][: n - filled]
+            k = r.to(torch.int64) - 1 if key_bits == 32 else (r - 1.0).to(torch.int64)
+            out[filled:filled + k.numel()] = _as_unsigned(k, key_bits)
+            filled += k.numel()
+        return out
+    for lo in range(0, n, step):
+        m = min(step, n - lo)
+        if dist == "uniform":
+            if key_bits == 32:
+                x = torch.randint(0, 1 << 32, (m,), dtype=torch.int64, generator=g, device=device)
+            else:
+                x = torch.randint(-(1 << 63), (1 << 63) - 1, (m,), dtype=torch.int64, generator=g,
+                                  device=device)
+                out[lo:lo + m] = x.view(torch.uint64)
+                continue
+        elif dist == "normal":
+            mean, sd = float(2 ** (key_bits - 1)), float(2 ** (key_bits - 4))
+            y = torch.normal(mean, sd, (m,), dtype=torch.float64, generator=g, device=device)
+            if key_bits == 64:
+                # Rounded and clipped to the key range, taken as (value - 2^63) in int64,
+                # then the sign bit flipped: the value's 64-bit pattern.
+                z = torch.clamp(torch.round(y) - 2.0 ** 63, -(2.0 ** 63), 2.0 ** 63 - 1024.0)
+                out[lo:lo + m] = (z.to(torch.int64) ^ (-(1 << 63))).view(torch.uint64)
+                continue
+            x = torch.clamp(torch.round(y), 0.0, float(2 ** 32 - 1)).to(torch.int64)
+        else:
+            raise ValueError(f"distribution {dist!r} is not drawn on the GPU")
+        out[lo:lo + m] = _as_unsigned(x, key_bits)
+    return out
+
+
+def index_payload_device(n: int, val_bits: int = 32, offset: int = 0, device="cuda"):
+    """The index payload v_i = offset + i as a uint32/uint64 GPU tensor."""
+    import torch
+    x = torch.arange(offset, offset + n, dtype=torch.int64, device=device)
+    return _as_unsigned(x, val_bits) if val_bits == 32 else x.view(torch.uint64)
+
+
 def index_payload(n: int, val_bits: int = 32) -> np.ndarray:
     """The payload v_i = i, which makes the stable sort checkable by its properties."""
     return np.arange(n, dtype=np.uint32 if val_bits == 32 else np.uint64)
