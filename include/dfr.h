@@ -94,6 +94,30 @@ dfr_status dfr_sort_u64(dfr_ctx* ctx, uint64_t* keys, uint64_t* vals, size_t n, 
                         size_t temp_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------
+ * Allocation-free plain sort, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * The same stable ascending sort as dfr_sort_u32/u64 (unsigned keys of key_bytes 4 or
+ * 8; vals NULL with val_bytes 0, else val_bytes 4 or 8), on at most
+ * DFR_NOALLOC_MAX_RECORDS records, at the default launch settings (the context's
+ * options and tunings do not apply; "timing" is ignored).  It allocates nothing:
+ * the temp buffer, the per-level lists and the status block live in a fixed device
+ * array of DFR_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (its address is looked up once per device by dfr_create),
+ * and the host staging is the pinned buffer dfr_create reserves.  Every such call on
+ * one GPU, from any context, shares that GPU's array and leaves its contents behind;
+ * calls that overlap in time on one GPU (different streams or threads) race on it and
+ * must be serialised by the caller.  Like the plain sort it blocks the host for its
+ * planning read-backs.  DFR_E_TOO_LARGE for n > DFR_NOALLOC_MAX_RECORDS; other errors
+ * as for the plain sort.
+ * ------------------------------------------------------------------------------- */
+#define DFR_NOALLOC_MAX_RECORDS ((size_t)1 << 22)
+#define DFR_NOALLOC_SCRATCH_BYTES ((size_t)192 << 20)
+
+dfr_status dfr_sort_noalloc(dfr_ctx* ctx, void* keys, void* vals, size_t n, int key_bytes,
+                            int val_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------
  * Segmented sort: many independent arrays laid end to end, each sorted on its own
  * exactly as the plain sort would sort it (Sec. 3; large buckets are themselves
  * sorted by the same procedure).

@@ -36,9 +36,12 @@ EXPORTED = [
     "dfr_count", "dfr_deal", "dfr_submit", "dfr_poll", "dfr_set_option", "dfr_get_stats",
     "dfr_plan_top_digits", "dfr_local_sort_capacity", "dfr_deal_tile_records",
     "dfr_size_class", "dfr_autotune", "dfr_get_tune", "dfr_set_tune", "dfr_get_serve_stats",
-    "dfr_sort_keys", "dfr_sort_segmented_keys", "dfr_stream_copy",
+    "dfr_sort_keys", "dfr_sort_segmented_keys", "dfr_sort_noalloc", "dfr_stream_copy",
 ]
 
+# The allocation-free entry point's limits (include/dfr.h).
+NOALLOC_MAX_RECORDS = 1 << 22
+NOALLOC_SCRATCH_BYTES = 192 << 20
 
 # Key types of dfr_sort_keys.
 KEY_U32, KEY_U64, KEY_I32, KEY_I64, KEY_F32, KEY_F64 = range(6)
@@ -167,6 +170,8 @@ def lib():
     L.dfr_sort_keys.restype = S
     L.dfr_sort_segmented_keys.argtypes = [P, S, P, P, I, P, Z, P, Z, P]
     L.dfr_sort_segmented_keys.restype = S
+    L.dfr_sort_noalloc.argtypes = [P, P, P, Z, I, I, P]
+    L.dfr_sort_noalloc.restype = S
     L.dfr_stream_copy.argtypes = [P, P, P, Z, P]
     L.dfr_stream_copy.restype = S
     _lib = L
@@ -324,6 +329,23 @@ class Context:
         else:
             self._raise(lib().dfr_sort_keys(self._h, kt, keys.data_ptr(), vp, vb, n, tp, tb,
                                             self._stream(stream)), "sort")
+        return keys, vals
+
+    def sort_noalloc_(self, keys, vals=None, stream=None):
+        """Stable in-place sort of unsigned ``keys`` (``vals`` follows) that allocates
+        no device memory: at most NOALLOC_MAX_RECORDS records, default settings, in the
+        library's fixed scratch array on this GPU (calls overlapping on one GPU race)."""
+        _check_tensor(keys, "keys")
+        if _key_type(keys) not in (KEY_U32, KEY_U64):
+            raise TypeError("the allocation-free sort takes uint32 or uint64 keys")
+        vp, vb = None, 0
+        if vals is not None:
+            _check_tensor(vals, "vals")
+            if vals.numel() != keys.numel():
+                raise ValueError("vals must match keys in length")
+            vp, vb = vals.data_ptr(), _val_width(vals)
+        self._raise(lib().dfr_sort_noalloc(self._h, keys.data_ptr(), vp, keys.numel(),
+                                           _width(keys), vb, self._stream(stream)), "sort_noalloc")
         return keys, vals
 
     def sort_segmented_(self, keys, vals, offsets, temp=None, stream=None):

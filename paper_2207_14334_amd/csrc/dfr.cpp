@@ -60,6 +60,9 @@ constexpr uint64_t kSegScanTiles = 1024;
 constexpr size_t kPerSegScanMax = 16;
 // Top digits with at most this many non-empty bins count as a skewed prefix.
 constexpr uint32_t kFewTopValues = 16;
+// Pinned host staging reserved by dfr_create (the allocation-free entry point's whole
+// staging: tile and segment lists, plan and bucket read-backs of one level).
+constexpr size_t kNoallocPinBytes = size_t(4) << 20;
 
 }  // namespace
 
@@ -85,6 +88,12 @@ struct dfr_ctx {
     char* pin = nullptr;
     size_t pin_cap = 0;
     size_t pin_used = 0;
+    // The allocation-free entry point: this device's fixed scratch array, and whether
+    // the current call runs on it (then nothing may be allocated: the arena, the temp
+    // buffer and the status block live in that array, and the pinned staging is the
+    // one reserved at dfr_create).
+    char* static_scratch = nullptr;
+    bool static_mode = false;
 
     // Options.
     size_t divert = 0;  // 0 = default N_d
@@ -142,6 +151,10 @@ dfr_status fail_hip(dfr_ctx* c, hipError_t e, const char* what) {
 dfr_status arena_need(dfr_ctx* c, size_t bytes, hipStream_t s) {
     const size_t need = c->arena_used + bytes;
     if (need <= c->arena_cap) return DFR_OK;
+    if (c->static_mode) {  // the fixed scratch does not grow
+        c->err = "allocation-free sort: level scratch exceeds the fixed scratch array";
+        return DFR_E_TOO_LARGE;
+    }
     const size_t cap = std::max<size_t>(round_up(need + need / 4, 1 << 20), 16 << 20);
     const auto t0 = std::chrono::steady_clock::now();
     char* na = nullptr;
@@ -189,6 +202,10 @@ dfr_status pin_reserve(dfr_ctx* c, size_t bytes, hipStream_t s) {
     HIP_TRY(c, hipStreamSynchronize(s));
     c->pin_used = 0;
     if (bytes <= c->pin_cap) return DFR_OK;
+    if (c->static_mode) {  // no allocation: the staging reserved at dfr_create is all
+        c->err = "allocation-free sort: host staging exceeds the reserved buffer";
+        return DFR_E_TOO_LARGE;
+    }
     if (c->pin) HIP_TRY(c, hipHostFree(c->pin));
     c->pin = nullptr;
     size_t cap = std::max<size_t>(round_up(bytes * 2, 1 << 20), 4 << 20);
@@ -232,7 +249,7 @@ struct Timed {
     bool deal;
     hipEvent_t a = nullptr;
     Timed(dfr_ctx* c_, hipStream_t s_, int st, bool d = false) : c(c_), s(s_), stage(st), deal(d) {
-        if (c->timing == 1 || (c->timing == 2 && deal)) {
+        if (!c->static_mode && (c->timing == 1 || (c->timing == 2 && deal))) {
             a = get_event(c);
             if (a) (void)hipEventRecord(a, s);
         }
@@ -1894,6 +1911,18 @@ dfr_status dfr_create(int hip_device, size_t hbm_budget_bytes, dfr_ctx** out) {
         delete c;
         return DFR_E_HIP;
     }
+    // Set-up of the allocation-free entry point: this device's scratch array (looked
+    // up once per device, this device current) and pinned staging reserved now.
+    void* sp = nullptr;
+    if (static_scratch_address(hip_device, &sp) != hipSuccess ||
+        hipHostMalloc((void**)&c->pin, kNoallocPinBytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(c->done);
+        delete c;
+        return DFR_E_HIP;
+    }
+    c->static_scratch = (char*)sp;
+    c->pin_cap = kNoallocPinBytes;
     *out = c;
     return DFR_OK;
 }
@@ -2015,6 +2044,49 @@ dfr_status dfr_sort_u32(dfr_ctx* c, uint32_t* keys, uint32_t* vals, size_t n, vo
 dfr_status dfr_sort_u64(dfr_ctx* c, uint64_t* keys, uint64_t* vals, size_t n, void* temp,
                         size_t temp_bytes, void* stream) {
     return sort_plain(c, 8, vals ? 8 : 0, keys, vals, n, temp, temp_bytes, stream);
+}
+
+dfr_status dfr_sort_noalloc(dfr_ctx* c, void* keys, void* vals, size_t n, int key_bytes,
+                            int val_bytes, void* stream) {
+    dfr_status st = validate(c, keys, vals, n, key_bytes, val_bytes, nullptr, 0);
+    if (st) return st;
+    if (n > NOALLOC_MAX_RECORDS) {
+        c->err = "allocation-free sort: more records than its fixed scratch holds";
+        return DFR_E_TOO_LARGE;
+    }
+    if (n <= 1) {
+        c->stats = dfr_stats{};
+        return DFR_OK;
+    }
+    if (!c->static_scratch) return DFR_E_UNSUPPORTED;
+    st = set_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    if (order.st) return order.st;
+    // Layout of the fixed scratch: the status block, the temp buffer, then the level
+    // scratch (the arena).  Everything the kernels need zeroed is cleared per call.
+    const size_t temp_bytes = dfr_temp_bytes(n, key_bytes, val_bytes);
+    char* base = c->static_scratch;
+    char* arena = base + ALIGN + temp_bytes;
+    const size_t arena_cap = NOALLOC_SCRATCH_BYTES - ALIGN - temp_bytes;
+    char* const saved_arena = c->arena;
+    const size_t saved_cap = c->arena_cap, saved_used = c->arena_used;
+    uint32_t* const saved_err = c->err_dev;
+    c->arena = arena;
+    c->arena_cap = arena_cap;
+    c->arena_used = 0;
+    c->err_dev = (uint32_t*)base;
+    c->static_mode = true;
+    const dfr_tune t = default_tune(key_bytes, val_bytes);  // options and tunings do not apply
+    std::vector<LSeg> segs{LSeg{0, n, 8 * key_bytes}};
+    st = run_sort(c, key_bytes, val_bytes, keys, val_bytes ? vals : nullptr, segs, base + ALIGN, s, &t);
+    c->static_mode = false;
+    c->arena = saved_arena;
+    c->arena_cap = saved_cap;
+    c->arena_used = saved_used;
+    c->err_dev = saved_err;
+    return st;
 }
 
 dfr_status dfr_sort_keys(dfr_ctx* c, int32_t key_type, void* keys, void* vals, int val_bytes,

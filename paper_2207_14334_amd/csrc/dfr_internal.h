@@ -248,6 +248,16 @@ struct CopyChunk {
     uint32_t len;
 };
 
+// The allocation-free entry point's fixed device scratch (one array per GPU): the
+// status block, the temp buffer of a sort of at most NOALLOC_MAX_RECORDS records of up
+// to 16 bytes, and the level scratch such a sort needs at the default settings.
+constexpr size_t NOALLOC_MAX_RECORDS = size_t(1) << 22;
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(192) << 20;
+constexpr int MAX_DEVICES = 64;
+// Address of this GPU's scratch array; `device` must be the current device.  Looked up
+// once per device (hipGetSymbolAddress), then cached.
+hipError_t static_scratch_address(int device, void** ptr);
+
 // Tile and capacity choices per (key bytes, value bytes).
 uint32_t deal_tile_records(int kb, int vb);  // the default tile
 bool deal_tile_supported(int kb, int vb, uint32_t tile);  // the default or half of it

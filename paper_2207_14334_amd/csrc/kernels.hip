@@ -35,6 +35,7 @@
 #include "dfr_internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace dfr {
 
@@ -2237,6 +2238,34 @@ hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, v
         else copy_kb_vb<8, 8>(kin, vin, kout, vout, tiles, ntiles, s);
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free entry point (dfr_sort_noalloc): one
+// array per GPU, held until the process ends.  Host code never uses the array's name
+// as an address: static_scratch_address() looks up this GPU's copy once (with that GPU
+// current) and every later use goes through the pointer it returns.
+// ---------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t static_scratch_address(int device, void** ptr) {
+    static std::mutex mu;
+    static void* addr[MAX_DEVICES] = {};
+    *ptr = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes it current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace dfr
