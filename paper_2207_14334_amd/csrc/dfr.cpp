@@ -625,7 +625,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ca.keys = j.k[in];
         ca.tiles = dtiles;
         ca.ntiles = (uint32_t)tiles.size();
-        const uint32_t blocks = (uint32_t)std::min<size_t>(tiles.size(), 2048);
+        // Two rounds of blocks over the 256 CUs (8 resident each): the LDS-atomic-bound
+        // count overlaps one block's tile flush with another's counting.
+        const uint32_t blocks = (uint32_t)std::min<size_t>(tiles.size(), 4096);
         ca.tiles_per_block = (uint32_t)((tiles.size() + blocks - 1) / blocks);
         ca.base_shift = 0;
         ca.bits = rb;
