@@ -427,8 +427,9 @@ def c1_part(torch, dfr, calls=50):
             "result_check": "pass" if ok else "keys differ from numpy's sort"}
 
 
-def dist_part(torch, dfr, dist, log2n=28, steps=3):
-    """The plain 2^log2n uint32 + index payload sort on another distribution."""
+def dist_part(torch, dfr, dist, log2n=28, steps=3, options=()):
+    """The plain 2^log2n uint32 + index payload sort on another distribution, or under
+    library options (name, value)."""
     import numpy as np
 
     import workloads
@@ -439,6 +440,8 @@ def dist_part(torch, dfr, dist, log2n=28, steps=3):
     k, v = torch.empty_like(base_k), torch.empty_like(base_v)
     temp = torch.empty(dfr.temp_bytes(n, 4, 4), dtype=torch.uint8, device="cuda")
     ctx = dfr.Context(0)
+    for name, value in options:
+        ctx.set_option(name, value)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     times = []
     for i in range(steps + 1):
@@ -452,14 +455,22 @@ def dist_part(torch, dfr, dist, log2n=28, steps=3):
             times.append(ev[0].elapsed_time(ev[1]))
     st = ctx.stats()
     parity = check_result(keys_h, host_np(k), host_np(v))
+    ctx.set_option("timing", 1)
+    k.copy_(base_k)
+    v.copy_(base_v)
+    ctx.sort_(k, v, temp)
+    torch.cuda.synchronize()
+    stages = {kk: round(vv, 4) for kk, vv in ctx.stats().items() if kk.startswith("ms_")}
     ctx.close()
     del base_k, base_v, k, v, temp
     torch.cuda.empty_cache()
     ms = float(np.median(times))
-    return {"workload": f"2^{log2n} uint32 keys, {dist}, uint32 index payload, seed 0", "n": n,
+    opts = "".join(f", option {name}={value}" for name, value in options)
+    return {"workload": f"2^{log2n} uint32 keys, {dist}, uint32 index payload, seed 0{opts}", "n": n,
             "ms": round(ms, 4), "gkeys_per_s": round(n / ms / 1e6, 3),
-            "plan": {kk: st[kk] for kk in ("levels", "top_digits", "deal_passes", "large_buckets")},
-            "result_check": parity}
+            "plan": {kk: st[kk] for kk in ("levels", "top_digits", "deal_passes", "large_buckets",
+                                           "deal_passes_estimated", "estimated_overflow")},
+            "stage_ms": stages, "result_check": parity}
 
 
 def main():
@@ -512,12 +523,17 @@ def main():
         log(f"c1: {out['c1']}")
         out["normal"] = dist_part(torch, dfr, "normal")
         log(f"normal: {out['normal']}")
+        # Fast Radix's estimated buckets for the first deal (no count) on the headline
+        # input, against the counted path that "value" times.
+        out["estimated_buckets"] = dist_part(torch, dfr, "uniform", options=[("estimated_buckets", 1)])
+        log(f"estimated buckets: {out['estimated_buckets']}")
         out["batched"] = [batched_part(torch, dfr, d, args.arrays, args.max_len, 3)
                           for d in ("uniform", "zipf")]
         out["serving"] = serving_part(torch, dfr, args.requests, args.rho or [0.7, 0.9],
                                       args.budget_gib)
         ok = ok and all(p["result_check"] == "pass" for p in
-                        [out["c1"], out["normal"], out["serving"], *out["batched"]])
+                        [out["c1"], out["normal"], out["estimated_buckets"], out["serving"],
+                         *out["batched"]])
     out["wall_s"] = round(time.perf_counter() - wall0, 1)
     print(json.dumps(out), flush=True)
     if not ok:

@@ -268,6 +268,13 @@ dfr_status dfr_get_serve_stats(dfr_ctx* ctx, dfr_serve_stats* out);
  *                     where a level could take them from its digit counts (one segment
  *                     dealt on two digits) or histograms (dealt on one digit); same
  *                     result, for testing.  0 to restore.
+ *   "estimated_buckets" 1 to deal the first level of a plain sort the Fast Radix way
+ *                     (Sec. 3): no count, two top digits when n alone predicts two for
+ *                     uniform keys, the lower one dealt into buckets of estimated size
+ *                     n / 2^b with overflow slots (Sec. 3.1), the upper one counted in
+ *                     that pass and dealt exactly; a level whose buckets outgrow their
+ *                     slots is dealt with counted buckets instead.  Same result.  0 to
+ *                     restore.
  *   "radix_bits"      digit width b of the deal passes, 4..8 with at most 8 digits
  *                     per key (so 8 for 64-bit keys); the paper's digits are 8 bits
  *                     (Sec. 4).  0 = tuned or default.

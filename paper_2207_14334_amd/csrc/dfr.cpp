@@ -101,6 +101,7 @@ struct dfr_ctx {
     int timing = 0;  // 1 every stage, 2 the deal launches only
     bool force_lookback = false;  // deal every level with decoupled look-back
     bool force_key_heads = false;  // find bucket heads from the keys on every level
+    bool est_buckets = false;      // first level of plain sorts: Fast Radix estimated buckets
     int radix_bits = 0;           // 0 = tuned or default
     uint32_t tile_records = 0;
     size_t window = 0;
@@ -1138,6 +1139,295 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     return DFR_OK;
 }
 
+// A first level dealt the Fast Radix way (Sec. 3): no count, the number of top digits
+// estimated from n alone for uniform keys (Sec. 3.1: buckets of n / M^d records), and
+// used only when that is two digits.  The lower digit is dealt into estimated buckets
+// with an overflow area (k_deal_est), which also counts the upper digit; the upper
+// digit is then dealt exactly, by decoupled look-back over the buckets in order, each
+// bucket's estimated slots followed by its overflow slots.  Bucket heads come from the
+// keys, then the runs of small buckets are diverted and the large ones recurse, as in
+// deal_level.  *used is false (and nothing has been written) when the level does not
+// qualify or a bucket outgrew its estimate and overflow slots: the caller then deals
+// the level with counted buckets.
+dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used) {
+    dfr_ctx* c = j.c;
+    *used = false;
+    j.err_known = false;
+    const int kb = j.kb, vb = j.vb, rb = j.rb;
+    const int ndig = num_digits(kb, rb);
+    const uint64_t n = g.len;
+    if (g.start != 0 || g.hi_bit != 8 * kb || ndig < 2 || j.tile != deal_tile_records(kb, vb) ||
+        n > DFR_MAX_SEGMENT_RECORDS)
+        return DFR_OK;
+    int d = 0;
+    double expect = (double)n;
+    while (d < ndig && expect > (double)j.divert) {
+        expect /= (double)(1u << rb);
+        ++d;
+    }
+    if (d != 2) return DFR_OK;
+    const int du = ndig - 2, dw = ndig - 1;  // the two top digits: lower (estimated), upper (exact)
+    const int su = rb * du, wu = std::min(rb, 8 * kb - su);
+    const int sw = rb * dw, ww = std::min(rb, 8 * kb - sw);
+    const uint32_t M = 1u << wu;
+    const uint64_t E = n / M;
+    // Overflow slots per bucket: four standard deviations of a bucket's count for
+    // uniform keys, sqrt(E), at least 256; Eq. 2's expected overflow is far below that.
+    const uint32_t C = (uint32_t)round_up(std::max<uint64_t>(256, (uint64_t)(4.0 * std::sqrt((double)E)) + 1), 64);
+    const uint32_t T = j.tile;
+    const uint64_t nt0 = (n + T - 1) / T;
+    const uint64_t nt1 = nt0 + 2 * (uint64_t)M + 1;  // tiles of the exact pass, at most
+    const uint64_t bcap = std::min<uint64_t>(n, (uint64_t)1 << (wu + ww));
+    const size_t wsmall = j.wsmall;
+    const uint64_t nslots = (n + wsmall - 1) / wsmall;
+    const uint64_t medcap = n / (wsmall + 1), bigcap = n / (j.cap + 1);
+    const size_t need = asize<uint64_t>(nt1 * RADIX + 1) + 3 * asize<uint32_t>(RADIX) + asize<uint32_t>(8) +
+                        asize<char>((size_t)M * C * kb) + asize<char>((size_t)M * C * std::max(vb, 1)) +
+                        asize<Tile>(nt1) + asize<Tile>(nt0) + asize<Seg>(1) + asize<uint32_t>(nt0) +
+                        asize<uint64_t>(nt0) + asize<uint16_t>(nt0 * HEAD_SLOTS) + asize<uint64_t>(bcap) +
+                        asize<uint32_t>(bcap) + 2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
+                        2 * asize<Big>(bigcap) + 3 * asize<uint32_t>(nslots + medcap) + asize<uint32_t>(8);
+    dfr_status st = arena_reserve(c, need, j.s);
+    if (st) return st;
+    uint64_t* lb = aalloc<uint64_t>(c, nt1 * RADIX + 1);
+    uint32_t* cnt = aalloc<uint32_t>(c, RADIX);
+    uint32_t* hist_w = aalloc<uint32_t>(c, RADIX);
+    uint32_t* lost = aalloc<uint32_t>(c, 8);
+    char* kovf = aalloc<char>(c, (size_t)M * C * kb);
+    char* vovf = aalloc<char>(c, (size_t)M * C * std::max(vb, 1));
+    Tile* tiles1 = aalloc<Tile>(c, nt1);
+    Tile* htiles = aalloc<Tile>(c, nt0);
+    Seg* dseg = aalloc<Seg>(c, 1);
+    uint32_t* htcount = aalloc<uint32_t>(c, nt0);
+    uint64_t* htbase = aalloc<uint64_t>(c, nt0);
+    uint16_t* htslot = aalloc<uint16_t>(c, nt0 * HEAD_SLOTS);
+    uint64_t* dbstart = aalloc<uint64_t>(c, bcap);
+    uint32_t* dbseg = aalloc<uint32_t>(c, bcap);
+    uint32_t* cfirst = aalloc<uint32_t>(c, nslots);
+    uint32_t* clast = aalloc<uint32_t>(c, nslots);
+    uint32_t* med = aalloc<uint32_t>(c, medcap);
+    Big* big = aalloc<Big>(c, bigcap);
+    Big* done = aalloc<Big>(c, bigcap);
+    uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
+    uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
+    uint32_t* wide = aalloc<uint32_t>(c, nslots + medcap);
+    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work, wide
+
+    // --- the estimated deal of the lower digit into the temp buffer and overflow -----
+    {
+        Timed tz(c, j.s, ST_OTHER);
+        HIP_TRY(c, launch_fill_u64(lb, 0, nt0 * RADIX + 1, j.s));
+        HIP_TRY(c, launch_fill_u32(cnt, 0, RADIX, j.s));
+        HIP_TRY(c, launch_fill_u32(hist_w, 0, RADIX, j.s));
+        HIP_TRY(c, launch_fill_u32(lost, 0, 8, j.s));
+    }
+    {
+        Timed tm(c, j.s, ST_DEAL, true);
+        EstArgs ea{};
+        ea.kin = j.k[0];
+        ea.vin = j.v[0];
+        ea.kout = j.k[1];
+        ea.vout = j.v[1];
+        ea.kovf = kovf;
+        ea.vovf = vovf;
+        ea.n = n;
+        ea.ntiles = (uint32_t)nt0;
+        ea.tile = T;
+        ea.shift = su;
+        ea.width = wu;
+        ea.nshift = sw;
+        ea.nwidth = ww;
+        ea.E = E;
+        ea.C = C;
+        ea.lookback = lb;
+        ea.ticket = (uint32_t*)(lb + nt0 * RADIX);
+        ea.cnt = cnt;
+        ea.next_hist = hist_w;
+        ea.lost = lost;
+        ea.err = j.err_dev;
+        HIP_TRY(c, launch_deal_est(kb, vb, ea, j.s));
+    }
+    // Bucket totals and lost records come back (the exact pass's tiles depend on them).
+    st = pin_reserve(c, (RADIX + 8) * 4 + 64, j.s);
+    if (st) return st;
+    uint32_t* hcnt = palloc<uint32_t>(c, RADIX + 8);
+    HIP_TRY(c, hipMemcpyAsync(hcnt, cnt, RADIX * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipMemcpyAsync(hcnt + RADIX, lost, 8 * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipStreamSynchronize(j.s));
+    std::vector<uint32_t> bcount(hcnt, hcnt + M);
+    const uint32_t nlost = hcnt[RADIX];
+    synced(c);
+    uint64_t total = 0, ovf = 0;
+    for (uint32_t v = 0; v < M; ++v) {
+        total += bcount[v];
+        ovf += bcount[v] > E ? bcount[v] - E : 0;
+    }
+    if (nlost || total != n) return DFR_OK;  // a bucket outgrew its slots: deal it counted
+    *used = true;
+    c->stats.top_digits = 2;
+    c->stats.deal_passes += 1;
+    c->stats.deal_passes_estimated += 1;
+    c->stats.estimated_overflow = (double)ovf / (double)n;
+
+    // --- the exact deal of the upper digit, back into the caller's buffer --------------
+    std::vector<Tile> t1;
+    for (uint32_t v = 0; v < M; ++v) {
+        const uint64_t inmain = std::min<uint64_t>(bcount[v], E), inovf = bcount[v] - inmain;
+        for (uint64_t o = 0; o < inmain; o += T)
+            t1.push_back(Tile{(uint64_t)v * E + o, (uint32_t)std::min<uint64_t>(T, inmain - o), 0});
+        for (uint64_t o = 0; o < inovf; o += T)
+            t1.push_back(Tile{(uint64_t)v * C + o, (uint32_t)std::min<uint64_t>(T, inovf - o), TILE_IN2});
+    }
+    Seg sg{};
+    sg.start = 0;
+    sg.len = n;
+    sg.first_tile = 0;
+    sg.npass = 1;
+    sg.shift[0] = (int8_t)sw;
+    sg.width[0] = (int8_t)ww;
+    sg.hslot[0] = 0;
+    sg.lo_bit = su;
+    st = upload(j, tiles1, t1.data(), t1.size() * sizeof(Tile));
+    if (!st) st = upload(j, dseg, &sg, sizeof sg);
+    if (st) return st;
+    HIP_TRY(c, launch_fill_u64(lb, 0, t1.size() * RADIX + 1, j.s));
+    {
+        Timed tm(c, j.s, ST_DEAL, true);
+        DealArgs da{};
+        da.off = nullptr;  // look-back
+        da.tile = T;
+        da.kin = j.k[1];
+        da.vin = j.v[1];
+        da.kin2 = kovf;
+        da.vin2 = vb ? vovf : nullptr;
+        da.kout = j.k[0];
+        da.vout = j.v[0];
+        da.tiles = tiles1;
+        da.ntiles = (uint32_t)t1.size();
+        da.segs = dseg;
+        da.hist = hist_w;
+        da.hist_digits = 1;
+        da.pass = 0;
+        da.lookback = lb;
+        da.ticket = (uint32_t*)(lb + t1.size() * RADIX);
+        da.err = j.err_dev;
+        HIP_TRY(c, launch_deal(kb, vb, da, j.s));
+    }
+    c->stats.deal_passes += 1;
+    c->stats.deal_passes_lookback += 1;
+
+    // --- buckets (from the keys), classify, local sort ----------------------------------
+    std::vector<Tile> ht;
+    std::vector<uint32_t> ft;
+    build_tiles(std::vector<LSeg>{LSeg{0, n, 8 * kb}}, std::vector<uint32_t>{0}, T, ht, ft);
+    st = upload(j, htiles, ht.data(), ht.size() * sizeof(Tile));
+    if (st) return st;
+    {
+        Timed tm(c, j.s, ST_BUCKETS);
+        HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
+        HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
+        HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
+        HeadArgs ha{};
+        ha.keys = j.k[0];
+        ha.tiles = htiles;
+        ha.ntiles = (uint32_t)ht.size();
+        ha.segs = dseg;
+        ha.tcount = htcount;
+        ha.tbase = htbase;
+        ha.tslot = htslot;
+        ha.bstart = dbstart;
+        ha.bseg = dbseg;
+        ha.bcap = bcap;
+        ha.nbuckets = counters;
+        ha.err = j.err_dev;
+        HIP_TRY(c, launch_heads(kb, ha, j.s));
+        c->stats.levels_heads_keys += 1;
+        ClassifyArgs ca{};
+        ca.bstart = dbstart;
+        ca.bseg = dbseg;
+        ca.nbuckets = counters;
+        ca.bcap = bcap;
+        ca.segs = dseg;
+        ca.wsmall = (uint32_t)wsmall;
+        ca.cap = (uint32_t)j.cap;
+        ca.kbits = 8 * kb;
+        ca.cfirst = cfirst;
+        ca.clast = clast;
+        ca.nslots = (uint32_t)nslots;
+        ca.med = med;
+        ca.nmed = counters + 1;
+        ca.medcap = (uint32_t)medcap;
+        ca.big = big;
+        ca.nbig = counters + 2;
+        ca.bigcap = (uint32_t)bigcap;
+        ca.done = done;
+        ca.ndone = counters + 3;
+        ca.donecap = (uint32_t)bigcap;
+        ca.work = work;
+        ca.nwork = counters + 5;
+        ca.workcap = (uint32_t)(nslots + medcap);
+        ca.err = j.err_dev;
+        HIP_TRY(c, launch_classify(ca, (uint32_t)std::min<uint64_t>((bcap + 255) / 256, 4096), j.s));
+    }
+    {
+        Timed tm(c, j.s, ST_LOCAL);
+        LocalArgs la{};
+        la.kin = j.k[0];
+        la.vin = j.v[0];
+        la.kout = j.k[0];
+        la.vout = j.v[0];
+        la.bstart = dbstart;
+        la.bseg = dbseg;
+        la.nbuckets = counters;
+        la.bcap = bcap;
+        la.segs = dseg;
+        la.cfirst = cfirst;
+        la.clast = clast;
+        la.nslots = (uint32_t)nslots;
+        la.med = med;
+        la.nmed = counters + 1;
+        la.medcap = (uint32_t)medcap;
+        la.work = work;
+        la.nwork = counters + 5;
+        la.workcap = (uint32_t)(nslots + medcap);
+        la.spill = spill;
+        la.nspill = counters + 4;
+        la.spillcap = (uint32_t)(nslots + medcap);
+        la.wide = wide;
+        la.nwide = counters + 6;
+        la.widecap = (uint32_t)(nslots + medcap);
+        la.err = j.err_dev;
+        la.stat = j.err_dev;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 8192);
+        HIP_TRY(c, launch_local_sort(kb, vb, la, blocks, local_sort_first_form(kb, vb, su), j.s));
+    }
+    c->stats.used_diversion = 1;
+    // --- large buckets: the next level's segments --------------------------------------
+    st = pin_reserve(c, 8 * 4 + STAT_WORDS * 4 + bigcap * sizeof(Big) + 256, j.s);
+    if (st) return st;
+    uint32_t* hc = palloc<uint32_t>(c, 8);
+    uint32_t* he = palloc<uint32_t>(c, STAT_WORDS);
+    HIP_TRY(c, hipMemcpyAsync(hc, counters, 8 * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, STAT_WORDS * 4, hipMemcpyDeviceToHost, j.s));
+    HIP_TRY(c, hipStreamSynchronize(j.s));
+    memcpy(j.stat_host, he, sizeof j.stat_host);
+    j.err_word_host = he[STAT_ERR];
+    j.err_known = true;
+    const uint32_t nbig = std::min<uint32_t>(hc[2], (uint32_t)bigcap);
+    c->stats.chunks += hc[5];
+    Big* hb = palloc<Big>(c, std::max<uint32_t>(nbig, 1));
+    if (nbig) {
+        HIP_TRY(c, hipMemcpyAsync(hb, big, nbig * sizeof(Big), hipMemcpyDeviceToHost, j.s));
+        HIP_TRY(c, hipStreamSynchronize(j.s));
+    }
+    std::vector<Big> bigs(hb, hb + nbig);
+    synced(c);
+    c->stats.large_buckets += nbig;
+    std::sort(bigs.begin(), bigs.end(), [](const Big& a, const Big& b) { return a.start < b.start; });
+    for (auto& b : bigs) next.push_back(LSeg{b.start, b.len, (int)b.hi_bit});
+    return DFR_OK;
+}
+
 dfr_status check_err(Job& j) {
     dfr_ctx* c = j.c;
     uint32_t e = j.err_word_host;
@@ -1210,7 +1500,12 @@ dfr_status run_sort(dfr_ctx* c, int kb, int vb, void* keys, void* vals, const st
     while (!large.empty()) {
         std::vector<LSeg> next;
         int next_in = in;
-        st = deal_level(j, large, in, next, &next_in);
+        bool est = false;
+        if (c->est_buckets && j.first_level && small.empty() && large.size() == 1 && !forced) {
+            st = est_level(j, large[0], next, &est);
+            if (st) return st;
+        }
+        if (!est) st = deal_level(j, large, in, next, &next_in);
         if (st) return st;
         j.first_level = false;
         ++level;
@@ -2389,6 +2684,10 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
     }
     if (!strcmp(name, "force_key_heads")) {
         c->force_key_heads = value != 0;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "estimated_buckets")) {
+        c->est_buckets = value != 0;
         return DFR_OK;
     }
     if (!strcmp(name, "serve_workers") || !strcmp(name, "serve_batch_records")) {

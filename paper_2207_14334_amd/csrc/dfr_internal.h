@@ -116,6 +116,37 @@ struct DealArgs {
     const uint32_t* off; // when set: per-tile bucket bases, and no look-back
     uint32_t tile;       // records per tile (selects the kernel; see deal_tile_supported)
     uint32_t* err;
+    const void* kin2;    // tiles whose seg carries TILE_IN2 read from here (overflow areas)
+    const void* vin2;
+};
+
+// Tile flag: the tile's records are in the deal's second input (kin2/vin2), at
+// tile.start there; the segment index is the other bits.
+constexpr uint32_t TILE_IN2 = 1u << 31;
+
+// Fast Radix's deal into estimated buckets (Sec. 3; overflow, Sec. 3.1): one segment
+// [0, n), bucket v's first E records at [v * E, v * E + E) of kout, the next C at
+// [v * C, v * C + C) of kovf, in input order (decoupled look-back over the tiles).
+struct EstArgs {
+    const void* kin;
+    const void* vin;
+    void* kout;
+    void* vout;
+    void* kovf;
+    void* vovf;
+    uint64_t n;
+    uint32_t ntiles;
+    uint32_t tile;
+    int32_t shift, width;    // the dealt digit
+    int32_t nshift, nwidth;  // the next digit, counted for the exact pass that follows
+    uint64_t E;              // estimated slots per bucket
+    uint32_t C;              // overflow slots per bucket
+    uint64_t* lookback;      // [ntiles][RADIX]
+    uint32_t* ticket;
+    uint32_t* cnt;           // [RADIX] records of each bucket, summed over the tiles
+    uint32_t* next_hist;     // [RADIX] histogram of the next digit
+    uint32_t* lost;          // records of buckets that outgrew E + C (then redone exactly)
+    uint32_t* err;
 };
 
 // Bucket heads per tile, at most HEAD_SLOTS of them kept per tile as tile-relative
@@ -269,6 +300,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
 hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
+hipError_t launch_deal_est(int kb, int vb, const EstArgs& a, hipStream_t s);
 hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s);
 hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s);
 // For each segment's digit-j histogram h (digits of `bits` bits):

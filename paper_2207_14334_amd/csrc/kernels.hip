@@ -382,15 +382,17 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     if (t >= a.ntiles) return;
 
     const Tile tl = a.tiles[t];
-    const Seg* sg = a.segs + tl.seg;
+    const uint32_t seg_id = tl.seg & ~TILE_IN2;
+    const bool in2 = (tl.seg & TILE_IN2) != 0;  // a tile of an overflow area
+    const Seg* sg = a.segs + seg_id;
     const uint64_t seg_start = sg->start, seg_end = sg->start + sg->len;
     const uint32_t first_tile = sg->first_tile;
     const int shift = sg->shift[a.pass];
     const uint32_t dmask = (1u << sg->width[a.pass]) - 1u;
     const int hslot = sg->hslot[a.pass];
     const uint32_t len = tl.len;
-    const K* kin = (const K*)a.kin + tl.start;
-    const V* vin = (const V*)a.vin + tl.start;
+    const K* kin = (const K*)(in2 ? a.kin2 : a.kin) + tl.start;
+    const V* vin = (const V*)(in2 ? a.vin2 : a.vin) + tl.start;
 
     K key[ITEMS];
     V val[ITEMS];
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     uint32_t seg_excl = 0;
     if (LOOKBACK) {
         const uint32_t hv =
-            tid < RADIX ? a.hist[((size_t)tl.seg * a.hist_digits + hslot) * RADIX + tid] : 0u;
+            tid < RADIX ? a.hist[((size_t)seg_id * a.hist_digits + hslot) * RADIX + tid] : 0u;
         seg_excl = scan256_excl(hv, s_part, &total);
     }
     const uint32_t loc_excl = scan256_excl(tile_cnt, s_part, &total);
@@ -504,6 +506,157 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
         }
     }
     if (bad) atomicOr(a.err, ERR_RANGE);
+}
+
+// ---------------------------------------------------------------------------------
+// Fast Radix's deal without a count (Sec. 3): bucket v is estimated to hold E = n / 2^b
+// records and gets the slots [v * E, v * E + E); records past its estimate go to its
+// overflow slots [v * C, v * C + C) of a second area, where C is sized from the
+// expected overflow (Eq. 2; a few standard deviations of a bucket's count).  Each
+// record's rank in its bucket comes from decoupled look-back over the tiles (ticket
+// order), so every bucket keeps input order: its estimated slots, then its overflow
+// slots, in that order, are its records in input order.  The tile also counts the next
+// digit of its records: that histogram gives the exact pass that follows its bucket
+// starts (the penultimate pass counts the last digit, Sec. 3).  A record that finds no
+// slot is counted in *lost; the caller then redoes the pass with counted buckets.
+// ---------------------------------------------------------------------------------
+template <int KB, int VB, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_deal_est(EstArgs a) {
+    using K = typename uint_of<KB>::type;
+    using V = typename uint_of<VB>::type;
+    constexpr int W = THREADS / 64;
+    constexpr uint32_t T = THREADS * ITEMS;
+    static_assert(THREADS >= RADIX, "one thread per digit value");
+    __shared__ K s_keys[T];
+    __shared__ V s_vals[VB ? T : 1];
+    __shared__ uint32_t s_wcnt[W * RADIX];
+    __shared__ uint32_t s_delta[RADIX];  // rank in the bucket of staged index 0, mod 2^32
+    __shared__ uint32_t s_local[RADIX];
+    __shared__ uint32_t s_next[RADIX];
+    __shared__ uint32_t s_part[RADIX / 64];
+    __shared__ uint32_t s_ticket, s_lost;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) {
+        s_ticket = atomicAdd(a.ticket, 1u);
+        s_lost = 0;
+    }
+    for (int i = tid; i < W * RADIX; i += THREADS) s_wcnt[i] = 0;
+    for (int i = tid; i < RADIX; i += THREADS) s_next[i] = 0;
+    __syncthreads();
+    const uint32_t t = s_ticket;
+    if (t >= a.ntiles) return;
+    const uint64_t start = (uint64_t)t * a.tile;
+    const uint32_t len = (uint32_t)umin64(a.tile, a.n - start);
+    const uint32_t dmask = (1u << a.width) - 1u, nmask = (1u << a.nwidth) - 1u;
+    const K* kin = (const K*)a.kin + start;
+    const V* vin = (const V*)a.vin + start;
+
+    K key[ITEMS];
+    V val[ITEMS];
+    uint32_t rnk[ITEMS];
+    const uint32_t wbase = (uint32_t)w * ITEMS * 64;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        const bool ok = idx < len;
+        key[k] = ok ? kin[idx] : K(0);
+        if (VB) val[k] = ok ? vin[idx] : V(0);
+    }
+    uint32_t* wc = s_wcnt + w * RADIX;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        const bool ok = idx < len;
+        const uint64_t act = __ballot(ok);
+        const uint32_t d = (uint32_t)(key[k] >> a.shift) & dmask;
+        const uint64_t m = same_digit_lanes<RADIX_BITS>(d, act);
+        const uint32_t below = lanes_below(m);
+        const uint32_t base = wc[d];
+        if (ok && below == 0) wc[d] = base + (uint32_t)__popcll(m);
+        rnk[k] = base + below;
+        if (ok) atomicAdd(&s_next[(uint32_t)(key[k] >> a.nshift) & nmask], 1u);
+    }
+    __syncthreads();
+
+    // Per digit: offsets of each wave's run, the tile's count, its publication, and the
+    // bucket totals; then the rank in the bucket of the tile's first record of the digit.
+    uint32_t tile_cnt = 0;
+    if (tid < RADIX) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = s_wcnt[ww * RADIX + tid];
+            s_wcnt[ww * RADIX + tid] = run;
+            run += c;
+        }
+        tile_cnt = run;
+        __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid], (t == 0 ? LB_PRE : LB_AGG) | (uint64_t)run,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (run) atomicAdd(&a.cnt[tid], run);
+        const uint32_t nx = s_next[tid];
+        if (nx) atomicAdd(&a.next_hist[tid], nx);
+    }
+    uint32_t total;
+    const uint32_t loc_excl = scan256_excl(tile_cnt, s_part, &total);
+    if (tid < RADIX) {
+        s_local[tid] = loc_excl;
+        uint64_t excl = 0;
+        if (t != 0) {
+            uint32_t j = t - 1;
+            for (;;) {
+                const uint64_t x = wait_published(&a.lookback[(size_t)j * RADIX + tid], a.err);
+                excl += x & LB_COUNT;
+                if ((x & LB_PRE) || j == 0) break;
+                --j;
+            }
+            __hip_atomic_store(&a.lookback[(size_t)t * RADIX + tid], LB_PRE | (excl + tile_cnt),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_delta[tid] = (uint32_t)excl - loc_excl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t idx = wbase + k * 64 + lane;
+        if (idx < len) {
+            const uint32_t d = (uint32_t)(key[k] >> a.shift) & dmask;
+            const uint32_t p = wc[d] + s_local[d] + rnk[k];
+            if (p < T) {
+                s_keys[p] = key[k];
+                if (VB) s_vals[p] = val[k];
+            }
+        }
+    }
+    __syncthreads();
+    // Runs of equal digits go to consecutive slots of their bucket (or of its overflow).
+    K* kout = (K*)a.kout;
+    V* vout = (V*)a.vout;
+    K* kovf = (K*)a.kovf;
+    V* vovf = (V*)a.vovf;
+    uint32_t lost = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = (uint32_t)k * THREADS + tid;
+        if (i < len) {
+            const K kk = s_keys[i];
+            const uint32_t d = (uint32_t)(kk >> a.shift) & dmask;
+            const uint64_t r = (uint64_t)(s_delta[d] + i);  // rank in bucket d
+            if (r < a.E) {
+                kout[(uint64_t)d * a.E + r] = kk;
+                if (VB) vout[(uint64_t)d * a.E + r] = s_vals[i];
+            } else if (r - a.E < a.C) {
+                const uint64_t q = (uint64_t)d * a.C + (r - a.E);
+                kovf[q] = kk;
+                if (VB) vovf[q] = s_vals[i];
+            } else {
+                ++lost;
+            }
+        }
+    }
+    if (lost) atomicAdd(&s_lost, lost);
+    __syncthreads();
+    if (tid == 0 && s_lost) atomicAdd(a.lost, s_lost);
 }
 
 // ---------------------------------------------------------------------------------
@@ -2065,6 +2218,27 @@ hipError_t launch_tile_scan(const TileScanArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_scan_a, dim3(a.nblocks), dim3(RADIX), 0, s, a);
     hipLaunchKernelGGL(k_tile_scan_b, dim3(1), dim3(4 * RADIX), 0, s, a);
     hipLaunchKernelGGL(k_tile_scan_c, dim3(a.nblocks), dim3(RADIX), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int KB, int VB>
+static void deal_est_kb_vb(const EstArgs& a, hipStream_t s) {
+    constexpr int ITEMS = (KB + VB <= 8 ? DEAL_TILE_SMALL : DEAL_TILE_LARGE) / DEAL_THREADS;
+    hipLaunchKernelGGL((k_deal_est<KB, VB, DEAL_THREADS, ITEMS>), dim3(a.ntiles), dim3(DEAL_THREADS), 0, s, a);
+}
+
+hipError_t launch_deal_est(int kb, int vb, const EstArgs& a, hipStream_t s) {
+    if (a.ntiles == 0) return hipSuccess;
+    if (a.tile != deal_tile_records(kb, vb)) return hipErrorInvalidValue;
+    if (kb == 4) {
+        if (vb == 0) deal_est_kb_vb<4, 0>(a, s);
+        else if (vb == 4) deal_est_kb_vb<4, 4>(a, s);
+        else deal_est_kb_vb<4, 8>(a, s);
+    } else {
+        if (vb == 0) deal_est_kb_vb<8, 0>(a, s);
+        else if (vb == 4) deal_est_kb_vb<8, 4>(a, s);
+        else deal_est_kb_vb<8, 8>(a, s);
+    }
     return hipGetLastError();
 }
 

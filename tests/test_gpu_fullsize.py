@@ -157,3 +157,29 @@ def test_size_limit_records(env):
     for q in rng.integers(0, n, size=2):
         assert o.rank_of(keys, int(ov[q])) == int(q), int(q)
     print(f"[done] n={n}: levels={st['levels']} deal_passes={st['deal_passes']}", flush=True)
+
+
+# The headline shape dealt the Fast Radix way (estimated buckets for the first deal).
+@pytest.mark.parametrize("bits,n", [(32, 1 << 28), (64, 1 << 27)], ids=["u32-2p28", "u64-2p27"])
+def test_full_size_estimated_buckets(env, bits, n):
+    torch, dfr, ctx = env
+    o = oracle.get()
+    print(f"[case] full-size estimated buckets u{bits} n={n}", flush=True)
+    keys = workloads.make_keys("uniform", n, bits, 0)
+    vals = workloads.index_payload(n, bits)
+    dk = torch.from_numpy(keys).cuda()
+    dv = torch.from_numpy(vals).cuda()
+    ctx.set_option("estimated_buckets", 1)
+    try:
+        ctx.sort_(dk, dv)
+        torch.cuda.synchronize()
+        st = ctx.stats()
+    finally:
+        ctx.set_option("estimated_buckets", 0)
+    ok, ov = dk.cpu().numpy(), dv.cpu().numpy()
+    del dk, dv
+    assert st["deal_passes_estimated"] == 1, st
+    assert o.check_index_payload(keys, ok, ov) is None, st
+    rng = np.random.default_rng(n + 1)
+    for p in rng.integers(0, n, size=2):
+        assert o.rank_of(keys, int(ov[p])) == int(p), int(p)

@@ -684,3 +684,51 @@ def test_calls_on_different_streams(torch, ctx, o):
         assert np.array_equal(host(da), ra[0]), rep
         assert np.array_equal(host(dva), np.sort(ra[1])), rep
         assert np.array_equal(host(db), rb[0]) and np.array_equal(host(dvb), rb[1]), rep
+
+
+# --------------------------------------------------------------------------------------
+# Fast Radix's estimated buckets (Sec. 3; overflow, Sec. 3.1), the "estimated_buckets"
+# option: the first deal without a count, into buckets of n / 2^b slots plus overflow
+# slots; levels whose buckets outgrow their slots are dealt with counted buckets.
+# --------------------------------------------------------------------------------------
+
+def _overflowing_keys(n, seed):
+    """Uniform 32-bit keys whose bits 16..23 take the value 7 about 400 times more than
+    their share: bucket 7 of the estimated deal overflows its n / 256 slots."""
+    k = workloads.make_keys("uniform", n, 32, seed)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(n, 400, replace=False)
+    k[pick] = (k[pick] & np.uint32(0xFF00FFFF)) | np.uint32(7 << 16)
+    return k
+
+
+EST_CASES = [
+    # (key bits, distribution, n, estimated deal expected to be used)
+    (32, "uniform", (1 << 22) + 5, True),
+    (32, "normal", 1 << 22, True),       # bits 16..23 of the normal keys are near uniform
+    (32, "overflow", 1 << 22, True),     # one bucket well over its estimate, within slots
+    (32, "zipf", 1 << 22, False),        # most keys share bits 16..23: counted instead
+    (32, "few", (1 << 21) + 1, False),
+    (64, "uniform", (1 << 21) + 3, True),
+    (64, "skewed", 1 << 21, False),
+]
+
+
+@pytest.mark.parametrize("bits,dist,n,used", EST_CASES, ids=[f"u{b}-{d}-{n}" for b, d, n, _ in EST_CASES])
+def test_estimated_buckets(torch, ctx, o, bits, dist, n, used):
+    k = _overflowing_keys(n, 3) if dist == "overflow" else workloads.make_keys(dist, n, bits, 3)
+    v = workloads.index_payload(n, bits)
+    say("estimated buckets", bits, dist, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, estimated_buckets=1)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    assert st["deal_passes_estimated"] == (1 if used else 0), st
+    if used:
+        assert st["top_digits"] == 2 and st["deal_passes_lookback"] >= 1, st
+        # The overflow the estimated deal met, against the counts of the dealt digit.
+        shift = 8 * (bits // 8) - 16
+        h = np.bincount(((k >> k.dtype.type(shift)) & k.dtype.type(255)).astype(np.int64), minlength=256)
+        e = n // 256
+        assert st["estimated_overflow"] == pytest.approx(np.maximum(h - e, 0).sum() / n, abs=1e-12), st
+    if dist == "overflow":
+        assert st["estimated_overflow"] * n >= 300, st
