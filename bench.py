@@ -245,8 +245,9 @@ def batched_part(torch, dfr, dist, arrays, max_len, steps, plain_runs=1):
     }
 
 
-def serving_part(torch, dfr, requests, rhos, budget_gib):
-    """Poisson request stream: FIFO plain calls against the batching request queue."""
+def serving_part(torch, dfr, requests, rhos, budget_gib, options=()):
+    """Poisson request stream: FIFO plain calls against the batching request queue
+    (library options (name, value) set on its context before the first request)."""
     import threading
 
     import numpy as np
@@ -271,6 +272,8 @@ def serving_part(torch, dfr, requests, rhos, budget_gib):
         torch.cuda.synchronize()
 
     ctx = dfr.Context(0, hbm_budget_bytes=budget_gib << 30)
+    for name, value in options:
+        ctx.set_option(name, value)
     sys.setswitchinterval(2e-4)  # the submitting thread must not wait long for the GIL
     reset()
     for i in range(min(len(work), 30)):
@@ -386,6 +389,7 @@ def serving_part(torch, dfr, requests, rhos, budget_gib):
         "serve_stats": {kk: vv for kk, vv in ctx.serve_stats().items()
                         if kk in ("batches", "requests", "max_batch_requests", "peak_held_bytes",
                                   "allocs")},
+        "options": [f"{name}={value}" for name, value in options],
         "result_check": parity, "requests_checked": 40,
     }
     ctx.close()
@@ -394,7 +398,7 @@ def serving_part(torch, dfr, requests, rhos, budget_gib):
     return out
 
 
-def c1_part(torch, dfr, calls=50):
+def c1_part(torch, dfr, calls=50, options=()):
     """2^20 uint32 keys, key-only (small enough to stay in the caches): wall time of one
     call, from its start to the end of its work on the stream."""
     import numpy as np
@@ -405,6 +409,8 @@ def c1_part(torch, dfr, calls=50):
     base = torch.from_numpy(keys_h).cuda()
     copies = [base.clone() for _ in range(calls + 5)]
     ctx = dfr.Context(0)
+    for name, value in options:
+        ctx.set_option(name, value)
     torch.cuda.synchronize()
     for i in range(5):
         ctx.sort_(copies[i])
@@ -419,7 +425,8 @@ def c1_part(torch, dfr, calls=50):
     ok = np.array_equal(host_np(copies[-1]), np.sort(keys_h))
     ctx.close()
     w = np.array(wall)
-    return {"workload": "2^20 uint32 keys, uniform, key-only, seed 0", "n": n,
+    opts = "".join(f", option {name}={value}" for name, value in options)
+    return {"workload": f"2^20 uint32 keys, uniform, key-only, seed 0{opts}", "n": n,
             "latency_ms": {"median": round(float(np.median(w)), 4), "min": round(float(w.min()), 4),
                            "p90": round(float(np.percentile(w, 90)), 4)},
             "gkeys_per_s": round(n / np.median(w) / 1e6, 3), "calls": calls,
@@ -489,7 +496,7 @@ def main():
     ap.add_argument("--max-len", type=int, default=1 << 20)
     ap.add_argument("--key-type", default="u32", choices=("u32", "u64", "i32", "i64", "f32", "f64"))
     ap.add_argument("--set", action="append", default=[], metavar="OPTION=VALUE",
-                    help="a library option (dfr_set_option) for the plain workload")
+                    help="a library option (dfr_set_option) for the plain or serving workload")
     ap.add_argument("--seeds", type=int, default=3, help="inputs the plain steps cycle through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true",
@@ -513,14 +520,18 @@ def main():
         return
     if args.workload == "serving":
         rhos = args.rho or [0.3, 0.5, 0.7, 0.9, 1.2, 1.5]
-        print(json.dumps({"serving": serving_part(torch, dfr, args.requests, rhos, args.budget_gib)}),
-              flush=True)
+        opts = [(o.split("=", 1)[0], int(o.split("=", 1)[1])) for o in args.set]
+        print(json.dumps({"serving": serving_part(torch, dfr, args.requests, rhos, args.budget_gib,
+                                                  opts)}), flush=True)
         return
     out = run_plain(args, torch, dfr)
     ok = out["result_check"] == "pass"
     if args.workload == "all":
         out["c1"] = c1_part(torch, dfr)
         log(f"c1: {out['c1']}")
+        # The same with the plan taken from the length alone: no read-back before the deal.
+        out["c1_plan_from_length"] = c1_part(torch, dfr, options=[("plan_lengths_records", 1 << 22)])
+        log(f"c1 plan from length: {out['c1_plan_from_length']}")
         out["normal"] = dist_part(torch, dfr, "normal")
         log(f"normal: {out['normal']}")
         # Fast Radix's estimated buckets for the first deal (no count) on the headline
@@ -532,8 +543,8 @@ def main():
         out["serving"] = serving_part(torch, dfr, args.requests, args.rho or [0.7, 0.9],
                                       args.budget_gib)
         ok = ok and all(p["result_check"] == "pass" for p in
-                        [out["c1"], out["normal"], out["estimated_buckets"], out["serving"],
-                         *out["batched"]])
+                        [out["c1"], out["c1_plan_from_length"], out["normal"],
+                         out["estimated_buckets"], out["serving"], *out["batched"]])
     out["wall_s"] = round(time.perf_counter() - wall0, 1)
     print(json.dumps(out), flush=True)
     if not ok:

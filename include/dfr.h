@@ -192,10 +192,11 @@ dfr_status dfr_stream_copy(dfr_ctx* ctx, const void* src, void* dst, size_t byte
 /* ---------------------------------------------------------------------------------
  * Serving: submit sort requests of any size and width, poll for completion.
  *
- * Requests are sorted by worker threads of the context (2 by default), each with its
+ * Requests are sorted by worker threads of the context (3 by default), each with its
  * own HIP stream and scratch.  A worker takes the oldest queued request and every
- * later queued request with the same widths, up to "serve_batch_records" records in
- * all, and sorts them as one segmented sort (each request is one segment, so the
+ * later queued request with the same widths and at most "serve_gather_records"
+ * records, up to "serve_batch_records" records in all (a larger request is sorted
+ * alone), and sorts them as one segmented sort (each request is one segment, so the
  * result is the one a plain sort of that request alone gives): the records are
  * gathered into a staging buffer, sorted, and scattered back into the requests' own
  * buffers (a batch of one request is sorted in place).  Requests that arrive while
@@ -275,14 +276,23 @@ dfr_status dfr_get_serve_stats(dfr_ctx* ctx, dfr_serve_stats* out);
  *                     that pass and dealt exactly; a level whose buckets outgrow their
  *                     slots is dealt with counted buckets instead.  Same result.  0 to
  *                     restore.
+ *   "plan_lengths_records" first levels whose segments all hold at most this many
+ *                     records choose their top digits from the lengths alone, as for
+ *                     uniform keys (Sec. 3.1), instead of from their digit histograms,
+ *                     so that nothing is read back before their deals (a one-level sort
+ *                     then waits on the device only at its end); skewed keys may then
+ *                     leave large buckets to a second level.  0 (the default) always
+ *                     plans from the histograms.  Same result.
  *   "radix_bits"      digit width b of the deal passes, 4..8 with at most 8 digits
  *                     per key (so 8 for 64-bit keys); the paper's digits are 8 bits
  *                     (Sec. 4).  0 = tuned or default.
  *   "tile_records"    records per deal tile: dfr_deal_tile_records(kb, vb) or half
  *                     of it.  0 = tuned or default.
- *   "serve_workers"   worker threads of the serving queue, 1..8 (default 2), and
- *   "serve_batch_records" most records in one serving batch (default 2^25); both
- *                     only before the first dfr_submit (DFR_E_UNSUPPORTED after).
+ *   "serve_workers"   worker threads of the serving queue, 1..8 (default 3),
+ *   "serve_batch_records" most records in one serving batch (default 2^25), and
+ *   "serve_gather_records" largest request gathered into a batch with others (larger
+ *                     ones are sorted alone, in place; default 2^20, 0 = no limit); all
+ *                     three only before the first dfr_submit (DFR_E_UNSUPPORTED after).
  *   "window_records"  width of the windows that pack runs of small buckets into
  *                     local-sort chunks (Sec. 3: runs of small buckets), 16 ..
  *                     capacity / 2.  0 = tuned or default.
@@ -322,6 +332,8 @@ typedef struct {
     int32_t levels_heads_counts;  /* ... from the two dealt digits' counts           */
     int32_t levels_heads_hist;    /* ... from the dealt digit's histograms           */
     int32_t deal_passes_estimated; /* deal launches into estimated buckets (Sec. 3) */
+    int32_t plan_from_lengths;    /* 1 if the first level was planned from the segment
+                                     lengths alone (no read-back before its deals)  */
 } dfr_stats;
 
 dfr_status dfr_get_stats(const dfr_ctx* ctx, dfr_stats* out);

@@ -69,6 +69,7 @@ class Stats(ctypes.Structure):
         ("deal_passes_scanned", ctypes.c_int32), ("deal_passes_lookback", ctypes.c_int32),
         ("levels_heads_keys", ctypes.c_int32), ("levels_heads_counts", ctypes.c_int32),
         ("levels_heads_hist", ctypes.c_int32), ("deal_passes_estimated", ctypes.c_int32),
+        ("plan_from_lengths", ctypes.c_int32),
     ]
 
     def as_dict(self):

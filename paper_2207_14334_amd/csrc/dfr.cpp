@@ -102,6 +102,8 @@ struct dfr_ctx {
     bool force_lookback = false;  // deal every level with decoupled look-back
     bool force_key_heads = false;  // find bucket heads from the keys on every level
     bool est_buckets = false;      // first level of plain sorts: Fast Radix estimated buckets
+    uint64_t plan_lengths_max = 0;  // first levels of segments this short plan from their
+                                    // lengths alone (0: never)
     int radix_bits = 0;           // 0 = tuned or default
     uint32_t tile_records = 0;
     size_t window = 0;
@@ -125,8 +127,9 @@ struct dfr_ctx {
     // Request serving (dfr_submit / dfr_poll), started by the first submit.
     std::mutex serve_mu;
     struct Server* server = nullptr;
-    int serve_workers = 2;
+    int serve_workers = 3;
     uint64_t serve_batch_records = 1ull << 25;
+    uint64_t serve_gather_records = 1ull << 20;  // largest request gathered into a batch
 };
 
 namespace {
@@ -652,30 +655,56 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // Collision estimates, non-empty bins, overflow, OR and AND lie next to each other in
     // the arena: one copy brings them all back.
     const size_t readback = off_and + asize<uint64_t>(S) - off_coll;
-    st = pin_reserve(c, readback + ALIGN, j.s);
-    if (st) return st;
-    char* h_rb = palloc<char>(c, readback);
-    HIP_TRY(c, hipMemcpyAsync(h_rb, c->arena + off_coll, readback, hipMemcpyDeviceToHost, j.s));
-    HIP_TRY(c, hipStreamSynchronize(j.s));
-    const double* h_coll = (const double*)h_rb;
-    const uint32_t* h_nz = (const uint32_t*)(h_rb + (off_nz - off_coll));
-    const uint32_t* h_ovf = (const uint32_t*)(h_rb + (off_ovf - off_coll));
-    const uint64_t* h_or = (const uint64_t*)(h_rb + (off_or - off_coll));
-    const uint64_t* h_and = (const uint64_t*)(h_rb + (off_and - off_coll));
+    // A first level whose segments are all short plans from their lengths alone: every
+    // digit taken as varying and uniform, the paper's estimate of the top digits for
+    // uniform keys (Sec. 3, Sec. 3.1).  Nothing is read back before its deals, so a
+    // one-level sort waits on the device only at its end.  A guess that leaves a bucket
+    // too large for the local sort only sends it to the next level; a constant digit is
+    // only a deal that moves nothing.
+    uint64_t max_len = 0;
+    for (const LSeg& g : segs) max_len = std::max<uint64_t>(max_len, g.len);
+    const bool from_lengths = j.first_level && j.top_d_forced == 0 && c->plan_lengths_max > 0 &&
+                              max_len <= c->plan_lengths_max;
     std::vector<uint64_t> vor(S), vand(S);
-    for (size_t i = 0; i < S; ++i) {
-        if (kb == 4) {
-            vor[i] = ((const uint32_t*)h_or)[i];
-            vand[i] = ((const uint32_t*)h_and)[i];
-        } else {
-            vor[i] = h_or[i];
-            vand[i] = h_and[i];
+    std::vector<double> coll(S * ndig);
+    std::vector<uint32_t> nonzero(S * ndig), overflow(S * ndig, 0);
+    auto digit_width = [&](int dig) { return std::min(rb, 8 * kb - rb * dig); };
+    if (from_lengths) {
+        const uint64_t all = kb == 8 ? ~0ull : 0xffffffffull;
+        for (size_t i = 0; i < S; ++i) {
+            vor[i] = all;
+            vand[i] = 0;
+            for (int dg = 0; dg < ndig; ++dg) {
+                coll[i * ndig + dg] = 1.0 / (double)(1u << digit_width(dg));
+                nonzero[i * ndig + dg] = 1u << digit_width(dg);
+            }
         }
+        c->stats.plan_from_lengths = 1;
+    } else {
+        st = pin_reserve(c, readback + ALIGN, j.s);
+        if (st) return st;
+        char* h_rb = palloc<char>(c, readback);
+        HIP_TRY(c, hipMemcpyAsync(h_rb, c->arena + off_coll, readback, hipMemcpyDeviceToHost, j.s));
+        HIP_TRY(c, hipStreamSynchronize(j.s));
+        const double* h_coll = (const double*)h_rb;
+        const uint32_t* h_nz = (const uint32_t*)(h_rb + (off_nz - off_coll));
+        const uint32_t* h_ovf = (const uint32_t*)(h_rb + (off_ovf - off_coll));
+        const uint64_t* h_or = (const uint64_t*)(h_rb + (off_or - off_coll));
+        const uint64_t* h_and = (const uint64_t*)(h_rb + (off_and - off_coll));
+        for (size_t i = 0; i < S; ++i) {
+            if (kb == 4) {
+                vor[i] = ((const uint32_t*)h_or)[i];
+                vand[i] = ((const uint32_t*)h_and)[i];
+            } else {
+                vor[i] = h_or[i];
+                vand[i] = h_and[i];
+            }
+        }
+        coll.assign(h_coll, h_coll + S * ndig);
+        nonzero.assign(h_nz, h_nz + S * ndig);
+        overflow.assign(h_ovf, h_ovf + S * ndig);
+        synced(c);
     }
-    const std::vector<double> coll(h_coll, h_coll + S * ndig);
-    const std::vector<uint32_t> nonzero(h_nz, h_nz + S * ndig);
-    const std::vector<uint32_t> overflow(h_ovf, h_ovf + S * ndig);
-    synced(c);
 
     // --- 2. plan ------------------------------------------------------------------
     // Per segment: its varying digits (from OR/AND) and the digits d_s to deal (forced
@@ -712,7 +741,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         d = std::max(d, di);
     }
     c->arena_used = region_a;  // the rest of the arena is free again
-    if (j.first_level) {
+    if (j.first_level && !from_lengths) {
         // What Fast Radix's estimated buckets would have overflowed on the top varying
         // digit of each segment (Sec. 3.1; Eq. 2 gives its expectation for uniform keys).
         double ov = 0, len = 0;
@@ -1113,7 +1142,30 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // The status block comes back with the counters: no kernel after this point can
     // change it unless another level runs (which clears err_known).
     HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, STAT_WORDS * 4, hipMemcpyDeviceToHost, j.s));
+    // A level planned from its lengths brings its digit statistics back now, for the
+    // estimated-bucket overflow of its top varying digit.
+    char* h_plan = nullptr;
+    if (from_lengths) {
+        st = pin_reserve(c, readback + ALIGN, j.s);
+        if (st) return st;
+        h_plan = palloc<char>(c, readback);
+        HIP_TRY(c, hipMemcpyAsync(h_plan, c->arena + off_coll, readback, hipMemcpyDeviceToHost, j.s));
+    }
     HIP_TRY(c, hipStreamSynchronize(j.s));
+    if (h_plan) {
+        const uint32_t* h_ovf = (const uint32_t*)(h_plan + (off_ovf - off_coll));
+        const uint64_t* h_or = (const uint64_t*)(h_plan + (off_or - off_coll));
+        const uint64_t* h_and = (const uint64_t*)(h_plan + (off_and - off_coll));
+        double ov = 0, len = 0;
+        for (uint32_t i : active) {
+            const uint64_t o = kb == 4 ? ((const uint32_t*)h_or)[i] : h_or[i];
+            const uint64_t a = kb == 4 ? ((const uint32_t*)h_and)[i] : h_and[i];
+            const std::vector<int> vv = varying_digits(o, a, kb, rb);
+            if (!vv.empty()) ov += h_ovf[i * ndig + vv[0]];
+            len += (double)segs[i].len;
+        }
+        c->stats.estimated_overflow = len > 0 ? ov / len : 0.0;
+    }
     memcpy(j.stat_host, he, sizeof j.stat_host);
     j.err_word_host = he[STAT_ERR];
     j.err_known = true;
@@ -1849,6 +1901,7 @@ struct Server {
     bool stop = false;
     size_t budget = 0;
     uint64_t batch_records = 0;
+    uint64_t gather_records = 0;
     size_t held = 0;
     std::vector<Worker> workers;
     std::vector<std::thread> threads;
@@ -2021,15 +2074,17 @@ void worker_loop(Server* sv, int wi) {
     for (;;) {
         sv->cv.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
         if (sv->stop) break;
-        // The oldest request, then later ones of the same widths, within the limit.
+        // The oldest request, then later ones of the same widths, within the limit.  A
+        // request above the gather limit is sorted alone, in place (gathering it would
+        // copy it twice), and is not gathered into another's batch.
         const Server::Req& head = sv->pending.front();
         const int kb = head.r.key_bytes, vb = head.r.val_bytes;
         std::vector<size_t> pick{0};
         uint64_t total = head.r.n;
-        for (size_t i = 1; i < sv->pending.size(); ++i) {
+        for (size_t i = 1; i < sv->pending.size() && head.r.n <= sv->gather_records; ++i) {
             const Server::Req& q = sv->pending[i];
             if (q.r.key_bytes != kb || q.r.val_bytes != vb) continue;
-            if (total + q.r.n > sv->batch_records) continue;
+            if (q.r.n > sv->gather_records || total + q.r.n > sv->batch_records) continue;
             pick.push_back(i);
             total += q.r.n;
         }
@@ -2118,6 +2173,7 @@ dfr_status start_server(dfr_ctx* c) {
     sv->owner = c;
     sv->budget = c->budget;
     sv->batch_records = std::max<uint64_t>(c->serve_batch_records, 1);
+    sv->gather_records = c->serve_gather_records;
     const int nw = std::max(1, std::min(c->serve_workers, 8));
     sv->workers.resize(nw);
     for (int i = 0; i < nw; ++i) {
@@ -2690,15 +2746,24 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
         c->est_buckets = value != 0;
         return DFR_OK;
     }
-    if (!strcmp(name, "serve_workers") || !strcmp(name, "serve_batch_records")) {
+    if (!strcmp(name, "plan_lengths_records")) {
+        if (value < 0) return DFR_E_INVALID_ARG;
+        c->plan_lengths_max = (uint64_t)value;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "serve_workers") || !strcmp(name, "serve_batch_records") ||
+        !strcmp(name, "serve_gather_records")) {
         std::lock_guard<std::mutex> g(c->serve_mu);
         if (c->server) return DFR_E_UNSUPPORTED;  // fixed once serving has started
         if (!strcmp(name, "serve_workers")) {
             if (value < 1 || value > 8) return DFR_E_INVALID_ARG;
             c->serve_workers = (int)value;
-        } else {
+        } else if (!strcmp(name, "serve_batch_records")) {
             if (value < 1) return DFR_E_INVALID_ARG;
             c->serve_batch_records = (uint64_t)value;
+        } else {
+            if (value < 0) return DFR_E_INVALID_ARG;
+            c->serve_gather_records = value == 0 ? ~0ull : (uint64_t)value;
         }
         return DFR_OK;
     }

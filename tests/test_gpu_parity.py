@@ -337,12 +337,41 @@ def test_segmented_mixed_plans(torch, ctx, o, bits):
     k = np.concatenate(keys)
     n = k.size
     v = workloads.index_payload(n, bits)
-    say("segmented_mixed", bits, n)
-    dk, dv = dev(torch, k), dev(torch, v)
-    ctx.sort_segmented_(dk, dv, off)
-    torch.cuda.synchronize()
     rk, rv = o.segmented_sort(k, v, off)
-    assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), ctx.stats()
+    # Plans from each segment's digit histograms (the read-back plan, the default), and
+    # from the lengths alone.
+    for from_hist in (1, 0):
+        say("segmented_mixed", bits, n, "histogram plans" if from_hist else "length plans")
+        if not from_hist:
+            ctx.set_option("plan_lengths_records", 1 << 22)
+        try:
+            dk, dv = dev(torch, k), dev(torch, v)
+            ctx.sort_segmented_(dk, dv, off)
+            torch.cuda.synchronize()
+            st = ctx.stats()
+        finally:
+            ctx.set_option("plan_lengths_records", 0)
+        assert np.array_equal(host(dk), rk) and np.array_equal(host(dv), rv), st
+        assert st["plan_from_lengths"] == 1 - from_hist, st
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf", "few", "narrow", "equal", "sorted"])
+def test_plan_from_lengths(torch, ctx, o, dist):
+    """With the plan_lengths_records option, a first level of short segments picks its
+    top digits from its length alone (no read-back before its deals): skewed, narrow or
+    constant keys then leave large buckets for the next level or deal digits that do not
+    vary; the result matches the oracle either way, and the same as the histogram plan."""
+    n = (1 << 21) + 77
+    k = workloads.make_keys(dist, n, 32, 19)
+    v = workloads.index_payload(n)
+    say("plan from lengths", dist, n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, plan_lengths_records=1 << 22)
+    hk, hv, ht = gpu_sort(torch, ctx, k, v)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    assert np.array_equal(hk, rk) and np.array_equal(hv, rv), ht
+    assert st["plan_from_lengths"] == 1 and st["top_digits"] == 2, st
+    assert ht["plan_from_lengths"] == 0, ht
 
 
 @pytest.mark.parametrize("bits,n", [(32, (1 << 25) + 12345), (64, (1 << 23) + 77)])
