@@ -338,17 +338,10 @@ def serving_part(torch, dfr, requests, rhos, budget_gib, options=()):
         end = max(arrive[i] + lat[i] for i in range(n))
         return lat, end
 
-    # Warm the workers up as the plain calls were: the largest requests of each width
-    # once, so that their buffers exist before the timed runs.
-    reset()
-    warm = []
-    for bits in (32, 64):
-        idx = [i for i, r in enumerate(stream_def) if r[2] == bits]
-        for i in sorted(idx, key=lambda i: -stream_def[i][1])[:4]:
-            warm.append(ctx.submit(*work[i]))
-    for t in warm:
-        while not ctx.poll(t)[0]:
-            time.sleep(1e-4)
+    # Warm the workers up as the plain calls were (these ran the whole stream once): one
+    # untimed served pass of the whole stream at the highest load, so that every worker's
+    # buffers have grown to their working size before the timed runs.
+    served(unit_arrivals * svc_mean / max(rhos))
     by_rho = {}
     st0 = ctx.serve_stats()
     for rho in rhos:

@@ -1863,20 +1863,20 @@ __global__ __launch_bounds__(THREADS) void k_copy_tiles(const void* kin, const v
 
 // Copy of runs between arbitrary addresses (gathering requests into one batch and
 // scattering the sorted batch back).  Runs are whole 4-byte words; where source and
-// destination are both 16-byte aligned the body moves as 16-byte vectors, four in
-// flight per thread.
+// destination are both 16-byte aligned the body moves as 16-byte vectors, four loads in
+// flight per thread before their stores.
+typedef unsigned int copy4u __attribute__((ext_vector_type(4)));
 template <int THREADS>
 __device__ __forceinline__ void copy_run(const void* src, void* dst, uint64_t bytes) {
     const uint32_t tid = threadIdx.x;
     if ((((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) {
-        const uint4* s4 = (const uint4*)src;
-        uint4* d4 = (uint4*)dst;
+        const copy4u* s4 = (const copy4u*)src;
+        copy4u* d4 = (copy4u*)dst;
         const uint64_t nvec = bytes >> 4;
         for (uint64_t i = tid; i < nvec; i += 4 * THREADS) {
-            uint4 r[4];
+            copy4u r[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (i + u * THREADS < nvec) r[u] = s4[i + u * THREADS];
+            for (int u = 0; u < 4; ++u) r[u] = i + u * THREADS < nvec ? s4[i + u * THREADS] : (copy4u)(0u);
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (i + u * THREADS < nvec) d4[i + u * THREADS] = r[u];
@@ -1892,8 +1892,7 @@ __device__ __forceinline__ void copy_run(const void* src, void* dst, uint64_t by
         for (uint64_t i = tid; i < nw; i += 4 * THREADS) {
             uint32_t r[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (i + u * THREADS < nw) r[u] = sw[i + u * THREADS];
+            for (int u = 0; u < 4; ++u) r[u] = i + u * THREADS < nw ? sw[i + u * THREADS] : 0u;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (i + u * THREADS < nw) dw[i + u * THREADS] = r[u];
@@ -1911,20 +1910,25 @@ __global__ __launch_bounds__(THREADS) void k_copy_chunks(const CopyChunk* chunks
 }
 
 // Streaming copy of 16-byte vectors, the bandwidth reference for the passes above (each
-// of which reads and writes every record once): every thread keeps STREAM_U loads in
-// flight, and consecutive threads touch consecutive vectors.
-constexpr int STREAM_THREADS = 256, STREAM_U = 8;
-__global__ __launch_bounds__(STREAM_THREADS) void k_stream_copy(const uint4* src, uint4* dst, uint64_t nvec) {
-    const uint64_t stride = (uint64_t)gridDim.x * STREAM_THREADS * STREAM_U;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * STREAM_THREADS * STREAM_U + threadIdx.x; i0 < nvec;
-         i0 += stride) {
-        uint4 r[STREAM_U];
+// of which reads and writes every record once).  Each block copies one contiguous run of
+// STREAM_THREADS * STREAM_U vectors: all its loads issue before its stores, consecutive
+// lanes touch consecutive vectors, and the lines are streamed past the caches
+// (non-temporal), since nothing reads them again.
+constexpr int STREAM_THREADS = 256, STREAM_U = 4;
+typedef unsigned int vec4u __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(STREAM_THREADS) void k_stream_copy(const vec4u* __restrict__ src,
+                                                                vec4u* __restrict__ dst, uint64_t nvec) {
+    const uint64_t i0 = (uint64_t)blockIdx.x * STREAM_THREADS * STREAM_U + threadIdx.x;
+    vec4u r[STREAM_U];
 #pragma unroll
-        for (int u = 0; u < STREAM_U; ++u)
-            if (i0 + (uint64_t)u * STREAM_THREADS < nvec) r[u] = src[i0 + (uint64_t)u * STREAM_THREADS];
+    for (int u = 0; u < STREAM_U; ++u) {
+        const uint64_t i = i0 + (uint64_t)u * STREAM_THREADS;
+        r[u] = i < nvec ? __builtin_nontemporal_load(src + i) : (vec4u)(0u);
+    }
 #pragma unroll
-        for (int u = 0; u < STREAM_U; ++u)
-            if (i0 + (uint64_t)u * STREAM_THREADS < nvec) dst[i0 + (uint64_t)u * STREAM_THREADS] = r[u];
+    for (int u = 0; u < STREAM_U; ++u) {
+        const uint64_t i = i0 + (uint64_t)u * STREAM_THREADS;
+        if (i < nvec) __builtin_nontemporal_store(r[u], dst + i);
     }
 }
 
@@ -1932,10 +1936,10 @@ hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStr
     const uint64_t nvec = bytes / 16;
     if (nvec == 0) return hipSuccess;
     const uint64_t per_block = (uint64_t)STREAM_THREADS * STREAM_U;
-    // Enough blocks to fill the 256 CUs several times over, each looping if needed.
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((nvec + per_block - 1) / per_block, 256u * 32u);
-    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(STREAM_THREADS), 0, s, (const uint4*)src,
-                       (uint4*)dst, nvec);
+    const uint64_t blocks = (nvec + per_block - 1) / per_block;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stream_copy, dim3((uint32_t)blocks), dim3(STREAM_THREADS), 0, s,
+                       (const vec4u*)src, (vec4u*)dst, nvec);
     return hipGetLastError();
 }
 
