@@ -256,7 +256,10 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
         __syncthreads();
     };
 
-    // One key into the wave's bins; `skew` marks digits added per group of lanes.
+    // One key into the wave's bins; `skew` marks digits added per group of lanes: the
+    // lanes sharing the first active lane's digit, then those sharing the digit of the
+    // first lane outside that group, each add their number in one LDS atomic (so a
+    // value most lanes share is grouped even when the first lane holds another).
     auto add_key = [&](K key, uint32_t skew) {
         vor |= key;
         vand &= key;
@@ -265,8 +268,17 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
             if ((skew >> j) & 1u) {
                 const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
                 const uint64_t m0 = __ballot(d == d0);
+                const uint64_t mo = __ballot(d != d0);
+                uint32_t d1 = d0;
+                uint64_t m1 = 0;
+                if (mo) {
+                    d1 = __builtin_amdgcn_readlane(d, __ffsll((unsigned long long)mo) - 1);
+                    m1 = __ballot(d == d1);
+                }
                 if (d == d0) {
                     if (lanes_below(m0) == 0) atomicAdd(&hw[j * RADIX + d0], (uint32_t)__popcll(m0));
+                } else if (d == d1) {
+                    if (lanes_below(m1) == 0) atomicAdd(&hw[j * RADIX + d1], (uint32_t)__popcll(m1));
                 } else {
                     atomicAdd(&hw[j * RADIX + d], 1u);
                 }
@@ -302,7 +314,8 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
                 buf[r] = v < nvec ? vp[v] : make_uint4(0, 0, 0, 0);
             }
             // Skew test on each wave's first vector: digits on which more than a quarter
-            // of the lanes share the first lane's value.
+            // of the lanes share the first lane's value, or the value of the first lane
+            // that differs from it.
             uint32_t skew = 0;
             {
                 const K k0 = (K)buf[0].x | (KB == 8 ? ((K)buf[0].y << (8 * KB / 2)) : K(0));
@@ -310,7 +323,14 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
                 for (int j = 0; j < ndig; ++j) {
                     const uint32_t d = (uint32_t)(k0 >> (base + j * bits)) & dmask;
                     const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                    if (__popcll(__ballot(ok0 && d == d0)) > 16) skew |= 1u << j;
+                    const uint64_t m0 = __ballot(ok0 && d == d0), mo = __ballot(ok0 && d != d0);
+                    uint32_t most = (uint32_t)__popcll(m0);
+                    if (mo) {
+                        const uint32_t d1 = __builtin_amdgcn_readlane(d, __ffsll((unsigned long long)mo) - 1);
+                        const uint32_t c1 = (uint32_t)__popcll(__ballot(ok0 && d == d1));
+                        most = c1 > most ? c1 : most;
+                    }
+                    if (most > 16) skew |= 1u << j;
                 }
             }
 #pragma unroll
