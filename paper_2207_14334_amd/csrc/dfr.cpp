@@ -55,6 +55,8 @@ enum Stage { ST_COUNT = 0, ST_DEAL, ST_BUCKETS, ST_LOCAL, ST_OTHER, ST_N };
 
 // Largest segment, in tiles, whose bucket bases one block scans ahead of the deal.
 constexpr uint64_t kSegScanTiles = 1024;
+// Longest single segment (in tiles) whose bases one block walks.
+constexpr uint64_t kSingleWalkTiles = 256;
 // Most segments of a level whose tiles are scanned segment by segment with the
 // one-segment scan when some segment is longer than kSegScanTiles.
 constexpr size_t kPerSegScanMax = 16;
@@ -588,7 +590,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint64_t max_seg_tiles = 0;
     for (const LSeg& g : segs) max_seg_tiles = std::max<uint64_t>(max_seg_tiles, (g.len + j.tile - 1) / j.tile);
     const bool single = S == 1 && !c->force_lookback;
-    const bool segscan = S > 1 && max_seg_tiles <= kSegScanTiles && !c->force_lookback;
+    // A short single segment takes the one-block walk too: one launch instead of three.
+    const bool segscan = !c->force_lookback && (S > 1 ? max_seg_tiles <= kSegScanTiles
+                                                      : S == 1 && max_seg_tiles <= kSingleWalkTiles);
     const bool perseg = S > 1 && !segscan && S <= kPerSegScanMax && !c->force_lookback;
     const bool nolb = single || segscan || perseg;
     const size_t tcnt_n = nolb ? tiles.size() * ndig * RADIX : 0;
@@ -622,9 +626,12 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     if (st) return st;
     {
         Timed tm(c, j.s, ST_COUNT);
-        HIP_TRY(c, launch_fill_u32(dhist, 0, hist_n, j.s));
-        HIP_TRY(c, launch_fill_u64(dor, 0, S, j.s));
-        HIP_TRY(c, launch_fill_u64(dand, ~0ull, S, j.s));
+        FillSet fs{};
+        fs.count = 3;
+        fs.p[0] = dhist, fs.v[0] = 0, fs.n[0] = hist_n, fs.w[0] = 4;
+        fs.p[1] = dor, fs.v[1] = 0, fs.n[1] = S, fs.w[1] = 8;
+        fs.p[2] = dand, fs.v[2] = ~0ull, fs.n[2] = S, fs.w[2] = 8;
+        HIP_TRY(c, launch_fill_set(fs, j.s));
         CountArgs ca{};
         ca.keys = j.k[in];
         ca.tiles = dtiles;
@@ -907,7 +914,22 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             const uint32_t grid = (ntp + ca.tiles_per_block - 1) / ca.tiles_per_block;
             HIP_TRY(c, launch_count(kb, ca, grid, j.s));
         }
-        if (single) {
+        if (segscan) {
+            SegScanArgs sa{};
+            sa.segs = dsegs;
+            sa.nsegs = (uint32_t)S;
+            sa.hist = dhist;
+            sa.hist_digits = ndig;
+            sa.cnt = p == 0 ? tcnt : tone;
+            sa.cnt_ndig = p == 0 ? ndig : 1;
+            sa.cnt_from_count_tiles = p == 0;
+            sa.pass = p;
+            sa.tile = j.tile;
+            sa.off = toff;
+            sa.ticket = lb + ntiles * RADIX;
+            Timed ts(c, j.s, ST_OTHER);
+            HIP_TRY(c, launch_seg_scan(sa, j.s));
+        } else if (single) {
             const Seg& g = hs[active[0]];
             TileScanArgs ta{};
             ta.cnt = p == 0 ? tcnt : tone;
@@ -918,9 +940,9 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
             ta.nblocks = scan_nb;
             ta.partial = tpart;
             ta.off = toff;
+            ta.ticket = lb + ntiles * RADIX;
             Timed ts(c, j.s, ST_OTHER);
             HIP_TRY(c, launch_tile_scan(ta, j.s));
-            HIP_TRY(c, launch_fill_u64(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
         } else if (perseg) {
             // A few long segments: the one-segment scan over each segment's tiles.
             Timed ts(c, j.s, ST_OTHER);
@@ -940,21 +962,6 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                 ta.off = toff + (size_t)g.first_tile * RADIX;
                 HIP_TRY(c, launch_tile_scan(ta, j.s));
             }
-            HIP_TRY(c, launch_fill_u64(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
-        } else if (segscan) {
-            SegScanArgs sa{};
-            sa.segs = dsegs;
-            sa.nsegs = (uint32_t)S;
-            sa.hist = dhist;
-            sa.hist_digits = ndig;
-            sa.cnt = p == 0 ? tcnt : tone;
-            sa.cnt_ndig = p == 0 ? ndig : 1;
-            sa.cnt_from_count_tiles = p == 0;
-            sa.pass = p;
-            sa.tile = j.tile;
-            sa.off = toff;
-            Timed ts(c, j.s, ST_OTHER);
-            HIP_TRY(c, launch_seg_scan(sa, j.s));
             HIP_TRY(c, launch_fill_u64(lb + ntiles * RADIX, 0, 1, j.s));  // tile ticket
         } else {
             HIP_TRY(c, launch_fill_u64(lb, 0, ntiles * RADIX + 1, j.s));
@@ -997,9 +1004,12 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     // --- 4. buckets ---------------------------------------------------------------
     {
         Timed tm(c, j.s, ST_BUCKETS);
-        HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
-        HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
-        HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
+        FillSet fs{};
+        fs.count = 3;
+        fs.p[0] = counters, fs.v[0] = 0, fs.n[0] = 8, fs.w[0] = 4;
+        fs.p[1] = cfirst, fs.v[1] = 0xffffffffu, fs.n[1] = nslots, fs.w[1] = 4;
+        fs.p[2] = clast, fs.v[2] = 0, fs.n[2] = nslots, fs.w[2] = 4;
+        HIP_TRY(c, launch_fill_set(fs, j.s));
         // One segment dealt on two digits, bases scanned ahead: its buckets are the
         // non-empty digit pairs, counted from the first digit's histogram and the second
         // deal's per-tile counts, so the keys need not be read again.
@@ -1268,10 +1278,13 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
     // --- the estimated deal of the lower digit into the temp buffer and overflow -----
     {
         Timed tz(c, j.s, ST_OTHER);
-        HIP_TRY(c, launch_fill_u64(lb, 0, nt0 * RADIX + 1, j.s));
-        HIP_TRY(c, launch_fill_u32(cnt, 0, RADIX, j.s));
-        HIP_TRY(c, launch_fill_u32(hist_w, 0, RADIX, j.s));
-        HIP_TRY(c, launch_fill_u32(lost, 0, 8, j.s));
+        FillSet fs{};
+        fs.count = 4;
+        fs.p[0] = lb, fs.v[0] = 0, fs.n[0] = nt0 * RADIX + 1, fs.w[0] = 8;
+        fs.p[1] = cnt, fs.v[1] = 0, fs.n[1] = RADIX, fs.w[1] = 4;
+        fs.p[2] = hist_w, fs.v[2] = 0, fs.n[2] = RADIX, fs.w[2] = 4;
+        fs.p[3] = lost, fs.v[3] = 0, fs.n[3] = 8, fs.w[3] = 4;
+        HIP_TRY(c, launch_fill_set(fs, j.s));
     }
     {
         Timed tm(c, j.s, ST_DEAL, true);
@@ -1376,9 +1389,12 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
     if (st) return st;
     {
         Timed tm(c, j.s, ST_BUCKETS);
-        HIP_TRY(c, launch_fill_u32(counters, 0, 8, j.s));
-        HIP_TRY(c, launch_fill_u32(cfirst, 0xffffffffu, nslots, j.s));
-        HIP_TRY(c, launch_fill_u32(clast, 0, nslots, j.s));
+        FillSet fs{};
+        fs.count = 3;
+        fs.p[0] = counters, fs.v[0] = 0, fs.n[0] = 8, fs.w[0] = 4;
+        fs.p[1] = cfirst, fs.v[1] = 0xffffffffu, fs.n[1] = nslots, fs.w[1] = 4;
+        fs.p[2] = clast, fs.v[2] = 0, fs.n[2] = nslots, fs.w[2] = 4;
+        HIP_TRY(c, launch_fill_set(fs, j.s));
         HeadArgs ha{};
         ha.keys = j.k[0];
         ha.tiles = htiles;

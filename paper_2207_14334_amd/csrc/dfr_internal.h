@@ -85,6 +85,7 @@ struct SegScanArgs {
     int32_t pass;
     uint32_t tile;         // records per tile
     uint32_t* off;         // [tiles][RADIX], indexed by the deal's tile list
+    uint64_t* ticket;      // if set, the deal's tile ticket, cleared by the scan
 };
 
 // Per-tile bucket bases from per-tile digit counts (one segment): off[t][v] is the
@@ -98,6 +99,7 @@ struct TileScanArgs {
     uint32_t nblocks;
     uint32_t* partial;  // [nblocks][RADIX]
     uint32_t* off;      // [ntiles][RADIX]
+    uint64_t* ticket;   // if set, the deal's tile ticket, cleared by the scan
 };
 
 struct DealArgs {
@@ -295,9 +297,20 @@ bool deal_tile_supported(int kb, int vb, uint32_t tile);  // the default or half
 uint32_t local_sort_capacity(int kb, int vb);    // the general kernel's chunk capacity
 uint32_t local_bucket_capacity(int kb, int vb);  // the bucketed kernels' chunk capacity
 
+// Up to four fills in one launch: n[i] words of width w[i] (4 or 8 bytes) at p[i] set
+// to v[i].
+struct FillSet {
+    void* p[4];
+    uint64_t v[4];
+    uint64_t n[4];
+    int32_t w[4];
+    int32_t count;
+};
+
 // Launchers (kernels.hip).  Each returns the launch's hipError_t.
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_set(const FillSet& f, hipStream_t s);
 hipError_t launch_count(int kb, const CountArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_deal(int kb, int vb, const DealArgs& a, hipStream_t s);
 hipError_t launch_deal_est(int kb, int vb, const EstArgs& a, hipStream_t s);

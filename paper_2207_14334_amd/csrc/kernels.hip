@@ -174,6 +174,18 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
          i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+// Several fills in one launch (blockIdx.y picks the range): fewer launches on the short
+// sorts, where launches rather than bytes take the time.
+__global__ void k_fill_set(FillSet f) {
+    const int r = blockIdx.y;
+    if (r >= f.count) return;
+    const uint64_t n = f.n[r];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (f.w[r] == 8) ((uint64_t*)f.p[r])[i] = f.v[r];
+        else ((uint32_t*)f.p[r])[i] = (uint32_t)f.v[r];
+    }
+}
 
 // ---------------------------------------------------------------------------------
 // Count (Sec. 2): per-segment digit histograms of up to MAX_PASSES digits, in one read.
@@ -2019,6 +2031,14 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
 }
+hipError_t launch_fill_set(const FillSet& f, hipStream_t s) {
+    uint64_t most = 0;
+    for (int i = 0; i < f.count; ++i) most = std::max<uint64_t>(most, f.n[i]);
+    if (f.count <= 0 || most == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((most + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_set, dim3(blocks, (uint32_t)f.count), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
@@ -2095,6 +2115,7 @@ __global__ __launch_bounds__(4 * RADIX) void k_tile_scan_b(TileScanArgs a) {
     __shared__ uint32_t s_q[4][RADIX];
     __shared__ uint32_t s_part[RADIX / 64];
     const uint32_t v = threadIdx.x % RADIX, q = threadIdx.x / RADIX;
+    if (a.ticket && threadIdx.x == 0) *a.ticket = 0;
     const uint32_t per = (a.nblocks + 3) / 4;
     const uint32_t b0 = q * per, b1 = b0 + per < a.nblocks ? b0 + per : a.nblocks;
     uint32_t run = 0;
@@ -2145,6 +2166,7 @@ __global__ __launch_bounds__(RADIX) void k_tile_scan_c(TileScanArgs a) {
 __global__ __launch_bounds__(RADIX) void k_seg_scan(SegScanArgs a) {
     __shared__ uint32_t s_part[RADIX / 64];
     const uint32_t s = blockIdx.x, v = threadIdx.x;
+    if (a.ticket && s == 0 && v == 0) *a.ticket = 0;
     const Seg* sg = a.segs + s;
     const uint64_t len = sg->len;
     if (len == 0 || a.pass < sg->first_pass) return;  // no tiles in this pass
