@@ -67,6 +67,7 @@ constexpr int LOCAL_MIN_WAVES32 = 8;   // the same for its 32-bit-word forms
 constexpr int COPY_THREADS = 256;
 constexpr int HEAD_THREADS = 512;
 constexpr int GENERAL_THREADS = 256;
+constexpr int LOCAL_RANK_WIN = 4;      // places of a bin the bucketed local sort compares unrolled
 // Largest chunk any local-sort kernel accepts (the general kernel's capacity).
 constexpr uint32_t LOCAL_CAP_ANY = LOCAL_CAP_SMALL;
 
@@ -1332,6 +1333,7 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
     constexpr uint32_t GMAX = 64;
+    constexpr int RANK_WIN = LOCAL_RANK_WIN;
     // With SEPPOS the words hold the sort bits only and the position sits beside them in
     // s_pos (ties broken by it); otherwise the words carry it in their low IB bits.
     constexpr int PB = SEPPOS ? 0 : IB;
@@ -1411,18 +1413,24 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     for (int ww = 0; ww < W; ++ww) gmax = s_max[ww] > gmax ? s_max[ww] : gmax;
     if (gmax > GMAX) return false;  // a big group of near-equal keys
     __syncthreads();
+    // Each bin's start, read as a 16-bit half of the packed counters.
+    const uint16_t* s_start = (const uint16_t*)s_bin;
 #pragma unroll
     for (int k = 0; k < MAXI; ++k) {
         const uint32_t idx = wbase + k * 64 + lane;
         if ((uint32_t)k < iu && idx < len) {
             const uint32_t d = (uint32_t)(xw[k] >> dshift) & (nbins - 1);
-            const uint32_t st = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
-            const uint32_t q = st + slot[k];
+            const uint32_t q = s_start[d] + slot[k];
             if (q < CAP) {
                 s_w[q] = xw[k];
                 if (SEPPOS) s_pos[q] = (uint16_t)idx;
             }
         }
+    }
+    // Past the last word, RANK_WIN words above every word (ties lose on the position).
+    if (tid < RANK_WIN) {
+        s_w[len + tid] = ~WT(0);
+        if (SEPPOS) s_pos[len + tid] = 0xffffu;
     }
     __syncthreads();
     // Rank inside the bin (its start plus the smaller words in it) and rebuild the
@@ -1445,18 +1453,27 @@ __device__ __forceinline__ bool bucket_sort_chunk(
         if ((uint32_t)k < iu && p < len) {
             const WT me = s_w[p];
             const uint32_t d = (uint32_t)(me >> dshift) & (nbins - 1);
-            const uint32_t gs = (s_bin[d >> 1] >> (16 * (d & 1))) & 0xffffu;
-            const uint32_t dn = d + 1;
-            const uint32_t ge = dn < nbins ? (s_bin[dn >> 1] >> (16 * (dn & 1))) & 0xffffu : len;
+            const uint32_t gs = s_start[d];
+            const uint32_t ge = d + 1 < nbins ? s_start[d + 1] : len;
+            // The first RANK_WIN places from the bin's start are compared without a
+            // bound: places past the bin hold larger words (later bins, or the
+            // sentinels past the chunk), which add nothing.
             uint32_t r = 0, src;
             if (SEPPOS) {
                 src = s_pos[p];
-                for (uint32_t q = gs; q < ge; ++q) {
+#pragma unroll
+                for (int i = 0; i < RANK_WIN; ++i) {
+                    const WT o = s_w[gs + i];
+                    r += (o < me) | ((o == me) & (s_pos[gs + i] < src));
+                }
+                for (uint32_t q = gs + RANK_WIN; q < ge; ++q) {
                     const WT o = s_w[q];
                     r += (o < me) | ((o == me) & (s_pos[q] < src));
                 }
             } else {
-                for (uint32_t q = gs; q < ge; ++q) r += s_w[q] < me;
+#pragma unroll
+                for (int i = 0; i < RANK_WIN; ++i) r += s_w[gs + i] < me;
+                for (uint32_t q = gs + RANK_WIN; q < ge; ++q) r += s_w[q] < me;
                 src = (uint32_t)me & ((1u << IB) - 1u);
             }
             const uint32_t at = gs + r < len ? gs + r : len - 1;
@@ -1532,8 +1549,8 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
     // Words, then (once ranked) values, share one buffer sized for the wider of the two.
     constexpr int WB = FORM < 2 ? 4 : 8;  // word bytes
     using SW = typename uint_of<(WB > VB ? WB : (VB > 4 ? 8 : 4))>::type;
-    __shared__ SW s_w[CAP];
-    __shared__ uint16_t s_pos[FORM == 1 ? CAP : 1];
+    __shared__ SW s_w[CAP + LOCAL_RANK_WIN];
+    __shared__ uint16_t s_pos[FORM == 1 ? CAP + LOCAL_RANK_WIN : 1];
     __shared__ uint32_t s_bin[NWORDS];
     __shared__ uint32_t s_part[W];
     __shared__ uint32_t s_max[W];
