@@ -1313,18 +1313,25 @@ __device__ __forceinline__ void wave0_offsets(uint32_t* cnt, int w, int lane) {
 }
 
 // The sort phase of the bucketed local sort, on words of type WT: 32-bit when the
-// sort bits and the position fit in 32 bits, else 64-bit.  x holds the chunk's keys
-// as loaded; s_rel the buckets' starts relative to the chunk (nbk > 1).  Returns
-// false, uniformly across the block, when the largest bin exceeds GMAX (the chunk then
-// goes to the stable kernel); otherwise the chunk is sorted into kout/vout.
-template <int MAXI>
-struct Words {
-    uint64_t v[MAXI];
+// sort bits and the position fit in 32 bits, else 64-bit.  Item k of thread tid is
+// record k * THREADS + tid of the chunk, so every thread's first nfull items hold
+// records and item nfull holds one for the threads below rem (item_valid).  x holds
+// the chunk's keys as loaded; s_rel the buckets' starts relative to the chunk
+// (nbk > 1).  Returns false, uniformly across the block, when the largest bin exceeds
+// GMAX (the chunk then goes to the stable kernel); otherwise the chunk is sorted into
+// kout/vout.
+template <typename K, int MAXI>
+struct Keys {
+    K v[MAXI];
 };
 
-template <typename WT, bool SEPPOS, int KB, int VB, int THREADS, int CAP, int IB, int DB, int MAXI>
+__device__ __forceinline__ bool item_valid(int k, uint32_t nfull, uint32_t rem, int tid) {
+    return (uint32_t)k < nfull || ((uint32_t)k == nfull && (uint32_t)tid < rem);
+}
+
+template <typename WT, bool SEPPOS, bool WIDE, int KB, int VB, int THREADS, int CAP, int IB, int DB, int MAXI>
 __device__ __forceinline__ bool bucket_sort_chunk(
-    Words<MAXI> x, uint32_t len, uint32_t iu, uint32_t wbase, int lane, int w,
+    const Keys<typename uint_of<KB>::type, MAXI>& x, uint32_t len, uint32_t nfull, uint32_t rem, int lane, int w,
     int tid, uint32_t nbk, bool direct, int lo, int h, int B, typename uint_of<KB>::type key0,
     const typename uint_of<KB>::type* kin, const typename uint_of<VB>::type* vin,
     typename uint_of<KB>::type* kout, typename uint_of<VB>::type* vout, const uint32_t* s_rel,
@@ -1337,15 +1344,21 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     // With SEPPOS the words hold the sort bits only and the position sits beside them in
     // s_pos (ties broken by it); otherwise the words carry it in their low IB bits.
     constexpr int PB = SEPPOS ? 0 : IB;
-    const uint64_t mask_h = (1ull << h) - 1ull;  // h < 64 here
+    constexpr int KBITS = 8 * KB, WBITS = 8 * (int)sizeof(WT);
+    const K mask_h = h >= KBITS ? ~K(0) : (K)((K(1) << h) - K(1));
+    // The bucket index sits above the h sort bits.  h reaches WBITS only where that
+    // index is 0 (the words then hold the sort bits alone), so shifts by h are taken
+    // modulo WBITS and the bucket part is masked off in that case.
+    const int hsh = h & (WBITS - 1);
+    const WT bmask = h >= WBITS ? WT(0) : ~WT(0);
     WT xw[MAXI];
 
 #pragma unroll
     for (int k = 0; k < MAXI; ++k) {
-        const uint32_t idx = wbase + k * 64 + lane;
-        uint64_t bi = 0;
+        const uint32_t idx = (uint32_t)k * THREADS + tid;
+        uint32_t bi = 0;
         if (direct) {
-            bi = (uint64_t)(((K)x.v[k] >> lo) - (key0 >> lo));
+            bi = (uint32_t)((x.v[k] >> lo) - (key0 >> lo));
         } else if (nbk > 1) {
             uint32_t lo_i = 0, hi_i = nbk;  // last i with s_rel[i] <= idx
             while (hi_i - lo_i > 1) {
@@ -1355,33 +1368,43 @@ __device__ __forceinline__ bool bucket_sort_chunk(
             }
             bi = lo_i;
         }
-        xw[k] = (WT)((((x.v[k] & mask_h) | (bi << h)) << PB) | (SEPPOS ? 0u : idx));
+        xw[k] = (WT)((((WT)(x.v[k] & mask_h) | ((WT)bi << hsh)) << PB) | (SEPPOS ? 0u : idx));
     }
     const int nbits = B < DB ? B : DB;
     const uint32_t nbins = 1u << nbits;
     const int dshift = PB + B - nbits;
-    const uint32_t nwords = nbins > 1 ? nbins / 2 : 1;
+    // Counters: one 32-bit word per bin (WIDE), or two 16-bit halves per word.
     if (nbk > 1 && !direct) __syncthreads();  // s_rel no longer needed
     // Slots inside the bins.
     uint32_t slot[MAXI];
 #pragma unroll
     for (int k = 0; k < MAXI; ++k) {
         slot[k] = 0;
-        const uint32_t idx = wbase + k * 64 + lane;
-        if ((uint32_t)k < iu && idx < len) {
+        if (item_valid(k, nfull, rem, tid)) {
             const uint32_t d = (uint32_t)(xw[k] >> dshift) & (nbins - 1);
-            const uint32_t sh = 16 * (d & 1);
-            slot[k] = (atomicAdd(&s_bin[d >> 1], 1u << sh) >> sh) & 0xffffu;
+            if (WIDE) {
+                slot[k] = atomicAdd(&s_bin[d], 1u);
+            } else {
+                const uint32_t sh = 16 * (d & 1);
+                slot[k] = (atomicAdd(&s_bin[d >> 1], 1u << sh) >> sh) & 0xffffu;
+            }
         }
     }
     __syncthreads();
-    // Bin counts -> bin starts (exclusive scan, in place), and the largest bin.
+    // Bin counts -> bin starts (exclusive scan, in place), and the largest bin.  Every
+    // counter word is scanned, each thread taking PERW adjacent ones (vector LDS
+    // accesses); words past nbins hold 0 and so take the start len.
     {
-        const uint32_t per = (nwords + THREADS - 1) / THREADS;
-        const uint32_t w0 = tid * per, w1 = w0 + per < nwords ? w0 + per : nwords;
+        constexpr int NW0 = WIDE ? (1 << DB) : (1 << DB) / 2;
+        constexpr int PERW = NW0 / THREADS;
+        static_assert(NW0 % THREADS == 0, "whole counter words per thread");
+        uint32_t v[PERW];
+#pragma unroll
+        for (int j = 0; j < PERW; ++j) v[j] = s_bin[tid * PERW + j];
         uint32_t sum = 0, mx = 0;
-        for (uint32_t i = w0; i < w1; ++i) {
-            const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
+#pragma unroll
+        for (int j = 0; j < PERW; ++j) {
+            const uint32_t c0 = WIDE ? v[j] : v[j] & 0xffffu, c1 = WIDE ? 0u : v[j] >> 16;
             sum += c0 + c1;
             mx = c0 > mx ? c0 : mx;
             mx = c1 > mx ? c1 : mx;
@@ -1402,10 +1425,16 @@ __device__ __forceinline__ bool bucket_sort_chunk(
         __syncthreads();
         uint32_t run = incl - sum;
         for (int ww = 0; ww < w; ++ww) run += s_part[ww];
-        for (uint32_t i = w0; i < w1; ++i) {
-            const uint32_t v = s_bin[i], c0 = v & 0xffffu, c1 = v >> 16;
-            s_bin[i] = run | ((run + c0) << 16);
-            run += c0 + c1;
+#pragma unroll
+        for (int j = 0; j < PERW; ++j) {
+            if (WIDE) {
+                s_bin[tid * PERW + j] = run;
+                run += v[j];
+            } else {
+                const uint32_t c0 = v[j] & 0xffffu, c1 = v[j] >> 16;
+                s_bin[tid * PERW + j] = run | ((run + c0) << 16);
+                run += c0 + c1;
+            }
         }
     }
     uint32_t gmax = 0;
@@ -1413,14 +1442,20 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     for (int ww = 0; ww < W; ++ww) gmax = s_max[ww] > gmax ? s_max[ww] : gmax;
     if (gmax > GMAX) return false;  // a big group of near-equal keys
     __syncthreads();
-    // Each bin's start, read as a 16-bit half of the packed counters.
-    const uint16_t* s_start = (const uint16_t*)s_bin;
+    // Each bin's start (a word, or a 16-bit half of the packed counters); entry nbins
+    // holds len, so every bin's end is its successor's start.
+    const uint16_t* s_start16 = (const uint16_t*)s_bin;
+    auto bin_start = [&](uint32_t d) -> uint32_t { return WIDE ? s_bin[d] : (uint32_t)s_start16[d]; };
+    if (tid == 0) {
+        if (WIDE) s_bin[nbins] = len;
+        else ((uint16_t*)s_bin)[nbins] = (uint16_t)len;
+    }
 #pragma unroll
     for (int k = 0; k < MAXI; ++k) {
-        const uint32_t idx = wbase + k * 64 + lane;
-        if ((uint32_t)k < iu && idx < len) {
+        const uint32_t idx = (uint32_t)k * THREADS + tid;
+        if (item_valid(k, nfull, rem, tid)) {
             const uint32_t d = (uint32_t)(xw[k] >> dshift) & (nbins - 1);
-            const uint32_t q = s_start[d] + slot[k];
+            const uint32_t q = bin_start(d) + slot[k];
             if (q < CAP) {
                 s_w[q] = xw[k];
                 if (SEPPOS) s_pos[q] = (uint16_t)idx;
@@ -1441,20 +1476,20 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     uint32_t pos[MAXI];  // destination in the low 16 bits, source above
     K ko[MAXI];
     // Bits in [h, lo) are the chunk's constant ones; bits >= lo are the bucket's.
-    const uint64_t lowmask = lo >= 8 * KB ? ~0ull : (1ull << lo) - 1ull;
-    const uint64_t mid0 = (uint64_t)key0 & lowmask & ~mask_h;
-    const uint64_t hi0 = (uint64_t)key0 & ~mask_h;
-    const uint64_t d0 = lo >= 8 * KB ? 0ull : (uint64_t)(key0 >> lo);
+    const K lowmask = lo >= KBITS ? ~K(0) : (K)((K(1) << lo) - K(1));
+    const K mid0 = key0 & lowmask & ~mask_h;
+    const K hi0 = key0 & ~mask_h;
+    const K d0 = lo >= KBITS ? K(0) : (K)(key0 >> lo);
 #pragma unroll
     for (int k = 0; k < MAXI; ++k) {
-        const uint32_t p = wbase + k * 64 + lane;
+        const uint32_t p = (uint32_t)k * THREADS + tid;
         pos[k] = 0xffffffffu;
         ko[k] = 0;
-        if ((uint32_t)k < iu && p < len) {
+        if (item_valid(k, nfull, rem, tid)) {
             const WT me = s_w[p];
             const uint32_t d = (uint32_t)(me >> dshift) & (nbins - 1);
-            const uint32_t gs = s_start[d];
-            const uint32_t ge = d + 1 < nbins ? s_start[d + 1] : len;
+            const uint32_t gs = bin_start(d);
+            const uint32_t ge = bin_start(d + 1);
             // The first RANK_WIN places from the bin's start are compared without a
             // bound: places past the bin hold larger words (later bins, or the
             // sentinels past the chunk), which add nothing.
@@ -1477,11 +1512,13 @@ __device__ __forceinline__ bool bucket_sort_chunk(
                 src = (uint32_t)me & ((1u << IB) - 1u);
             }
             const uint32_t at = gs + r < len ? gs + r : len - 1;
-            uint64_t hi = hi0;
-            if (direct) hi = mid0 | ((((uint64_t)me >> PB >> h) + d0) << lo);
-            else if (nbk > 1) hi = (uint64_t)kin[at] & ~mask_h;
+            const WT sw = me >> PB;  // the sort bits, the bucket index above them
+            K hi = hi0;
+            // Direct bucket indices: lo < KBITS, so the shift by lo is in range.
+            if (direct) hi = mid0 | (K)(((K)((sw >> hsh) & bmask) + d0) << lo);
+            else if (nbk > 1) hi = kin[at] & ~mask_h;
             pos[k] = at | (src << 16);
-            ko[k] = (K)((((uint64_t)me >> PB) & mask_h) | hi);
+            ko[k] = ((K)sw & mask_h) | hi;
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -1489,8 +1526,8 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     if (VB) {
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
-            const uint32_t idx = wbase + k * 64 + lane;
-            vx[k] = ((uint32_t)k < iu && idx < len) ? vin[idx] : V(0);
+            const uint32_t idx = (uint32_t)k * THREADS + tid;
+            vx[k] = item_valid(k, nfull, rem, tid) ? vin[idx] : V(0);
         }
     }
     __syncthreads();  // every word ranked: the word buffer takes the values
@@ -1498,8 +1535,8 @@ __device__ __forceinline__ bool bucket_sort_chunk(
     if (VB) {
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
-            const uint32_t idx = wbase + k * 64 + lane;
-            if ((uint32_t)k < iu && idx < len) s_v[idx] = vx[k];
+            const uint32_t idx = (uint32_t)k * THREADS + tid;
+            if (item_valid(k, nfull, rem, tid)) s_v[idx] = vx[k];
         }
         __syncthreads();
     }
@@ -1542,7 +1579,10 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
     constexpr int KBITS = 8 * KB;
     constexpr int IB = CAP <= 4096 ? 12 : CAP <= 8192 ? 13 : 16;  // bits of a position
     constexpr int DB = IB - 1;  // most bin bits
-    constexpr int NWORDS = (1 << DB) / 2;  // two 16-bit bin counters per LDS word
+    // Bin counters: 32-bit words where the LDS allows (32-bit words and records of at
+    // most 8 bytes), else two 16-bit counters per word; one entry more for the end.
+    constexpr bool WIDE = FORM == 0 && KB + VB <= 8;
+    constexpr int NWORDS = (WIDE ? (1 << DB) : (1 << DB) / 2) + 1;
     static_assert(CAP % THREADS == 0 && CAP <= (1 << IB), "chunk layout");
     static_assert(CAP < (1 << 16), "a destination and a source share one 32-bit word");
     static_assert(VB <= 8, "values fit the word buffer");
@@ -1551,7 +1591,7 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
     using SW = typename uint_of<(WB > VB ? WB : (VB > 4 ? 8 : 4))>::type;
     __shared__ SW s_w[CAP + LOCAL_RANK_WIN];
     __shared__ uint16_t s_pos[FORM == 1 ? CAP + LOCAL_RANK_WIN : 1];
-    __shared__ uint32_t s_bin[NWORDS];
+    __shared__ __align__(16) uint32_t s_bin[NWORDS];
     __shared__ uint32_t s_part[W];
     __shared__ uint32_t s_max[W];
     __shared__ K s_red[W];
@@ -1586,25 +1626,22 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
         const V* vin = (const V*)a.vin + start;
         K* kout = (K*)a.kout + start;
         V* vout = (V*)a.vout + start;
-        const uint32_t iu = (len + THREADS - 1) / THREADS;
-        const uint32_t wbase = (uint32_t)w * iu * 64;
+        const uint32_t nfull = len / THREADS, rem = len % THREADS;
 
-        Words<MAXI> xs;
-        uint64_t* x = xs.v;
+        Keys<K, MAXI> xs;
+        K* x = xs.v;
 #pragma unroll
         for (int k = 0; k < MAXI; ++k) {
-            const uint32_t idx = wbase + k * 64 + lane;
-            x[k] = ((uint32_t)k < iu && idx < len) ? (uint64_t)kin[idx] : 0ull;
+            const uint32_t idx = (uint32_t)k * THREADS + tid;
+            x[k] = item_valid(k, nfull, rem, tid) ? kin[idx] : K(0);
         }
         for (int i = tid; i < NWORDS; i += THREADS) s_bin[i] = 0;
         const K lowmask = lo >= KBITS ? ~K(0) : (K)((K(1) << lo) - K(1));
         const K key0 = kin[0];
         K vary = 0;
 #pragma unroll
-        for (int k = 0; k < MAXI; ++k) {
-            const uint32_t idx = wbase + k * 64 + lane;
-            if ((uint32_t)k < iu && idx < len) vary |= ((K)x[k] ^ key0) & lowmask;
-        }
+        for (int k = 0; k < MAXI; ++k)
+            if (item_valid(k, nfull, rem, tid)) vary |= (x[k] ^ key0) & lowmask;
         vary = wave_or(vary);
         if (lane == 0) s_red[w] = vary;
         __syncthreads();
@@ -1631,9 +1668,9 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
         if (B == 0) {  // nothing varies: the chunk is in order already
 #pragma unroll
             for (int k = 0; k < MAXI; ++k) {
-                const uint32_t idx = wbase + k * 64 + lane;
-                if ((uint32_t)k < iu && idx < len) {
-                    kout[idx] = (K)x[k];
+                const uint32_t idx = (uint32_t)k * THREADS + tid;
+                if (item_valid(k, nfull, rem, tid)) {
+                    kout[idx] = x[k];
                     if (VB) vout[idx] = vin[idx];
                 }
             }
@@ -1658,8 +1695,8 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
             __syncthreads();
         }
         using WT = typename uint_of<WB>::type;
-        const bool ok = bucket_sort_chunk<WT, FORM == 1, KB, VB, THREADS, CAP, IB, DB, MAXI>(
-            xs, len, iu, wbase, lane, w, tid, nbk, direct, lo, h, Bw, key0, kin, vin, kout, vout, s_rel,
+        const bool ok = bucket_sort_chunk<WT, FORM == 1, WIDE, KB, VB, THREADS, CAP, IB, DB, MAXI>(
+            xs, len, nfull, rem, lane, w, tid, nbk, direct, lo, h, Bw, key0, kin, vin, kout, vout, s_rel,
             (WT*)s_w, s_pos, s_bin, s_part, s_max);
         if (!ok) spill(item);
         else ++sorted;
