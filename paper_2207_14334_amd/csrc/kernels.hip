@@ -193,8 +193,8 @@ __global__ void k_fill_set(FillSet f) {
 // Keys arrive in 16-byte vector loads, all of a thread's share of a tile in flight at
 // once.  Each wave keeps private LDS bins.  A digit on which a wave's first keys mostly
 // agree (a skewed input) is added per group of equal lanes -- the lanes that share the
-// first active lane's digit add their number in one LDS atomic -- and otherwise one
-// atomic per key.
+// first active lane's digit, or the first other lane's, add their number in one LDS
+// atomic -- and otherwise one atomic per key.
 // ---------------------------------------------------------------------------------
 template <int KB, int THREADS, int NDIG>
 __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
@@ -301,6 +301,16 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
         }
     };
 
+    // One key, one atomic per digit (the digit loop unrolled): batches with no skewed
+    // digit and no ragged end.
+    auto add_plain = [&](K key) {
+        vor |= key;
+        vand &= key;
+#pragma unroll
+        for (int j = 0; j < NDIG; ++j)
+            if (j < ndig) atomicAdd(&hw[j * RADIX + ((uint32_t)(key >> (base + j * bits)) & dmask)], 1u);
+    };
+
     for (uint32_t t = t0; t < t1; ++t) {
         const Tile tl = a.tiles[t];
         if (tl.seg != cur) {
@@ -345,6 +355,21 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
                     }
                     if (most > 16) skew |= 1u << j;
                 }
+            }
+            if (skew == 0 && v0 + THREADS * VECS <= nvec) {
+#pragma unroll
+                for (int r = 0; r < VECS; ++r) {
+                    if (KB == 4) {
+                        add_plain((K)buf[r].x);
+                        add_plain((K)buf[r].y);
+                        add_plain((K)buf[r].z);
+                        add_plain((K)buf[r].w);
+                    } else {
+                        add_plain((K)buf[r].x | ((K)buf[r].y << 32));
+                        add_plain((K)buf[r].z | ((K)buf[r].w << 32));
+                    }
+                }
+                continue;
             }
 #pragma unroll
             for (int r = 0; r < VECS; ++r) {
