@@ -416,7 +416,6 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     // index i of digit d goes to segment position s_delta[d] + i; a segment holds fewer
     // than 2^32 records, so the position is exact in 32-bit arithmetic).
     __shared__ uint32_t s_delta[RADIX];
-    __shared__ uint32_t s_local[RADIX];
     __shared__ uint32_t s_part[RADIX / 64];
     __shared__ uint32_t s_ticket;
 
@@ -506,11 +505,11 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     const uint32_t loc_excl = scan256_excl(tile_cnt, s_part, &total);
 
     if (!LOOKBACK && tid < RADIX) {
-        s_local[tid] = loc_excl;
+        for (int ww = 0; ww < W; ++ww) s_wcnt[ww * RADIX + tid] += loc_excl;  // wave runs from the tile start
         s_delta[tid] = a.off[(size_t)t * RADIX + tid] - loc_excl;
     }
     if (LOOKBACK && tid < RADIX) {
-        s_local[tid] = loc_excl;
+        for (int ww = 0; ww < W; ++ww) s_wcnt[ww * RADIX + tid] += loc_excl;  // wave runs from the tile start
         uint64_t excl = 0;
         if (t != first_tile) {
             uint32_t j = t - 1;
@@ -533,7 +532,7 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
         const uint32_t idx = wbase + k * 64 + lane;
         if (idx < len) {
             const uint32_t d = (uint32_t)(key[k] >> shift) & dmask;
-            const uint32_t p = wc[d] + s_local[d] + rnk[k];
+            const uint32_t p = wc[d] + rnk[k];
             if (p < T) {
                 s_keys[p] = key[k];
                 if (VB) s_vals[p] = val[k];
@@ -589,7 +588,6 @@ __global__ __launch_bounds__(THREADS) void k_deal_est(EstArgs a) {
     __shared__ V s_vals[VB ? T : 1];
     __shared__ uint32_t s_wcnt[W * RADIX];
     __shared__ uint32_t s_delta[RADIX];  // rank in the bucket of staged index 0, mod 2^32
-    __shared__ uint32_t s_local[RADIX];
     __shared__ uint32_t s_next[RADIX];
     __shared__ uint32_t s_part[RADIX / 64];
     __shared__ uint32_t s_ticket, s_lost;
@@ -658,7 +656,7 @@ __global__ __launch_bounds__(THREADS) void k_deal_est(EstArgs a) {
     uint32_t total;
     const uint32_t loc_excl = scan256_excl(tile_cnt, s_part, &total);
     if (tid < RADIX) {
-        s_local[tid] = loc_excl;
+        for (int ww = 0; ww < W; ++ww) s_wcnt[ww * RADIX + tid] += loc_excl;  // wave runs from the tile start
         uint64_t excl = 0;
         if (t != 0) {
             uint32_t j = t - 1;
@@ -679,7 +677,7 @@ __global__ __launch_bounds__(THREADS) void k_deal_est(EstArgs a) {
         const uint32_t idx = wbase + k * 64 + lane;
         if (idx < len) {
             const uint32_t d = (uint32_t)(key[k] >> a.shift) & dmask;
-            const uint32_t p = wc[d] + s_local[d] + rnk[k];
+            const uint32_t p = wc[d] + rnk[k];
             if (p < T) {
                 s_keys[p] = key[k];
                 if (VB) s_vals[p] = val[k];
