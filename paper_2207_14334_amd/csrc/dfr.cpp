@@ -642,7 +642,13 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         ca.tiles_per_block = (uint32_t)((tiles.size() + blocks - 1) / blocks);
         ca.base_shift = 0;
         ca.bits = rb;
-        ca.ndig = ndig;
+        // Keys of a segment agree above its hi_bit (the digits its parent bucket was
+        // dealt on, and the bits constant above them): only the digits below the
+        // highest hi_bit are counted; the plan sees the others as constant from OR/AND.
+        int top_bit = 0;
+        for (const LSeg& g : segs) top_bit = std::max(top_bit, g.hi_bit);
+        ca.ndig = std::max(1, std::min(ndig, (top_bit + rb - 1) / rb));
+        ca.hist_digits = ndig;
         ca.hist = dhist;
         ca.seg_or = dor;
         ca.seg_and = dand;

@@ -64,11 +64,12 @@ struct CountArgs {
     uint32_t tiles_per_block;
     int32_t base_shift;  // digit j sits at base_shift + j * bits
     int32_t bits;
-    int32_t ndig;        // <= MAX_PASSES
-    uint32_t* hist;      // [seg][ndig][RADIX]
+    int32_t ndig;        // digits counted, <= MAX_PASSES
+    int32_t hist_digits; // digits per histogram row (0: ndig); rows past ndig are left as they are
+    uint32_t* hist;      // [seg][hist_digits][RADIX]
     void* seg_or;        // [seg] key type, OR of the segment's keys
     void* seg_and;       // [seg] key type, AND of the segment's keys
-    uint32_t* tile_hist; // optional [tile][ndig][RADIX]: each tile's own counts
+    uint32_t* tile_hist; // optional [tile][hist_digits][RADIX]: each tile's own counts
     const Seg* segs;     // optional: digit shift per tile from segs[seg].shift[pass]
     int32_t pass;
 };

@@ -217,6 +217,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
     if (t0 >= a.ntiles) return;
     const uint32_t t1 = a.ntiles - t0 < a.tiles_per_block ? a.ntiles : t0 + a.tiles_per_block;
     const int ndig = a.ndig < NDIG ? a.ndig : NDIG, bits = a.bits;
+    const int nrow = a.hist_digits > 0 ? a.hist_digits : ndig;  // histogram row stride
     int base = a.base_shift;  // per tile from the segment when a.segs is set
     const uint32_t dmask = (1u << bits) - 1u;
     uint32_t* hw = s_h + w * SLICE;
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
                 s_h[ww * SLICE + idx] = 0;
             }
             s_tot[idx] += sum;
-            if (a.tile_hist) a.tile_hist[(size_t)t * ndig * RADIX + idx] = sum;
+            if (a.tile_hist) a.tile_hist[(size_t)t * nrow * RADIX + idx] = sum;
         }
         __syncthreads();  // bins are clear before any wave counts the next tile
     };
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
         for (int idx = tid; idx < ndig * RADIX; idx += THREADS) {
             const uint32_t sum = s_tot[idx];
             s_tot[idx] = 0;
-            if (sum && a.hist) atomicAdd(&a.hist[(size_t)seg * ndig * RADIX + idx], sum);
+            if (sum && a.hist) atomicAdd(&a.hist[(size_t)seg * nrow * RADIX + idx], sum);
         }
         if (!a.seg_or) {  // per-tile counts only
             __syncthreads();
