@@ -2241,29 +2241,51 @@ __global__ __launch_bounds__(RADIX) void k_tile_scan_c(TileScanArgs a) {
     }
 }
 
-__global__ __launch_bounds__(RADIX) void k_seg_scan(SegScanArgs a) {
+// G groups of RADIX threads split the segment's tiles: each sums its share per digit,
+// the shares are chained after the digit's bucket start, and each group writes its
+// tiles' bases (few segments: G = 4, so the serial walks are a quarter as long).
+template <int G>
+__global__ __launch_bounds__(RADIX * G) void k_seg_scan(SegScanArgs a) {
     __shared__ uint32_t s_part[RADIX / 64];
-    const uint32_t s = blockIdx.x, v = threadIdx.x;
-    if (a.ticket && s == 0 && v == 0) *a.ticket = 0;
+    __shared__ uint32_t s_gsum[G][RADIX];
+    __shared__ uint32_t s_start[RADIX];
+    const uint32_t s = blockIdx.x, v = threadIdx.x % RADIX, g = threadIdx.x / RADIX;
+    if (a.ticket && s == 0 && threadIdx.x == 0) *a.ticket = 0;
     const Seg* sg = a.segs + s;
     const uint64_t len = sg->len;
-    if (len == 0 || a.pass < sg->first_pass) return;  // no tiles in this pass
+    if (len == 0 || a.pass < sg->first_pass) return;  // no tiles in this pass (whole block)
     const int slot = sg->hslot[a.pass];
-    uint32_t total;
-    const uint32_t start =
-        scan256_excl(a.hist[((size_t)s * a.hist_digits + slot) * RADIX + v], s_part, &total);
     const uint32_t nt = (uint32_t)((len + a.tile - 1) / a.tile);
+    const uint32_t per = (nt + G - 1) / G;
+    const uint32_t t0 = g * per < nt ? g * per : nt, t1 = t0 + per < nt ? t0 + per : nt;
     const uint32_t ct = a.cnt_from_count_tiles ? sg->count_tile : sg->first_tile;
     const int cslot = a.cnt_from_count_tiles ? slot : 0;
-    uint32_t run = start;
-    for (uint32_t i0 = 0; i0 < nt; i0 += SCAN_BATCH) {
+    auto cnt_at = [&](uint32_t i) { return a.cnt[((size_t)(ct + i) * a.cnt_ndig + cslot) * RADIX + v]; };
+    uint32_t sum = 0;
+    if (G > 1) {
+        for (uint32_t i0 = t0; i0 < t1; i0 += SCAN_BATCH) {
+            uint32_t c[SCAN_BATCH];
+#pragma unroll
+            for (int i = 0; i < SCAN_BATCH; ++i) c[i] = i0 + i < t1 ? cnt_at(i0 + i) : 0u;
+#pragma unroll
+            for (int i = 0; i < SCAN_BATCH; ++i) sum += c[i];
+        }
+        s_gsum[g][v] = sum;
+    }
+    uint32_t total;
+    const uint32_t start =
+        scan256_excl(g == 0 ? a.hist[((size_t)s * a.hist_digits + slot) * RADIX + v] : 0u, s_part, &total);
+    if (g == 0) s_start[v] = start;
+    __syncthreads();
+    uint32_t run = s_start[v];
+    for (uint32_t gg = 0; gg < g; ++gg) run += s_gsum[gg][v];
+    for (uint32_t i0 = t0; i0 < t1; i0 += SCAN_BATCH) {
         uint32_t c[SCAN_BATCH];
 #pragma unroll
-        for (int i = 0; i < SCAN_BATCH; ++i)
-            c[i] = i0 + i < nt ? a.cnt[((size_t)(ct + i0 + i) * a.cnt_ndig + cslot) * RADIX + v] : 0u;
+        for (int i = 0; i < SCAN_BATCH; ++i) c[i] = i0 + i < t1 ? cnt_at(i0 + i) : 0u;
 #pragma unroll
         for (int i = 0; i < SCAN_BATCH; ++i) {
-            if (i0 + i < nt) a.off[(size_t)(sg->first_tile + i0 + i) * RADIX + v] = run;
+            if (i0 + i < t1) a.off[(size_t)(sg->first_tile + i0 + i) * RADIX + v] = run;
             run += c[i];
         }
     }
@@ -2333,7 +2355,8 @@ hipError_t launch_collisions(const uint32_t* hist, uint32_t nsegs, int ndig, int
 
 hipError_t launch_seg_scan(const SegScanArgs& a, hipStream_t s) {
     if (a.nsegs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_scan, dim3(a.nsegs), dim3(RADIX), 0, s, a);
+    if (a.nsegs <= 64) hipLaunchKernelGGL(k_seg_scan<4>, dim3(a.nsegs), dim3(4 * RADIX), 0, s, a);
+    else hipLaunchKernelGGL(k_seg_scan<1>, dim3(a.nsegs), dim3(RADIX), 0, s, a);
     return hipGetLastError();
 }
 
