@@ -293,10 +293,15 @@ dfr_status dfr_get_serve_stats(dfr_ctx* ctx, dfr_serve_stats* out);
  *   "serve_gather_records" largest request gathered into a batch with others (larger
  *                     ones are sorted alone, in place; default 2^20, 0 = no limit); all
  *                     three only before the first dfr_submit (DFR_E_UNSUPPORTED after).
+ *   "serve_fail_batches" test hook: the next this-many serving batches are reported
+ *                     failed (DFR_E_HIP from dfr_poll for each of their requests) once
+ *                     their device work is queued; the worker still waits for that work
+ *                     before the requests are done.  0 (the default) injects nothing.
  *   "window_records"  width of the windows that pack runs of small buckets into
  *                     local-sort chunks (Sec. 3: runs of small buckets), 16 ..
  *                     capacity / 2.  0 = tuned or default.
- * The last three, with "divert_records", override a tuned setting (dfr_autotune);
+ * "radix_bits", "tile_records", "window_records" and "divert_records" override a
+ * tuned setting (dfr_autotune);
  * a combination that no kernel supports falls back to the defaults.  None of them
  * changes the result.  Unknown names return DFR_E_UNSUPPORTED. */
 dfr_status dfr_set_option(dfr_ctx* ctx, const char* name, int64_t value);

@@ -23,6 +23,7 @@
 #include "dfr.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cmath>
@@ -132,6 +133,9 @@ struct dfr_ctx {
     int serve_workers = 3;
     uint64_t serve_batch_records = 1ull << 25;
     uint64_t serve_gather_records = 1ull << 20;  // largest request gathered into a batch
+    // Test hook: this many of the next serving batches report DFR_E_HIP once their
+    // device work is queued, to exercise the failure path without a device fault.
+    std::atomic<int> serve_fail_batches{0};
 };
 
 namespace {
@@ -2036,8 +2040,10 @@ dfr_status copy_batch(Job& j, const std::vector<Server::Req>& b, void* sk, void*
 }
 
 // Sort one batch on the worker's stream and wait for it; ms[0..2] receive the device
-// time of the gather, the sort and the scatter.
-dfr_status run_batch(Server::Worker& wk, const std::vector<Server::Req>& b, double* ms) {
+// time of the gather, the sort and the scatter.  Once anything may have been queued the
+// function always reaches the stream synchronisation, whatever fails; inject_fail marks
+// the batch failed at that point (the serving test hook).
+dfr_status run_batch(Server::Worker& wk, const std::vector<Server::Req>& b, double* ms, bool inject_fail) {
     dfr_ctx* w = wk.w;
     ms[0] = ms[1] = ms[2] = 0;
     const int kb = b[0].r.key_bytes, vb = b[0].r.val_bytes;
@@ -2053,26 +2059,36 @@ dfr_status run_batch(Server::Worker& wk, const std::vector<Server::Req>& b, doub
     dfr_status st = get_temp(w, n, kb, vb, &temp, wk.s);
     if (st) return st;
     const bool gather = b.size() > 1;
-    if (!gather) {
-        HIP_TRY(w, hipEventRecord(wk.ev[1], wk.s));
-        st = run_sort(w, kb, vb, b[0].r.keys, vb ? b[0].r.vals : nullptr, segs, temp, wk.s);
-        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[2], wk.s));
-    } else {
+    if (gather) {
         st = grow(w, &wk.sk, &wk.skcap, n * kb);
         if (!st && vb) st = grow(w, &wk.sv, &wk.svcap, n * vb);
-        if (st) return st;
+        if (st) return st;  // nothing of this batch is queued yet
+    }
+    auto mark = [&](int i) {
+        const hipError_t e = hipEventRecord(wk.ev[i], wk.s);
+        if (e != hipSuccess && !st) st = fail_hip(w, e, "hipEventRecord");
+    };
+    if (!gather) {
+        mark(1);
+        if (!st) st = run_sort(w, kb, vb, b[0].r.keys, vb ? b[0].r.vals : nullptr, segs, temp, wk.s);
+        if (!st) mark(2);
+    } else {
         Job j;
         j.c = w;
         j.kb = kb;
         j.vb = vb;
         j.s = wk.s;
-        HIP_TRY(w, hipEventRecord(wk.ev[0], wk.s));
-        st = copy_batch(j, b, wk.sk, wk.sv, true);
-        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[1], wk.s));
+        mark(0);
+        if (!st) st = copy_batch(j, b, wk.sk, wk.sv, true);
+        if (!st) mark(1);
         if (!st) st = run_sort(w, kb, vb, wk.sk, vb ? wk.sv : nullptr, segs, temp, wk.s);
-        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[2], wk.s));
+        if (!st) mark(2);
         if (!st) st = copy_batch(j, b, wk.sk, wk.sv, false);
-        if (!st) HIP_TRY(w, hipEventRecord(wk.ev[3], wk.s));
+        if (!st) mark(3);
+    }
+    if (!st && inject_fail) {
+        st = DFR_E_HIP;
+        w->err = "failure injected by the serve_fail_batches option";
     }
     // Wait for the batch's device work whatever its status: the requests' buffers are
     // handed back to their callers once their tickets are done.
@@ -2155,7 +2171,10 @@ void worker_loop(Server* sv, int wi) {
         double ms[3];
         const uint64_t allocs0 = wk.w->n_allocs;
         const double ms_alloc0 = wk.w->ms_alloc;
-        const dfr_status st = run_batch(wk, batch, ms);
+        bool inject = false;
+        for (int f = sv->owner->serve_fail_batches.load(); f > 0 && !inject;)
+            inject = sv->owner->serve_fail_batches.compare_exchange_weak(f, f - 1);
+        const dfr_status st = run_batch(wk, batch, ms, inject);
         const auto t_end = std::chrono::steady_clock::now();
 
         lk.lock();
@@ -2771,6 +2790,11 @@ dfr_status dfr_set_option(dfr_ctx* c, const char* name, int64_t value) {
     if (!strcmp(name, "plan_lengths_records")) {
         if (value < 0) return DFR_E_INVALID_ARG;
         c->plan_lengths_max = (uint64_t)value;
+        return DFR_OK;
+    }
+    if (!strcmp(name, "serve_fail_batches")) {
+        if (value < 0 || value > 1000000) return DFR_E_INVALID_ARG;
+        c->serve_fail_batches.store((int)value);
         return DFR_OK;
     }
     if (!strcmp(name, "serve_workers") || !strcmp(name, "serve_batch_records") ||

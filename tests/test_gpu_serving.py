@@ -197,3 +197,46 @@ def test_mix_at_full_request_sizes(torch, o):
             assert o.check_index_payload(k, ok, ov) is None, k.size
             p = int(rng.integers(0, k.size))
             assert o.rank_of(k, int(ov[p])) == p, (k.size, p)
+
+
+@pytest.mark.gpu
+def test_failed_batch_waits_for_its_work(torch, o):
+    """A batch reported failed (forced from the host by the serve_fail_batches test hook,
+    after the batch's device work is queued) has finished that work before its requests
+    are done: the lone request, sorted in place, is already sorted and stays unchanged
+    once dfr_poll reports the failure, and the next request is served normally."""
+    import paper_2207_14334_amd as dfr
+    n = (1 << 22) + 3
+    kh = workloads.make_keys("uniform", n, 32, 11)
+    want = o.stable_sort(kh)[0]
+    with dfr.Context(0) as ctx:
+        ctx.set_option("serve_workers", 1)
+        ctx.set_option("serve_fail_batches", 1)
+        k = torch.from_numpy(kh.copy()).cuda()
+        torch.cuda.synchronize()
+        t = ctx.submit(k)
+        status = None
+        for _ in range(40000):
+            try:
+                done, _lat = ctx.poll(t)
+            except dfr.DfrError as e:
+                status = e.status
+                break
+            assert not done, "the injected failure was not reported"
+            time.sleep(0.0005)
+        assert status == dfr.E_HIP
+        first = k.cpu().numpy()
+        assert np.array_equal(first, want)
+        time.sleep(0.05)
+        assert np.array_equal(k.cpu().numpy(), first)
+        k2 = torch.from_numpy(kh.copy()).cuda()
+        torch.cuda.synchronize()
+        t2 = ctx.submit(k2)
+        done = False
+        for _ in range(40000):
+            done, _lat = ctx.poll(t2)
+            if done:
+                break
+            time.sleep(0.0005)
+        assert done
+        assert np.array_equal(k2.cpu().numpy(), want)
