@@ -77,6 +77,14 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Bit b of d as 0 or ~0, and the lanes where it is set (the compare's lane mask taken on
+// that value directly, one instruction for each).
+__device__ __forceinline__ uint32_t digit_bit_mask(uint32_t d, int b, uint64_t* lanes) {
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+    *lanes = __builtin_amdgcn_uicmp(m, 0u, 33 /* not equal */);
+    return m;
+}
+
 // Lanes of the wave (within `active`) whose digit equals this lane's, from one ballot
 // per digit bit.  Lane order is input order, so lanes_below() of the result is this
 // record's stable rank among equal digits in the wave.  Per bit: the bit as 0 / ~0,
@@ -87,8 +95,8 @@ __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t active
     uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
-        const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-        const uint64_t bal = __ballot(m != 0);
+        uint64_t bal;
+        const uint32_t m = digit_bit_mask(d, b, &bal);
         lo |= (uint32_t)bal ^ m;
         hi |= (uint32_t)(bal >> 32) ^ m;
     }
@@ -100,8 +108,8 @@ __device__ __forceinline__ uint64_t same_digit_lanes_rt(uint32_t d, uint64_t act
 #pragma unroll
     for (int b = 0; b < RADIX_BITS; ++b) {
         if (b < bits) {
-            const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-            const uint64_t bal = __ballot(m != 0);
+            uint64_t bal;
+            const uint32_t m = digit_bit_mask(d, b, &bal);
             lo |= (uint32_t)bal ^ m;
             hi |= (uint32_t)(bal >> 32) ^ m;
         }
