@@ -556,18 +556,45 @@ __global__ __launch_bounds__(THREADS) void k_deal(DealArgs a) {
     V* vseg = (V*)a.vout + seg_start;
     const uint32_t seg_len = (uint32_t)(seg_end - seg_start);
     bool bad = false;
+    if (ITEMS <= 8 && len == T) {
+        // A full tile of wide records: every staged place holds a record, so each
+        // step's LDS reads go out for all items together before the stores (measured:
+        // 16-byte records 10% faster; with 16 items of 8-byte records, slower).
+        K kk[ITEMS];
+        V vv[VB ? ITEMS : 1];
+        uint32_t pp[ITEMS];
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t i = (uint32_t)k * THREADS + tid;
-        if (i < len) {
-            const K kk = s_keys[i];
-            const uint32_t d = (uint32_t)(kk >> shift) & dmask;
-            const uint32_t p = s_delta[d] + i;
-            if (p < seg_len) {
-                kseg[p] = kk;
-                if (VB) vseg[p] = s_vals[i];
+        for (int k = 0; k < ITEMS; ++k) kk[k] = s_keys[(uint32_t)k * THREADS + tid];
+        if (VB) {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) vv[k] = s_vals[(uint32_t)k * THREADS + tid];
+        }
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            pp[k] = s_delta[(uint32_t)(kk[k] >> shift) & dmask] + (uint32_t)k * THREADS + tid;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            if (pp[k] < seg_len) {
+                kseg[pp[k]] = kk[k];
+                if (VB) vseg[pp[k]] = vv[k];
             } else {
                 bad = true;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t i = (uint32_t)k * THREADS + tid;
+            if (i < len) {
+                const K kk = s_keys[i];
+                const uint32_t d = (uint32_t)(kk >> shift) & dmask;
+                const uint32_t p = s_delta[d] + i;
+                if (p < seg_len) {
+                    kseg[p] = kk;
+                    if (VB) vseg[p] = s_vals[i];
+                } else {
+                    bad = true;
+                }
             }
         }
     }
