@@ -44,6 +44,7 @@ using namespace dfr;
 namespace {
 
 constexpr size_t ALIGN = 256;
+static_assert((STAT_WORDS + LEVEL_WORDS) * 4 <= ALIGN, "status block and level counters fit one allocation");
 inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct LSeg {
@@ -892,7 +893,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* wide = aalloc<uint32_t>(c, nslots + medcap);
-    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work, wide
+    uint32_t* counters = j.err_dev + STAT_WORDS;  // buckets, medium, big, done, spill, work, wide
     uint32_t* joint = aalloc<uint32_t>(c, 1u << (2 * RADIX_BITS));  // pair counts (heads from counts)
     uint64_t* joint_rows = aalloc<uint64_t>(c, RADIX);
     uint32_t* hh_ids = aalloc<uint32_t>(c, S);    // heads from histograms: segments,
@@ -1154,14 +1155,14 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     c->stats.used_diversion = 1;
 
     // --- 6. large and finished buckets ----------------------------------------------
-    st = pin_reserve(c, 8 * 4 + 2 * bigcap * sizeof(Big) + 256, j.s);
+    st = pin_reserve(c, (STAT_WORDS + LEVEL_WORDS) * 4 + 2 * bigcap * sizeof(Big) + 256, j.s);
     if (st) return st;
-    uint32_t* hc = palloc<uint32_t>(c, 8);
-    uint32_t* he = palloc<uint32_t>(c, STAT_WORDS);
-    HIP_TRY(c, hipMemcpyAsync(hc, counters, 8 * 4, hipMemcpyDeviceToHost, j.s));
-    // The status block comes back with the counters: no kernel after this point can
-    // change it unless another level runs (which clears err_known).
-    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, STAT_WORDS * 4, hipMemcpyDeviceToHost, j.s));
+    // The status block comes back with the counters, which follow it, in one copy: no
+    // kernel after this point can change it unless another level runs (which clears
+    // err_known).
+    uint32_t* he = palloc<uint32_t>(c, STAT_WORDS + LEVEL_WORDS);
+    uint32_t* hc = he + STAT_WORDS;
+    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, (STAT_WORDS + LEVEL_WORDS) * 4, hipMemcpyDeviceToHost, j.s));
     // A level planned from its lengths brings its digit statistics back now, for the
     // estimated-bucket overflow of its top varying digit.
     char* h_plan = nullptr;
@@ -1283,7 +1284,7 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
     uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
     uint32_t* wide = aalloc<uint32_t>(c, nslots + medcap);
-    uint32_t* counters = aalloc<uint32_t>(c, 8);  // buckets, medium, big, done, spill, work, wide
+    uint32_t* counters = j.err_dev + STAT_WORDS;  // buckets, medium, big, done, spill, work, wide
 
     // --- the estimated deal of the lower digit into the temp buffer and overflow -----
     {
@@ -1481,12 +1482,11 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
     }
     c->stats.used_diversion = 1;
     // --- large buckets: the next level's segments --------------------------------------
-    st = pin_reserve(c, 8 * 4 + STAT_WORDS * 4 + bigcap * sizeof(Big) + 256, j.s);
+    st = pin_reserve(c, (STAT_WORDS + LEVEL_WORDS) * 4 + bigcap * sizeof(Big) + 256, j.s);
     if (st) return st;
-    uint32_t* hc = palloc<uint32_t>(c, 8);
-    uint32_t* he = palloc<uint32_t>(c, STAT_WORDS);
-    HIP_TRY(c, hipMemcpyAsync(hc, counters, 8 * 4, hipMemcpyDeviceToHost, j.s));
-    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, STAT_WORDS * 4, hipMemcpyDeviceToHost, j.s));
+    uint32_t* he = palloc<uint32_t>(c, STAT_WORDS + LEVEL_WORDS);
+    uint32_t* hc = he + STAT_WORDS;
+    HIP_TRY(c, hipMemcpyAsync(he, j.err_dev, (STAT_WORDS + LEVEL_WORDS) * 4, hipMemcpyDeviceToHost, j.s));
     HIP_TRY(c, hipStreamSynchronize(j.s));
     memcpy(j.stat_host, he, sizeof j.stat_host);
     j.err_word_host = he[STAT_ERR];

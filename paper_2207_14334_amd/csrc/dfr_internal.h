@@ -268,10 +268,13 @@ struct LocalArgs {
 };
 
 // Words of the per-call device status block: the error word, then kernel counters.
+// The level's list counters follow it (LEVEL_WORDS words at STAT_WORDS), so one copy
+// brings both back at a level's end.
 constexpr int STAT_ERR = 0;
 constexpr int STAT_FORM0 = 1;  // + form: chunks of the bucketed local sort, forms 0..2
 constexpr int STAT_GENERAL = 4;  // chunks of the general local sort
 constexpr int STAT_WORDS = 8;
+constexpr int LEVEL_WORDS = 8;  // buckets, medium, big, done, spill, work, wide
 
 // A run of at most 2^32 - 1 records copied between two places.
 struct CopyChunk {

@@ -9,12 +9,17 @@
 //   k_count        count: digit histograms of every digit in one read, plus the OR and
 //                  AND of each segment's keys (digits that never vary are skipped); also
 //                  each tile's own counts, for the deals' bucket bases.
-//   k_tile_scan_*  per-tile bucket bases of one segment (reduce, then scan);
-//   k_seg_scan     the same for many short segments, one block per segment.
+//   k_tile_scan_*  per-tile bucket bases of one long segment (reduce, then scan);
+//   k_seg_scan     the same for short segments, one block per segment.
 //   k_deal         deal: one stable scatter pass.  Each tile ranks its records by digit
 //                  with wave ballots and stages them in LDS in digit order, so each
 //                  bucket's run is written contiguously; its bases come from the scans,
 //                  or from decoupled look-back over the tiles before it.
+//   k_deal_est     Fast Radix's deal into estimated buckets with overflow slots, without
+//                  a count (Sec. 3); it counts the next digit on the way.
+//   k_fill_*, k_stream_copy
+//                  fills of scratch (several ranges per launch), and the streaming copy
+//                  that is the passes' bandwidth reference.
 //   k_heads*       bucket boundaries after the deals, from the keys: positions where
 //                  the leading bits change, listed in order.
 //   k_joint_*      the same without the keys, for one segment dealt on two digits:
