@@ -1563,16 +1563,24 @@ __device__ __forceinline__ bool bucket_sort_chunk(
             // sentinels past the chunk), which add nothing.
             uint32_t r = 0, src;
             if (SEPPOS) {
+                // Smaller words first; another word equal to this one (equal sort bits,
+                // rare) sends the lane through the bin once more to break the tie by
+                // input position.
                 src = s_pos[p];
+                bool tie = false;
 #pragma unroll
                 for (int i = 0; i < RANK_WIN; ++i) {
                     const WT o = s_w[gs + i];
-                    r += (o < me) | ((o == me) & (s_pos[gs + i] < src));
+                    r += o < me;
+                    tie |= (o == me) & (gs + i != p);
                 }
                 for (uint32_t q = gs + RANK_WIN; q < ge; ++q) {
                     const WT o = s_w[q];
-                    r += (o < me) | ((o == me) & (s_pos[q] < src));
+                    r += o < me;
+                    tie |= (o == me) & (q != p);
                 }
+                if (tie)
+                    for (uint32_t q = gs; q < ge; ++q) r += (s_w[q] == me) & (s_pos[q] < src);
             } else {
 #pragma unroll
                 for (int i = 0; i < RANK_WIN; ++i) r += s_w[gs + i] < me;
