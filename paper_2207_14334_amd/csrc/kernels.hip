@@ -62,6 +62,7 @@ constexpr int DEAL_TILE_SMALL = 8192;  // records per deal tile when key + value
 constexpr int DEAL_TILE_LARGE = 4096;  // records per deal tile for 12- and 16-byte records
 constexpr int COUNT_THREADS = 256;
 constexpr int COUNT_VECS = 8;          // 16-byte loads in flight per counting thread
+constexpr int COUNT_MIN_WAVES = 8;     // waves per SIMD the 32-bit count of up to four digits fits
 constexpr int LOCAL_THREADS = 512;
 constexpr int LOCAL_CAP_SMALL = 8192;  // general local sort: records per chunk (<= 8-byte records)
 constexpr int LOCAL_CAP_LARGE = 4096;  // the same for 12- and 16-byte records
@@ -210,16 +211,20 @@ __global__ void k_fill_set(FillSet f) {
 // atomic -- and otherwise one atomic per key.
 // ---------------------------------------------------------------------------------
 template <int KB, int THREADS, int NDIG>
-__global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
+__global__ __launch_bounds__(THREADS, KB == 4 && NDIG <= 4 ? COUNT_MIN_WAVES : 1) void k_count(CountArgs a) {
     using K = typename uint_of<KB>::type;
     constexpr int W = THREADS / 64;
     constexpr int SLICE = NDIG * RADIX;  // bins for up to NDIG digits
     constexpr int PER_VEC = 16 / KB;  // keys per 16-byte load
-    constexpr int VECS = COUNT_VECS;  // 16-byte loads in flight per thread
-    __shared__ uint32_t s_h[W * SLICE];
+    constexpr int VECS = KB == 8 ? 4 : COUNT_VECS;  // 16-byte loads in flight per thread
+    // The waves' bins; between tiles (all zero) the first words also carry the waves'
+    // OR and AND to the segment's flush.  With four digits the two arrays fill exactly
+    // an eighth of the LDS, so eight blocks share a CU.
+    __shared__ __align__(16) uint32_t s_h[W * SLICE];
     __shared__ uint32_t s_tot[SLICE];  // the block's counts for the current segment
-    __shared__ K s_or[W];
-    __shared__ K s_and[W];
+    static_assert(2 * W * sizeof(K) <= sizeof(s_h), "room for the OR/AND words");
+    K* const s_or = (K*)s_h;
+    K* const s_and = s_or + W;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int i = tid; i < W * SLICE; i += THREADS) s_h[i] = 0;
@@ -276,6 +281,8 @@ __global__ __launch_bounds__(THREADS) void k_count(CountArgs a) {
             for (int ww = 0; ww < W; ++ww) {
                 o2 |= s_or[ww];
                 n2 &= s_and[ww];
+                s_or[ww] = 0;  // the bins are zero again before the next tile
+                s_and[ww] = 0;
             }
             atomicOr(&((K*)a.seg_or)[seg], o2);
             atomicAnd(&((K*)a.seg_and)[seg], n2);
