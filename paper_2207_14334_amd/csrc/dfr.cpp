@@ -509,16 +509,17 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
     for (uint64_t i = 0; i < nb; ++i) med[i] = (uint32_t)i;
     // buckets, medium, spills, work, wide
     uint32_t counts3[5] = {(uint32_t)nb, (uint32_t)nb, 0, (uint32_t)nb, 0};
-    const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + 4 * asize<uint32_t>(nb) +
-                        asize<uint32_t>(5) + asize<uint32_t>(1);
+    const size_t need = asize<Seg>(S) + asize<uint64_t>(nb) + 2 * asize<uint32_t>(nb) +
+                        3 * asize<ChunkDesc>(nb) + asize<uint32_t>(5) + asize<uint32_t>(1);
     dfr_status st = arena_reserve(c, need, j.s);
     if (st) return st;
     Seg* dsegs = aalloc<Seg>(c, S);
     uint64_t* dbstart = aalloc<uint64_t>(c, nb);
     uint32_t* dbseg = aalloc<uint32_t>(c, nb);
     uint32_t* dmed = aalloc<uint32_t>(c, nb);
-    uint32_t* dspill = aalloc<uint32_t>(c, nb);
-    uint32_t* dwide = aalloc<uint32_t>(c, nb);
+    ChunkDesc* ddesc = aalloc<ChunkDesc>(c, nb);
+    ChunkDesc* dspill = aalloc<ChunkDesc>(c, nb);
+    ChunkDesc* dwide = aalloc<ChunkDesc>(c, nb);
     uint32_t* dcounts = aalloc<uint32_t>(c, 5);
     uint32_t* dnone = aalloc<uint32_t>(c, 1);
     st = upload(j, dsegs, hs.data(), S * sizeof(Seg));
@@ -548,6 +549,7 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         la.work = dmed;  // medium index i is work item i (no window slots)
         la.nwork = dcounts + 3;
         la.workcap = (uint32_t)nb;
+        la.desc = ddesc;
         la.spill = dspill;
         la.nspill = dcounts + 2;
         la.spillcap = (uint32_t)nb;
@@ -858,7 +860,8 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
                           asize<uint32_t>(nht) + asize<uint64_t>(nht) + asize<uint16_t>(nht * HEAD_SLOTS) +
                           asize<uint64_t>(bcap) + asize<uint32_t>(bcap) +
                           2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
-                          2 * asize<Big>(bigcap) + 3 * asize<uint32_t>(nslots + medcap) +
+                          2 * asize<Big>(bigcap) + asize<uint32_t>(nslots + medcap) +
+                          3 * asize<ChunkDesc>(nslots + medcap) +
                           asize<uint32_t>(8) + asize<uint32_t>(1u << (2 * RADIX_BITS)) +
                           asize<uint64_t>(RADIX) + 2 * asize<uint32_t>(S);
     const uint32_t scan_tpb = 128;
@@ -890,9 +893,10 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
     uint32_t* med = aalloc<uint32_t>(c, medcap);
     Big* big = aalloc<Big>(c, bigcap);
     Big* done = aalloc<Big>(c, bigcap);
-    uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
+    ChunkDesc* spill = aalloc<ChunkDesc>(c, nslots + medcap);
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
-    uint32_t* wide = aalloc<uint32_t>(c, nslots + medcap);
+    ChunkDesc* wide = aalloc<ChunkDesc>(c, nslots + medcap);
+    ChunkDesc* desc = aalloc<ChunkDesc>(c, nslots + medcap);
     uint32_t* counters = j.err_dev + STAT_WORDS;  // buckets, medium, big, done, spill, work, wide
     uint32_t* joint = aalloc<uint32_t>(c, 1u << (2 * RADIX_BITS));  // pair counts (heads from counts)
     uint64_t* joint_rows = aalloc<uint64_t>(c, RADIX);
@@ -1137,6 +1141,7 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         la.work = work;
         la.nwork = counters + 5;
         la.workcap = (uint32_t)(nslots + medcap);
+        la.desc = desc;
         la.spill = spill;
         la.nspill = counters + 4;
         la.spillcap = (uint32_t)(nslots + medcap);
@@ -1259,7 +1264,8 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
                         asize<Tile>(nt1) + asize<Tile>(nt0) + asize<Seg>(1) + asize<uint32_t>(nt0) +
                         asize<uint64_t>(nt0) + asize<uint16_t>(nt0 * HEAD_SLOTS) + asize<uint64_t>(bcap) +
                         asize<uint32_t>(bcap) + 2 * asize<uint32_t>(nslots) + asize<uint32_t>(medcap) +
-                        2 * asize<Big>(bigcap) + 3 * asize<uint32_t>(nslots + medcap) + asize<uint32_t>(8);
+                        2 * asize<Big>(bigcap) + asize<uint32_t>(nslots + medcap) +
+                        3 * asize<ChunkDesc>(nslots + medcap) + asize<uint32_t>(8);
     dfr_status st = arena_reserve(c, need, j.s);
     if (st) return st;
     uint64_t* lb = aalloc<uint64_t>(c, nt1 * RADIX + 1);
@@ -1281,9 +1287,10 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
     uint32_t* med = aalloc<uint32_t>(c, medcap);
     Big* big = aalloc<Big>(c, bigcap);
     Big* done = aalloc<Big>(c, bigcap);
-    uint32_t* spill = aalloc<uint32_t>(c, nslots + medcap);
+    ChunkDesc* spill = aalloc<ChunkDesc>(c, nslots + medcap);
     uint32_t* work = aalloc<uint32_t>(c, nslots + medcap);
-    uint32_t* wide = aalloc<uint32_t>(c, nslots + medcap);
+    ChunkDesc* wide = aalloc<ChunkDesc>(c, nslots + medcap);
+    ChunkDesc* desc = aalloc<ChunkDesc>(c, nslots + medcap);
     uint32_t* counters = j.err_dev + STAT_WORDS;  // buckets, medium, big, done, spill, work, wide
 
     // --- the estimated deal of the lower digit into the temp buffer and overflow -----
@@ -1469,6 +1476,7 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
         la.work = work;
         la.nwork = counters + 5;
         la.workcap = (uint32_t)(nslots + medcap);
+        la.desc = desc;
         la.spill = spill;
         la.nspill = counters + 4;
         la.spillcap = (uint32_t)(nslots + medcap);

@@ -237,6 +237,15 @@ struct ClassifyArgs {
     uint32_t* err;
 };
 
+// One local-sort chunk: consecutive buckets of one segment (or one medium bucket).
+struct ChunkDesc {
+    uint64_t start;  // its first record
+    uint32_t len;    // records; 0 for a work item that holds no chunk
+    uint32_t nbk;    // buckets in it
+    uint32_t f;      // its first bucket
+    int32_t lo;      // its records agree on the key bits >= lo
+};
+
 struct LocalArgs {
     const void* kin;
     const void* vin;
@@ -256,13 +265,17 @@ struct LocalArgs {
     const uint32_t* work;   // non-empty work items (window slots, then nslots + medium index)
     const uint32_t* nwork;
     uint32_t workcap;
-    uint32_t* spill;    // chunks the packed local sort hands to the general one
-    uint32_t* nspill;   // zero before the launch
+    ChunkDesc* desc;        // the work items' chunks (workcap entries), decoded first
+    ChunkDesc* spill;       // chunks the bucketed local sort hands to the general one
+    uint32_t* nspill;       // zero before the launch
     uint32_t spillcap;
-    uint32_t* wide;     // chunks the 32-bit-word form hands to the 64-bit-word form
-    uint32_t* nwide;    // zero before the launch
+    ChunkDesc* wide;        // chunks the 32-bit-word form hands to the 64-bit-word form
+    uint32_t* nwide;        // zero before the launch
     uint32_t widecap;
-    int32_t spill_only; // set by the launcher
+    // Set by the launcher: the list a bucketed kernel sorts (desc, or wide).
+    const ChunkDesc* chunks;
+    const uint32_t* nchunks;
+    uint32_t chunkcap;
     uint32_t* err;
     uint32_t* stat;     // chunks sorted by forms 0, 1, 2 and by the general kernel
 };

@@ -28,6 +28,8 @@
 //   k_hist_heads_* the same for segments dealt on one digit, from their histograms.
 //   k_classify     buckets -> runs of small buckets packed per window, medium buckets,
 //                  large buckets (recursion) and finished large buckets.
+//   k_chunk_desc   the work list's runs of small buckets (and medium buckets) decoded
+//                  into chunk descriptors ahead of the local sort.
 //   k_local_sort_bucket, k_local_sort
 //                  the diversion: each run of small buckets (or medium bucket) sorted
 //                  in LDS by bucketing words and ranking them inside their bins, or by
@@ -1315,18 +1317,14 @@ __global__ __launch_bounds__(CLASSIFY_THREADS) void k_classify(ClassifyArgs a) {
 }
 
 
-// A local-sort work item: either a window slot (a run of small buckets) or a medium
-// bucket (item >= nslots).  Returns false (uniformly across the block) for an empty slot or a bad one.
-struct Chunk {
-    uint64_t start;
-    uint32_t len;
-    uint32_t nbk;  // buckets in the chunk
-    uint32_t f;    // first bucket
-    int lo;        // buckets agree on bits >= lo
-};
+using Chunk = ChunkDesc;
 
+// A local-sort work item is a window slot (a run of small buckets) or a medium bucket
+// (item >= nslots).  Its chunk comes from the window's first and last bucket (or the
+// medium bucket) and the bucket list; false for an empty window, and for a malformed
+// item (reported when `report` is set).
 __device__ __forceinline__ bool decode_chunk(const LocalArgs& a, uint32_t item, uint64_t nb,
-                                             uint32_t cap, Chunk& ch) {
+                                             uint32_t cap, Chunk& ch, bool report) {
     uint32_t f, l;
     if (item < a.nslots) {
         f = a.cfirst[item];
@@ -1336,7 +1334,7 @@ __device__ __forceinline__ bool decode_chunk(const LocalArgs& a, uint32_t item, 
         f = l = a.med[item - a.nslots];
     }
     if ((uint64_t)l >= nb || f > l) {
-        if (threadIdx.x == 0) atomicOr(a.err, ERR_CHUNK);
+        if (report) atomicOr(a.err, ERR_CHUNK);
         return false;
     }
     const uint32_t s = a.bseg[f];
@@ -1346,7 +1344,7 @@ __device__ __forceinline__ bool decode_chunk(const LocalArgs& a, uint32_t item, 
         ((uint64_t)l + 1 < nb && a.bseg[l + 1] == s) ? a.bstart[l + 1] : sg->start + sg->len;
     const uint64_t len = end - start;
     if (len > cap || len == 0) {
-        if (threadIdx.x == 0) atomicOr(a.err, ERR_CHUNK);
+        if (report) atomicOr(a.err, ERR_CHUNK);
         return false;
     }
     ch.start = start;
@@ -1355,6 +1353,19 @@ __device__ __forceinline__ bool decode_chunk(const LocalArgs& a, uint32_t item, 
     ch.f = f;
     ch.lo = sg->lo_bit;
     return true;
+}
+
+// The work list's chunks, decoded ahead of the local sort (one item per thread): the
+// dependent reads of the bucket lists then overlap across items, and each sorting
+// block reads one descriptor per chunk.
+__global__ __launch_bounds__(256) void k_chunk_desc(LocalArgs a) {
+    const uint64_t nb = umin64(*a.nbuckets, a.bcap);
+    const uint32_t nwork = *a.nwork < a.workcap ? *a.nwork : a.workcap;
+    for (uint32_t it = blockIdx.x * 256u + threadIdx.x; it < nwork; it += gridDim.x * 256u) {
+        Chunk ch{};
+        if (!decode_chunk(a, a.work[it], nb, LOCAL_CAP_ANY, ch, true)) ch.len = 0;
+        a.desc[it] = ch;
+    }
 }
 
 // Offsets from per-wave digit counts (digit-major, then wave order), computed by wave 0
@@ -1680,26 +1691,36 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
     __shared__ K s_red[W];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t nitems = *a.nchunks < a.chunkcap ? *a.nchunks : a.chunkcap;
     const uint64_t nb = umin64(*a.nbuckets, a.bcap);
-    const uint32_t nwork = *a.nwork < a.workcap ? *a.nwork : a.workcap;
     uint32_t* s_rel = (uint32_t*)s_w;
     uint32_t sorted = 0;  // chunks this block finished (counted by thread 0)
 
-    auto spill = [&](uint32_t item) {
+    // Hand chunk `it` on to another list (its descriptor is read again there, so
+    // nothing of it stays live across the sort).
+    auto hand_on = [&](uint32_t it, ChunkDesc* list, uint32_t* count, uint32_t cap) {
         if (tid == 0) {
-            const uint32_t m = atomicAdd(a.nspill, 1u);
-            if (m < a.spillcap) a.spill[m] = item;
+            const uint32_t m = atomicAdd(count, 1u);
+            if (m < cap) list[m] = a.chunks[it];
             else atomicOr(a.err, ERR_LIST_CAP);
         }
         __syncthreads();
     };
+    auto spill = [&](uint32_t it) { hand_on(it, a.spill, a.nspill, a.spillcap); };
 
-    for (uint32_t it = blockIdx.x; it < nwork; it += gridDim.x) {
-        const uint32_t item = a.work[it];
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         Chunk ch;
-        if (!decode_chunk(a, item, nb, LOCAL_CAP_ANY, ch)) continue;
+        if (FORM == 0) {
+            // Form 0 decodes its work items itself (the pre-pass has reported bad ones):
+            // at eight waves per SIMD its registers are full, and the decode leaves fewer
+            // values live across the sort than a descriptor does.
+            if (!decode_chunk(a, a.work[it], nb, LOCAL_CAP_ANY, ch, false)) continue;
+        } else {
+            ch = a.chunks[it];
+            if (ch.len == 0) continue;
+        }
         if (ch.len > CAP) {  // larger than this kernel's tile: the general kernel sorts it
-            spill(item);
+            spill(it);
             continue;
         }
         const uint64_t start = ch.start;
@@ -1736,16 +1757,11 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
         const int bb = nbk > 1 ? 32 - __clz(nbk - 1) : 0;
         const int B = h > 0 ? h + bb : 0;
         if (B + IB > 64) {
-            spill(item);
+            spill(it);
             continue;
         }
         if (FORM < 2 && B + (FORM == 0 ? IB : 0) > 32) {  // the 64-bit form sorts it
-            if (tid == 0) {
-                const uint32_t m = atomicAdd(a.nwide, 1u);
-                if (m < a.widecap) a.wide[m] = item;
-                else atomicOr(a.err, ERR_LIST_CAP);
-            }
-            __syncthreads();
+            hand_on(it, a.wide, a.nwide, a.widecap);
             continue;
         }
         if (B == 0) {  // nothing varies: the chunk is in order already
@@ -1781,7 +1797,7 @@ __global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_W
         const bool ok = bucket_sort_chunk<WT, FORM == 1, WIDE, KB, VB, THREADS, CAP, IB, DB, MAXI>(
             xs, len, nfull, rem, lane, w, tid, nbk, direct, lo, h, Bw, key0, kin, vin, kout, vout, s_rel,
             (WT*)s_w, s_pos, s_bin, s_part, s_max);
-        if (!ok) spill(item);
+        if (!ok) spill(it);
         else ++sorted;
     }
     if (tid == 0 && sorted && a.stat) atomicAdd(&a.stat[STAT_FORM0 + FORM], sorted);
@@ -1817,18 +1833,17 @@ __global__ __launch_bounds__(THREADS) void k_local_sort(LocalArgs a) {
     __shared__ K s_red[W];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint64_t nb = umin64(*a.nbuckets, a.bcap);
-    const uint32_t nmed = *a.nmed < a.medcap ? *a.nmed : a.medcap;
-    const uint32_t nspill = *a.nspill < a.spillcap ? *a.nspill : a.spillcap;
-    const uint32_t nitems = nspill;
-    (void)nmed;
+    const uint32_t nitems = *a.nspill < a.spillcap ? *a.nspill : a.spillcap;
     uint32_t* s_rel = (uint32_t*)s_c;  // bucket starts, before records are staged
 
     uint32_t sorted = 0;  // chunks this block sorted (counted by thread 0)
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint32_t item = a.spill[it];
-        Chunk ch;
-        if (!decode_chunk(a, item, nb, CAP, ch)) continue;
+        const Chunk ch = a.spill[it];
+        if (ch.len == 0) continue;
+        if (ch.len > CAP) {  // larger than any local sort takes
+            if (tid == 0) atomicOr(a.err, ERR_CHUNK);
+            continue;
+        }
         ++sorted;
         const uint64_t start = ch.start;
         const uint32_t len = ch.len;
@@ -2542,33 +2557,34 @@ template <int KB, int VB>
 static void local_kb_vb(const LocalArgs& a, uint32_t blocks, int first_form, hipStream_t s) {
     constexpr int CAP = KB + VB <= 8 ? LOCAL_CAP_SMALL : LOCAL_CAP_LARGE;
     constexpr int BCAP = KB + VB <= 8 ? BUCKET_CAP_SMALL : BUCKET_CAP_LARGE;
-    // A 32-bit form first (first_form 0 or 1), handing chunks that need more to the
-    // 64-bit form; or the 64-bit form for every chunk (first_form 2).  Chunks none of
-    // them can take go to the general kernel.
-    LocalArgs wa = a;
-    wa.spill_only = 0;
+    // The work items' chunks are decoded first.  A 32-bit form (first_form 0 or 1) then
+    // sorts them, handing chunks that need more to the 64-bit form; or the 64-bit form
+    // sorts every chunk (first_form 2).  Chunks none of them can take go to the general
+    // kernel.  Every list but the work list holds descriptors.
+    const uint32_t dblocks = std::min<uint32_t>((a.workcap + 255) / 256, 1024);
+    if (dblocks) hipLaunchKernelGGL(k_chunk_desc, dim3(dblocks), dim3(256), 0, s, a);
+    LocalArgs la = a;
+    la.chunks = a.desc;
+    la.nchunks = a.nwork;
+    la.chunkcap = a.workcap;
     uint32_t wblocks = blocks;
     if (first_form < 2) {
-        LocalArgs pa = a;
-        pa.spill_only = 0;
         if (first_form == 0)
             hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 0>), dim3(blocks),
-                               dim3(LOCAL_THREADS), 0, s, pa);
+                               dim3(LOCAL_THREADS), 0, s, la);
         else
             hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 1>), dim3(blocks),
-                               dim3(LOCAL_THREADS), 0, s, pa);
-        wa.work = a.wide;
-        wa.nwork = a.nwide;
-        wa.workcap = a.widecap;
+                               dim3(LOCAL_THREADS), 0, s, la);
+        la.chunks = a.wide;
+        la.nchunks = a.nwide;
+        la.chunkcap = a.widecap;
         wblocks = blocks < 4096 ? blocks : 4096;
     }
     hipLaunchKernelGGL((k_local_sort_bucket<KB, VB, LOCAL_THREADS, BCAP, 2>), dim3(wblocks),
-                       dim3(LOCAL_THREADS), 0, s, wa);
-    LocalArgs ga = a;
-    ga.spill_only = 1;
+                       dim3(LOCAL_THREADS), 0, s, la);
     const uint32_t gblocks = blocks < 2048 ? blocks : 2048;
     hipLaunchKernelGGL((k_local_sort<KB, VB, GENERAL_THREADS, CAP>), dim3(gblocks),
-                       dim3(GENERAL_THREADS), 0, s, ga);
+                       dim3(GENERAL_THREADS), 0, s, a);
 }
 
 int local_sort_first_form(int kb, int vb, int max_lo_bit) {
