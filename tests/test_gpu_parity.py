@@ -530,6 +530,43 @@ def test_local_sort_forms(torch, ctx, o, bits, vbits, n, segmented, form):
     assert sum(forms) + st["chunks_general"] == st["chunks"], st
 
 
+def test_local_sort_hand_on_to_wide_form(torch, ctx, o):
+    """Two top digits of 2^20 uniform 32-bit keys leave buckets of about 16 records, so a
+    window of 2048 records holds about 128 of them: seven bits of bucket index beside 16
+    varying bits and a 13-bit position do not fit 32 bits.  The first kernel (form 0, as
+    lo_bit is 16) hands each such chunk's descriptor on to the 64-bit form, which sorts
+    it (the diversion of Sec. 3)."""
+    n = (1 << 20) + 11
+    k = workloads.make_keys("uniform", n, 32, 71)
+    v = workloads.index_payload(n, 32)
+    say("hand on to the 64-bit form", n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, force_top_digits=2)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    assert st["levels"] == 1 and st["chunks_form2"] > 0 and st["chunks_form1"] == 0, st
+    assert st["chunks_form0"] + st["chunks_form2"] + st["chunks_general"] == st["chunks"], st
+
+
+def test_local_sort_hand_on_to_general(torch, ctx, o):
+    """Buckets of about 4096 records whose 16 low bits vary only in bit 15 and bits 0-3:
+    binned by the top 12 of those bits, each bucket falls into two bins of about 2048
+    records, far above the 64 the bucketed form ranks, so its descriptor is handed on to
+    the stable LSD kernel, which sorts it."""
+    n = (1 << 20) + 5
+    rng = np.random.default_rng(73)
+    top = rng.integers(0, 256, n).astype(np.uint32) << np.uint32(24)
+    mid = np.uint32(0x5a) << np.uint32(16)
+    low = (rng.integers(0, 2, n).astype(np.uint32) << np.uint32(15)) | rng.integers(0, 16, n).astype(np.uint32)
+    k = top | mid | low
+    v = workloads.index_payload(n, 32)
+    say("hand on to the general kernel", n)
+    sk, sv, st = gpu_sort(torch, ctx, k, v, force_top_digits=2)
+    rk, rv = o.stable_sort(k, v)
+    assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
+    assert st["levels"] == 1 and st["chunks_general"] > 0, st
+    assert sum(st[f"chunks_form{i}"] for i in range(3)) + st["chunks_general"] == st["chunks"], st
+
+
 @pytest.mark.parametrize("spacing", [1, 2, 3, 4, 16])
 @pytest.mark.parametrize("kb", [4, 8])
 def test_local_sort_bucket_spacing(torch, ctx, o, spacing, kb):
