@@ -70,8 +70,8 @@ constexpr int LOCAL_CAP_SMALL = 8192;  // general local sort: records per chunk 
 constexpr int LOCAL_CAP_LARGE = 4096;  // the same for 12- and 16-byte records
 constexpr int BUCKET_CAP_SMALL = 5120; // bucketed local sort: records per chunk (<= 8-byte records)
 constexpr int BUCKET_CAP_LARGE = 4096;
-constexpr int LOCAL_MIN_WAVES = 6;     // waves per SIMD the 64-bit-word local sort must fit
-constexpr int LOCAL_MIN_WAVES32 = 8;   // the same for its 32-bit-word forms
+constexpr int LOCAL_MIN_WAVES = 6;     // waves per SIMD local-sort forms 1 and 2 must fit (80 VGPRs)
+constexpr int LOCAL_MIN_WAVES_FORM0 = 8;  // the same for form 0 (64 VGPRs)
 constexpr int COPY_THREADS = 256;
 constexpr int HEAD_THREADS = 512;
 constexpr int GENERAL_THREADS = 256;
@@ -1665,7 +1665,7 @@ __device__ __forceinline__ bool bucket_sort_chunk(
 // 2: 64-bit words with the position inside.  Forms 0 and 1 hand chunks that do not fit
 // to the 64-bit form's list.
 template <int KB, int VB, int THREADS, int CAP, int FORM>
-__global__ __launch_bounds__(THREADS, FORM < 2 ? LOCAL_MIN_WAVES32 : LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
+__global__ __launch_bounds__(THREADS, FORM == 0 ? LOCAL_MIN_WAVES_FORM0 : LOCAL_MIN_WAVES) void k_local_sort_bucket(LocalArgs a) {
     using K = typename uint_of<KB>::type;
     using V = typename uint_of<VB>::type;
     constexpr int W = THREADS / 64;
