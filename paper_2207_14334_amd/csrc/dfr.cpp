@@ -562,7 +562,7 @@ dfr_status divert_level(Job& j, const std::vector<LSeg>& segs, int in) {
         int max_lo = 0;
         for (const Seg& g : hs) max_lo = std::max(max_lo, (int)g.lo_bit);
         HIP_TRY(c, launch_local_sort(j.kb, j.vb, la, blocks,
-                                     local_sort_first_form(j.kb, j.vb, max_lo), j.s));
+                                     local_sort_first_form(j.kb, j.vb, max_lo, 0), j.s));
         c->stats.chunks += nb;
     }
     c->stats.used_diversion = 1;
@@ -1151,11 +1151,24 @@ dfr_status deal_level(Job& j, const std::vector<LSeg>& segs, int in, std::vector
         la.err = j.err_dev;
         la.stat = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 8192);
-        int max_lo = 0;
-        for (uint32_t i : active)
-            if (!full[i]) max_lo = std::max(max_lo, (int)hs[i].lo_bit);
+        // Bits a chunk's words need besides the position: the segment's lo_bit varying
+        // bits, and the index of a bucket within a window's run of buckets (expected
+        // from the buckets its dealt digits make, their values that occur, and the
+        // window width).
+        int max_lo = 0, max_index = 0;
+        for (uint32_t i : active) {
+            if (full[i]) continue;
+            uint64_t nbk = 1;
+            for (int p = 0; p < dsel[i] && p < (int)V[i].size(); ++p)
+                nbk = std::min<uint64_t>(nbk * nonzero[i * ndig + V[i][p]], segs[i].len);
+            const uint64_t per = std::max<uint64_t>(1, segs[i].len / std::max<uint64_t>(nbk, 1));
+            const uint64_t run = std::max<uint64_t>(1, std::min<uint64_t>(wsmall / per, nbk));  // buckets per window
+            const int ib = run > 1 ? 64 - __builtin_clzll(run - 1) : 0;
+            max_lo = std::max(max_lo, (int)hs[i].lo_bit);
+            max_index = std::max(max_index, (int)hs[i].lo_bit + ib);
+        }
         HIP_TRY(c, launch_local_sort(kb, j.vb, la, blocks,
-                                     local_sort_first_form(kb, j.vb, max_lo), j.s));
+                                     local_sort_first_form(kb, j.vb, max_lo, max_index - max_lo), j.s));
     }
     c->stats.used_diversion = 1;
 
@@ -1486,7 +1499,7 @@ dfr_status est_level(Job& j, const LSeg& g, std::vector<LSeg>& next, bool* used)
         la.err = j.err_dev;
         la.stat = j.err_dev;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(nslots + medcap, 8192);
-        HIP_TRY(c, launch_local_sort(kb, vb, la, blocks, local_sort_first_form(kb, vb, su), j.s));
+        HIP_TRY(c, launch_local_sort(kb, vb, la, blocks, local_sort_first_form(kb, vb, su, 0), j.s));
     }
     c->stats.used_diversion = 1;
     // --- large buckets: the next level's segments --------------------------------------

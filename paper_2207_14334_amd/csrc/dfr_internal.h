@@ -349,7 +349,7 @@ hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s
 // Which form of the local sort runs first for chunks whose buckets agree on every bit
 // >= max_lo_bit: 0 and 1 use 32-bit words (with and without the position inside), 2
 // 64-bit words.
-int local_sort_first_form(int kb, int vb, int max_lo_bit);
+int local_sort_first_form(int kb, int vb, int max_lo_bit, int index_bits);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
                              int first_form, hipStream_t s);
 hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t nchunks,

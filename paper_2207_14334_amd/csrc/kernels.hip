@@ -2587,15 +2587,15 @@ static void local_kb_vb(const LocalArgs& a, uint32_t blocks, int first_form, hip
                        dim3(GENERAL_THREADS), 0, s, a);
 }
 
-int local_sort_first_form(int kb, int vb, int max_lo_bit) {
-    // A chunk's sort bits are at most its lo_bit varying bits plus a few bits of bucket
-    // index.  With room for the position as well, the 32-bit words carry it (form 0);
-    // else, below 32 bits of lo_bit, the position goes beside them (form 1).  At 32 the
-    // bucket index of a run of buckets no longer fits, and every such chunk would be
-    // handed on to the 64-bit form after a wasted read.
-    const int ib = local_bucket_capacity(kb, vb) <= 4096 ? 12 : 13;
-    if (max_lo_bit + ib <= 32) return 0;
-    return max_lo_bit < 32 ? 1 : 2;
+int local_sort_first_form(int kb, int vb, int max_lo_bit, int index_bits) {
+    // A chunk's sort bits are at most its lo_bit varying bits plus the bits of its
+    // buckets' index (index_bits as the level expects them).  With room for the position
+    // as well, the 32-bit words carry it (form 0); else, while the sort bits fit 32, the
+    // position goes beside them (form 1).  Otherwise the first form would only read
+    // each chunk to hand it on to the 64-bit form.
+    const int pb = local_bucket_capacity(kb, vb) <= 4096 ? 12 : 13;
+    if (max_lo_bit + index_bits + pb <= 32) return 0;
+    return max_lo_bit < 32 && max_lo_bit + index_bits <= 32 ? 1 : 2;
 }
 
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,

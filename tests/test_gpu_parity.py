@@ -477,9 +477,12 @@ FORM_CASES = [
     # (key bits, payload bits, n, segmented, form expected): the headline shape (two
     # digits of 32-bit keys dealt, buckets of ~1024 records or more: 32-bit words with
     # the position inside); one digit of 32-bit keys dealt (position beside the words);
-    # 64-bit keys with buckets of ~256 records or more (64-bit words).
+    # two digits dealt into buckets of ~64 records, about 32 to a window, whose index
+    # leaves no room for the position (beside the words from the start); 64-bit keys
+    # with buckets of ~256 records or more (64-bit words).
     (32, 32, (1 << 26) + 7, False, 0),
     (32, 32, (1 << 20) + 3, False, 1),
+    (32, 32, (1 << 22) + 3, False, 1),
     (32, 32, None, True, 1),
     (64, 64, (1 << 24) + 5, False, 2),
     (32, 0, (1 << 26) + 1, False, 0),
@@ -531,19 +534,24 @@ def test_local_sort_forms(torch, ctx, o, bits, vbits, n, segmented, form):
 
 
 def test_local_sort_hand_on_to_wide_form(torch, ctx, o):
-    """Two top digits of 2^20 uniform 32-bit keys leave buckets of about 16 records, so a
-    window of 2048 records holds about 128 of them: seven bits of bucket index beside 16
-    varying bits and a 13-bit position do not fit 32 bits.  The first kernel (form 0, as
-    lo_bit is 16) hands each such chunk's descriptor on to the 64-bit form, which sorts
-    it (the diversion of Sec. 3)."""
-    n = (1 << 20) + 11
-    k = workloads.make_keys("uniform", n, 32, 71)
+    """Two top digits of 2^24 32-bit keys average 256 records a bucket, about 8 to a
+    window of 2048, so the level starts with form 0 (16 varying bits, 3 of bucket index
+    and a 13-bit position fill 32 bits).  Here 7/8 of the records fall in the lower half
+    of the top-16-bit values (buckets of ~448) and 1/8 in the upper half (buckets of
+    ~64): a window there holds about 32 buckets, too many for form 0, which hands those
+    chunks' descriptors on to the 64-bit form (the diversion of Sec. 3)."""
+    n = (1 << 24) - 3
+    rng = np.random.default_rng(71)
+    hot = rng.random(n) < 7 / 8
+    top = np.where(hot, rng.integers(0, 1 << 15, n), rng.integers(1 << 15, 1 << 16, n)).astype(np.uint32)
+    k = (top << np.uint32(16)) | (workloads.make_keys("uniform", n, 32, 71) >> np.uint32(16))
     v = workloads.index_payload(n, 32)
     say("hand on to the 64-bit form", n)
     sk, sv, st = gpu_sort(torch, ctx, k, v, force_top_digits=2)
     rk, rv = o.stable_sort(k, v)
     assert np.array_equal(sk, rk) and np.array_equal(sv, rv), st
-    assert st["levels"] == 1 and st["chunks_form2"] > 0 and st["chunks_form1"] == 0, st
+    assert st["levels"] == 1 and st["chunks_form1"] == 0, st
+    assert st["chunks_form0"] > 0 and st["chunks_form2"] > 0, st
     assert st["chunks_form0"] + st["chunks_form2"] + st["chunks_general"] == st["chunks"], st
 
 
