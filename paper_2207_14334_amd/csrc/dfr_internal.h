@@ -269,7 +269,7 @@ struct LocalArgs {
     ChunkDesc* spill;       // chunks the bucketed local sort hands to the general one
     uint32_t* nspill;       // zero before the launch
     uint32_t spillcap;
-    ChunkDesc* wide;        // chunks the 32-bit-word form hands to the 64-bit-word form
+    ChunkDesc* wide;        // chunks a 32-bit-word form hands to the 64-bit-word form
     uint32_t* nwide;        // zero before the launch
     uint32_t widecap;
     // Set by the launcher: the list a bucketed kernel sorts (desc, or wide).
@@ -347,8 +347,8 @@ hipError_t launch_joint_heads(int kb, const JointArgs& a, hipStream_t s);
 hipError_t launch_hist_heads(const HistHeadArgs& a, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, uint32_t blocks, hipStream_t s);
 // Which form of the local sort runs first for chunks whose buckets agree on every bit
-// >= max_lo_bit: 0 and 1 use 32-bit words (with and without the position inside), 2
-// 64-bit words.
+// >= max_lo_bit and whose bucket index is expected to take index_bits: 0 and 1 use
+// 32-bit words (with and without the position inside), 2 64-bit words.
 int local_sort_first_form(int kb, int vb, int max_lo_bit, int index_bits);
 hipError_t launch_local_sort(int kb, int vb, const LocalArgs& a, uint32_t blocks,
                              int first_form, hipStream_t s);

@@ -218,7 +218,9 @@ __global__ __launch_bounds__(THREADS, KB == 4 && NDIG <= 4 ? COUNT_MIN_WAVES : 1
     constexpr int W = THREADS / 64;
     constexpr int SLICE = NDIG * RADIX;  // bins for up to NDIG digits
     constexpr int PER_VEC = 16 / KB;  // keys per 16-byte load
-    constexpr int VECS = KB == 8 ? 4 : COUNT_VECS;  // 16-byte loads in flight per thread
+    // 16-byte loads in flight per thread; four for 64-bit keys, whose count otherwise
+    // takes 128 VGPRs (four waves per SIMD; with four loads, six).
+    constexpr int VECS = KB == 8 ? 4 : COUNT_VECS;
     // The waves' bins; between tiles (all zero) the first words also carry the waves'
     // OR and AND to the segment's flush.  With four digits the two arrays fill exactly
     // an eighth of the LDS, so eight blocks share a CU.
