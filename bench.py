@@ -11,7 +11,8 @@ with the rest of the metric beside it:
 * ``roofline`` -- the deal kernel (the dominant pass): algorithmic bytes per launch over
   its mean launch time from HIP events on the sort's stream during the timed steps;
   ``copy_ceiling`` -- the library's own streaming copy kernel on 4 GiB, the rate the
-  read-once/write-once passes can reach.
+  read-once/write-once passes can reach; ``read_ceiling`` -- its streaming read kernel
+  on 1 GiB (the 2^28 uint32 keys a count reads), the rate a count can reach.
 * ``cpu_baseline`` -- the CPU oracle on the host: all cores on the full 2^28 input of
   seed 0, and single-threaded on three 2^24 samples.
 * ``c1`` -- 2^20 uint32 keys, key-only: wall latency of one call.
@@ -153,6 +154,38 @@ def copy_ceiling(torch, ctx, gib=4, reps=5):
     return {"kernel": "k_stream_copy", "bytes_copied": gib << 30, "ms": round(t, 4),
             "GB/s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
             "copy_correct": ok}
+
+
+def read_ceiling(torch, ctx, gib=1, reps=5):
+    """The library's streaming read kernel on `gib` GiB of random words (bytes read over
+    its time from HIP events on its stream, median of `reps`), with its XOR checksum
+    checked against a fold of the same words by torch's own XOR."""
+    import numpy as np
+    n = (gib << 30) // 4
+    src = torch.randint(-(1 << 31), (1 << 31) - 1, (n,), dtype=torch.int32, device="cuda")
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.stream_read(src, out)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.stream_read(src, out)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    x = src
+    while x.numel() > 1:  # n is a power of two
+        h = x.numel() // 2
+        x = torch.bitwise_xor(x[:h], x[h:])
+    ok = bool(torch.equal(x, out))
+    del src, out, x
+    torch.cuda.empty_cache()
+    t = float(np.median(ms))
+    gbs = (gib << 30) / (t * 1e-3) / 1e9
+    return {"kernel": "k_stream_read", "bytes_read": gib << 30, "ms": round(t, 4),
+            "GB/s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "checksum_correct": ok}
 
 
 def check_segments(keys_in, keys_out, vals_out, off, segs):
@@ -493,7 +526,7 @@ def main():
     ap.add_argument("--seeds", type=int, default=3, help="inputs the plain steps cycle through")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true",
-                    help="skip the copy-kernel timing (profiling runs)")
+                    help="skip the copy and read reference timings (profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -670,6 +703,7 @@ def run_plain(args, torch, dfr):
     del base_k, base_v, temp
     torch.cuda.empty_cache()
     ceiling = None if args.no_copy_ceiling else copy_ceiling(torch, ctx)
+    rceiling = None if args.no_copy_ceiling else read_ceiling(torch, ctx)
     stage_ms = {k: round(v, 4) for k, v in stage.items() if k.startswith("ms_")}
     out = {
         "metric": METRIC, "value": round(gkeys, 4), "unit": "Gkeys/s", "n_gpus": 1,
@@ -708,6 +742,7 @@ def run_plain(args, torch, dfr):
                     "min": round(float(step_ms.min()), 4),
                     "p90": round(float(np.percentile(step_ms, 90)), 4)},
         "copy_ceiling": ceiling,
+        "read_ceiling": rceiling,
         "result_check": parity,
     }
     ctx.close()

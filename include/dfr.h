@@ -189,6 +189,15 @@ dfr_status dfr_deal(dfr_ctx* ctx, const void* keys_in, const void* vals_in, void
  * against beside the HBM peak.  DFR_E_INVALID_ARG for bad pointers or sizes. */
 dfr_status dfr_stream_copy(dfr_ctx* ctx, const void* src, void* dst, size_t bytes, void* stream);
 
+/* Bandwidth reference of the counts: read `bytes` (a multiple of 16, possibly 0; src
+ * 16-byte aligned) on the device with a plain streaming kernel of this library,
+ * enqueued on `stream`, and write the XOR of every 32-bit word read to *xor_out (one
+ * device word, 4-byte aligned, outside the source; 0 for no bytes).  A count reads each
+ * key once and writes little, so this rate is its ceiling beside the HBM peak.
+ * DFR_E_INVALID_ARG for bad pointers or sizes. */
+dfr_status dfr_stream_read(dfr_ctx* ctx, const void* src, size_t bytes, uint32_t* xor_out,
+                           void* stream);
+
 /* ---------------------------------------------------------------------------------
  * Serving: submit sort requests of any size and width, poll for completion.
  *

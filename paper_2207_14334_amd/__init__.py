@@ -37,6 +37,7 @@ EXPORTED = [
     "dfr_plan_top_digits", "dfr_local_sort_capacity", "dfr_deal_tile_records",
     "dfr_size_class", "dfr_autotune", "dfr_get_tune", "dfr_set_tune", "dfr_get_serve_stats",
     "dfr_sort_keys", "dfr_sort_segmented_keys", "dfr_sort_noalloc", "dfr_stream_copy",
+    "dfr_stream_read",
 ]
 
 # The allocation-free entry point's limits (include/dfr.h).
@@ -175,6 +176,8 @@ def lib():
     L.dfr_sort_noalloc.restype = S
     L.dfr_stream_copy.argtypes = [P, P, P, Z, P]
     L.dfr_stream_copy.restype = S
+    L.dfr_stream_read.argtypes = [P, P, Z, P, P]
+    L.dfr_stream_read.restype = S
     _lib = L
     return L
 
@@ -393,6 +396,18 @@ class Context:
             raise ValueError("src and dst must have the same byte size")
         self._raise(lib().dfr_stream_copy(self._h, src.data_ptr(), dst.data_ptr(), nb,
                                           self._stream(stream)), "stream_copy")
+
+    def stream_read(self, src, out, stream=None):
+        """Read GPU tensor ``src`` (byte size a multiple of 16) with the library's
+        streaming read kernel, the bandwidth reference of the counts, writing the XOR of
+        its 32-bit words into ``out`` (a one-element int32/uint32 GPU tensor)."""
+        _check_tensor(src, "src")
+        _check_tensor(out, "out")
+        if out.numel() != 1 or out.element_size() != 4:
+            raise ValueError("out must hold one 32-bit word")
+        nb = src.numel() * src.element_size()
+        self._raise(lib().dfr_stream_read(self._h, src.data_ptr(), nb, out.data_ptr(),
+                                          self._stream(stream)), "stream_read")
 
     # -- tuning --------------------------------------------------------------------
     def autotune(self, keys, vals=None, offsets=None, reps: int = 2, stream=None) -> dict:

@@ -2714,6 +2714,25 @@ dfr_status dfr_stream_copy(dfr_ctx* c, const void* src, void* dst, size_t bytes,
     return DFR_OK;
 }
 
+dfr_status dfr_stream_read(dfr_ctx* c, const void* src, size_t bytes, uint32_t* xor_out, void* stream) {
+    if (!c) return DFR_E_INVALID_ARG;
+    if (c->failed) return DFR_E_HIP;
+    if (!xor_out || (uintptr_t)xor_out % 4 || bytes % 16 || (bytes && (!src || (uintptr_t)src % 16)) ||
+        overlap(src, bytes, xor_out, 4))
+        return DFR_E_INVALID_ARG;
+    dfr_status st = set_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    CallOrder order(c, s);
+    if (order.st) return order.st;
+    const uint64_t parts = stream_read_parts(bytes);
+    st = arena_reserve(c, asize<uint32_t>(parts), s);
+    if (st) return st;
+    uint32_t* part = aalloc<uint32_t>(c, parts);
+    HIP_TRY(c, launch_stream_read(src, bytes, part, xor_out, s));
+    return DFR_OK;
+}
+
 dfr_status dfr_submit(dfr_ctx* c, const dfr_request* req, uint64_t* ticket) {
     if (!c || !req || !ticket) return DFR_E_INVALID_ARG;
     const int kb = req->key_bytes, vb = req->val_bytes;

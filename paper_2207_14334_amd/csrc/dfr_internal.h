@@ -356,6 +356,9 @@ hipError_t launch_copy_chunks(int kb, int vb, const CopyChunk* chunks, uint32_t 
                               hipStream_t s);
 // Streaming copy of bytes / 16 vectors (both pointers 16-byte aligned).
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
+// Words of partial results the streaming read needs for `bytes` (one per 32 KB block).
+uint64_t stream_read_parts(uint64_t bytes);
+hipError_t launch_stream_read(const void* src, uint64_t bytes, uint32_t* part, uint32_t* out, hipStream_t s);
 hipError_t launch_copy_tiles(int kb, int vb, const void* kin, const void* vin, void* kout,
                              void* vout, const Tile* tiles, uint32_t ntiles, hipStream_t s);
 

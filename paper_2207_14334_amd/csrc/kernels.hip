@@ -17,9 +17,9 @@
 //                  or from decoupled look-back over the tiles before it.
 //   k_deal_est     Fast Radix's deal into estimated buckets with overflow slots, without
 //                  a count (Sec. 3); it counts the next digit on the way.
-//   k_fill_*, k_stream_copy
-//                  fills of scratch (several ranges per launch), and the streaming copy
-//                  that is the passes' bandwidth reference.
+//   k_fill_*, k_stream_copy, k_stream_read, k_xor_fold
+//                  fills of scratch (several ranges per launch); the streaming copy and
+//                  read that are the passes' and the counts' bandwidth references.
 //   k_heads*       bucket boundaries after the deals, from the keys: positions where
 //                  the leading bits change, listed in order.
 //   k_joint_*      the same without the keys, for one segment dealt on two digits:
@@ -2116,6 +2116,78 @@ __global__ __launch_bounds__(STREAM_THREADS) void k_stream_copy(const vec4u* __r
         const uint64_t i = i0 + (uint64_t)u * STREAM_THREADS;
         if (i < nvec) __builtin_nontemporal_store(r[u], dst + i);
     }
+}
+
+// Streaming read of 16-byte vectors, the bandwidth reference of the counts (which read
+// every key once and write little): each block reads one contiguous run of
+// STREAM_THREADS * STREAM_RU vectors, all its loads in flight together, and writes the
+// XOR of its words to part[block]; one block then folds the parts into *out.  The result
+// is the XOR of every 32-bit word read: a checksum that keeps the loads live and can be
+// checked, at no more than one word written per 32 KB read.
+constexpr int STREAM_RU = 8;
+constexpr uint64_t STREAM_RUN = (uint64_t)STREAM_THREADS * STREAM_RU;  // vectors per block
+__global__ __launch_bounds__(STREAM_THREADS) void k_stream_read(const vec4u* __restrict__ src, uint64_t nvec,
+                                                                uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_x[STREAM_THREADS / 64];
+    const uint64_t i0 = (uint64_t)blockIdx.x * STREAM_RUN + threadIdx.x;
+    vec4u r[STREAM_RU];
+#pragma unroll
+    for (int u = 0; u < STREAM_RU; ++u) {
+        const uint64_t i = i0 + (uint64_t)u * STREAM_THREADS;
+        r[u] = i < nvec ? src[i] : (vec4u)(0u);
+    }
+    uint32_t x = 0;
+#pragma unroll
+    for (int u = 0; u < STREAM_RU; ++u) x ^= r[u].x ^ r[u].y ^ r[u].z ^ r[u].w;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x ^= __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) s_x[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int w = 0; w < STREAM_THREADS / 64; ++w) b ^= s_x[w];
+        part[blockIdx.x] = b;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_xor_fold(const uint32_t* __restrict__ part, uint64_t n,
+                                                   uint32_t* out) {
+    __shared__ uint32_t s_x[16];
+    uint32_t x = 0;
+    // Sixteen independent loads in flight per thread and step.
+    for (uint64_t i0 = threadIdx.x; i0 < n; i0 += 16 * 1024) {
+        uint32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * 1024;
+            v[u] = i < n ? part[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x ^= v[u];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x ^= __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) s_x[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) b ^= s_x[w];
+        *out = b;
+    }
+}
+
+uint64_t stream_read_parts(uint64_t bytes) { return (bytes / 16 + STREAM_RUN - 1) / STREAM_RUN; }
+
+hipError_t launch_stream_read(const void* src, uint64_t bytes, uint32_t* part, uint32_t* out, hipStream_t s) {
+    const uint64_t nvec = bytes / 16, parts = stream_read_parts(bytes);
+    if (parts > 0x7fffffffu) return hipErrorInvalidValue;
+    if (parts)
+        hipLaunchKernelGGL(k_stream_read, dim3((uint32_t)parts), dim3(STREAM_THREADS), 0, s,
+                           (const vec4u*)src, nvec, part);
+    hipLaunchKernelGGL(k_xor_fold, dim3(1), dim3(1024), 0, s, part, parts, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s) {

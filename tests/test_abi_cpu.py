@@ -90,6 +90,8 @@ def test_null_context_and_bad_arguments(L):
     assert L.dfr_autotune(None, 4, 4, None, None, None, 0, 1, None, None) == dfr.E_INVALID_ARG
     assert L.dfr_get_tune(None, 4, 4, 0, None) == dfr.E_INVALID_ARG
     assert L.dfr_set_tune(None, 4, 4, 0, None) == dfr.E_INVALID_ARG
+    assert L.dfr_stream_copy(None, P(4096), P(8192), 16, None) == dfr.E_INVALID_ARG
+    assert L.dfr_stream_read(None, P(4096), 16, P(8192), None) == dfr.E_INVALID_ARG
 
 
 def test_create_without_gpu_fails_cleanly(L):
